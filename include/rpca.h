@@ -1,0 +1,193 @@
+/*
+ * librpca -- Split-SPCP (Burer-Monteiro robust PCA with the sparse part
+ * marginalised) on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Driggs, Becker & Aravkin, "Adapting Regularized Low-Rank Models
+ * for Parallel Architectures"):
+ *
+ *   phi(L)  = min_S 1/2 ||P_Omega(L + S - X)||_F^2 + lam_S ||S||_1
+ *           = sum_{(i,j) in Omega} huber_{lam_S}(L_ij - X_ij)            (Sec. 1, eq. PhiDef)
+ *   f(U,V)  = phi(U V^T) + lam_L/2 (||U||_F^2 + ||V||_F^2)               (eq. smoothNC, eq. Thm5)
+ *   G       = Omega .* clip(U V^T - X, -lam_S, lam_S)                    (Sec. 3.2, eq. diff)
+ *   df/dU   = G V + lam_L U,   df/dV = G^T U + lam_L V
+ *
+ * minimised by L-BFGS (memory 10, Sec. 5.1) and checked by the convergence
+ * certificate of Sec. 3.4 (gap bound eq. Fbound).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - X is FP32, column-major, m x n, leading dimension m (one video frame per
+ *    column, as in Sec. 5.4).  Unobserved entries may hold any finite value.
+ *  - U is m x k and V is n x k, FP32, row-major (row i of U is U[i*k .. i*k+k)).
+ *    Gradients use the same layout.
+ *  - Pointers documented as "device" must be HIP device allocations on the
+ *    context's device.  "host" pointers are ordinary host memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on `stream` unless documented otherwise.
+ *  - The caller owns every buffer it passes in; the context owns its workspace.
+ *    A context must not be used from two streams or two threads at once.
+ *  - Return codes: 0 = success; > 0 = warning, outputs valid; < 0 = error,
+ *    outputs unspecified.  All argument checks happen before any HIP call.
+ */
+#ifndef RPCA_H
+#define RPCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rpca_status {
+  RPCA_OK = 0,
+  RPCA_ENOTCONV = 1,      /* iteration budget spent; outputs are the last iterate */
+  RPCA_ELINESEARCH = 2,   /* no strong-Wolfe step found after a restart; outputs valid */
+  RPCA_ENOTCERT = 3,      /* converged but the certificate does not reach the target gap */
+  RPCA_EINVAL = -1,       /* bad argument (checked before any HIP call) */
+  RPCA_ENOMEM = -2,       /* device or pinned allocation failed */
+  RPCA_EHIP = -3,         /* a HIP runtime call failed */
+  RPCA_ENONFINITE = -4    /* objective or gradient became NaN/Inf */
+};
+
+enum rpca_precision {
+  RPCA_PREC_FP32 = 0,         /* FP32 products on MFMA, FP32 residual, FP64 reductions */
+  RPCA_PREC_BF16_POLISH = 1,  /* BF16 MFMA products until a loose tolerance, then FP32 */
+  RPCA_PREC_BF16 = 2          /* BF16 MFMA products throughout */
+};
+
+enum rpca_init {
+  RPCA_INIT_GIVEN = 0,        /* start from the U, V the caller passes */
+  RPCA_INIT_RSVD = 1          /* randomized-SVD cold start (Sec. 4.2), overwrites U, V */
+};
+
+typedef struct rpca_ctx rpca_ctx;
+
+/* Solver options.  rpca_default_opts() fills the defaults listed here. */
+typedef struct rpca_opts {
+  int32_t precision;        /* rpca_precision, default RPCA_PREC_FP32 */
+  int32_t mem;              /* L-BFGS pairs kept, 1..15, default 10 (Sec. 5.1) */
+  int32_t max_iter;         /* L-BFGS iterations, default 5000 */
+  int32_t init;             /* rpca_init, default RPCA_INIT_GIVEN */
+  double gtol;              /* stop: ||g||_inf <= gtol * max(1,|f|), default 1e-6 */
+  double ftol;              /* stop: relative f decrease over 5 iterations < ftol, default 1e-9 */
+  double bf16_gtol;         /* BF16 phase tolerance before the FP32 polish, default 1e-3 */
+  double c1, c2;            /* strong-Wolfe constants, default 1e-4, 0.9 */
+  int32_t certify;          /* 1: run the certificate at the end and tighten gtol until
+                               rel_gap <= cert_tol (at most 4 rounds); default 1 */
+  double cert_tol;          /* certified threshold on gap/F, default 1e-3 */
+  int32_t rsvd_oversample;  /* p, default 10 */
+  int32_t rsvd_power;       /* q, default 2 */
+  uint64_t seed;            /* seed of the counter-based generator (rSVD sketch, power start) */
+  int32_t slots_per_sync;   /* line-search trials per host poll, default 16 */
+} rpca_opts;
+
+typedef struct rpca_info {
+  int32_t status;           /* rpca_status of the solve */
+  int32_t iters;            /* accepted L-BFGS iterations (all phases) */
+  int32_t evals;            /* objective+gradient evaluations */
+  int32_t iters_bf16;       /* iterations done in the BF16 phase */
+  double f;                 /* final objective f(U,V) */
+  double gnorm_inf;         /* final ||grad f||_inf */
+  double rel_gap;           /* certificate gap/F (NaN when not certified) */
+  int32_t certified;        /* rel_gap <= cert_tol */
+  int32_t cert_rounds;      /* certificate evaluations performed */
+  double seconds;           /* wall time of the call */
+} rpca_info;
+
+typedef struct rpca_cert {
+  double T1, T2, T3, T4;    /* the four terms of ||E||_F^2 (Sec. 3.4), normalised by lam_L */
+  double E;                 /* ||E||_F including the rank-truncation correction */
+  double F;                 /* F(L) = lam_L ||L||_* + phi(L) (eq. genConvex) */
+  double phi;               /* phi(L) */
+  double phi0;              /* phi(0) = sum_Omega huber(X) */
+  double F_bound;           /* min(F, phi0, best F known to the context) */
+  double normL;             /* ||L||_F */
+  double gap;               /* E * (lam_L ||L||_F + F_bound)  (eq. Fbound) */
+  double rel_gap;           /* gap / F */
+  double normM2;            /* ||P_U^perp D P_V^perp||_F^2 */
+  double theta[32];         /* leading singular values of P_U^perp D P_V^perp (Ritz estimates) */
+  double sigma[64];         /* singular values of L (first min(k,64)) */
+  int32_t r;                /* numerical rank of L used by the certificate */
+  int32_t power_iters;      /* block power iterations run for T4 */
+  int32_t block;            /* block size of the power iteration */
+  int32_t certified;        /* rel_gap <= cert_tol */
+} rpca_cert;
+
+/* Fill `opts` with the defaults.  Never fails. */
+void rpca_default_opts(rpca_opts* opts);
+
+/* Create a context for m x n data, factor rank k (1 <= k <= 32, k <= min(m,n)),
+ * weights lam_S > 0, lam_L > 0 (eq. lag / eq. Thm5).
+ * mask: NULL for full observation, else m x n column-major bytes (nonzero =
+ * observed, the sampling operator P_Omega of Sec. 6.2) in HOST memory; it is
+ * packed into a device bitmask, the caller keeps ownership.
+ * Allocates the device workspace on the current HIP device.
+ * Returns RPCA_EINVAL, RPCA_ENOMEM or RPCA_EHIP on failure (*out untouched). */
+int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
+                const uint8_t* mask, rpca_ctx** out);
+
+/* Objective and gradient at (U, V) (Sec. 1 eq. PhiDef/eq. smoothNC, Sec. 3.2 eq. diff).
+ * X, U, V, gU, gV: device.  f: device pointer to one double receiving f(U,V).
+ * Deterministic: the same inputs give bitwise identical outputs. */
+int rpca_objgrad(rpca_ctx* ctx, const float* X, const float* U, const float* V,
+                 double* f, float* gU, float* gV, void* stream);
+
+/* Minimise f from (U, V) with L-BFGS + strong-Wolfe line search (Sec. 5.1).
+ * X: device.  U, V: device, in = start (ignored with RPCA_INIT_RSVD), out =
+ * solution.  opts: host, NULL = defaults.  info: host, may be NULL.
+ * Blocks the calling thread until the solve ends (the iteration runs on the
+ * device; the host only polls a status word between batches of trials). */
+int rpca_solve(rpca_ctx* ctx, const float* X, float* U, float* V,
+               const rpca_opts* opts, rpca_info* info, void* stream);
+
+/* Convergence certificate at L = U V^T (Sec. 3.4): T1..T3 from the factor
+ * SVD (footnote of Sec. 3.4) and one gradient sweep; T4 by projected block
+ * power iteration on P_U^perp D P_V^perp (an estimate from Ritz values, see
+ * the design notes); gap bound eq. Fbound.  X, U, V: device.  out: host.
+ * Blocks until the result is in `out`. */
+int rpca_certificate(rpca_ctx* ctx, const float* X, const float* U, const float* V,
+                     rpca_cert* out, void* stream);
+
+/* Randomized-SVD start (Sec. 4.2): U0 = U_k S_k^{1/2}, V0 = V_k S_k^{1/2} from
+ * the sketch Y = P_Omega(X) Omega_s, q power steps, B = Q^T P_Omega(X).
+ * Omega_s: device, n x (k+p) row-major FP32 test matrix (p = oversample);
+ * pass NULL to draw it on the device from `seed` (SplitMix64 + Box-Muller).
+ * U, V: device outputs.  Synchronous. */
+int rpca_init_rsvd(rpca_ctx* ctx, const float* X, const float* Omega_s, int32_t oversample,
+                   int32_t power_steps, uint64_t seed, float* U, float* V, void* stream);
+
+/* Kernel classes reported by the profiler. */
+enum rpca_kernel_class {
+  RPCA_K_SWEEP = 0,       /* fused objective/gradient sweep over X */
+  RPCA_K_FINISH = 1,      /* finishing reduction + line-search step */
+  RPCA_K_UPDATE = 2,      /* L-BFGS history update (FP64 dots) */
+  RPCA_K_DIRECTION = 3,   /* L-BFGS direction */
+  RPCA_K_NCLASS = 8
+};
+
+typedef struct rpca_profile {
+  int64_t launches[8];      /* launches per rpca_kernel_class since the last reset */
+  double ms[8];             /* summed device time (HIP events on the launch stream) */
+} rpca_profile;
+
+/* Turn per-launch HIP-event timing of the solver kernels on (1) or off (0).
+ * When on, rpca_objgrad and rpca_solve record an event pair around each kernel
+ * on the stream it runs on; times are collected at the next synchronisation.
+ * Meant for measurement; it adds a little host overhead per launch. */
+int rpca_profile_enable(rpca_ctx* ctx, int32_t on);
+
+/* Copy the accumulated profile into `out` (host); reset it when `reset` != 0.
+ * Synchronises the context's pending events. */
+int rpca_profile_read(rpca_ctx* ctx, rpca_profile* out, int32_t reset);
+
+/* Release the context and its device workspace. NULL is ignored. */
+void rpca_destroy(rpca_ctx* ctx);
+
+/* Human-readable name of a status code (static storage). */
+const char* rpca_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCA_H */

@@ -1,0 +1,908 @@
+// Convergence certificate (Sec. 3.4) and randomized-SVD start (Sec. 4.2).
+//
+// Both need thin products with the m x n operator G = Omega .* clip(U V^T - X)
+// (the certificate, D = G / lam_L) or with A = P_Omega(X) (the rSVD).  Two
+// sweeps cover every case, in FP64 for the vectors and the accumulation:
+//   left : Y = Op W    (W is n x b, Y is m x b; rows of a strip complete in-wave)
+//   right: Z = Op^T Y  (Y is m x b, Z is n x b; per-row-group partials, fixed-order sum)
+// The residual tile is recomputed in registers exactly as in the objective
+// sweep (MFMA with the accumulator seeded by -X), so nothing of size m x n is
+// ever stored.
+//
+// Certificate terms.  With the factor SVD of the footnote of Sec. 3.4 written
+// as U1 = U T_U, V1 = V T_V (T from the eigen-decompositions of U^T U, V^T V
+// and the SVD of R_U R_V^T), every term except the last needs only k x k
+// Gram matrices of [U, G V] and [V, G^T U], which one objective sweep provides:
+//   T1 = ||I + U1^T D V1||^2,   T2 = ||D^T U1||^2 - ||U1^T D V1||^2,
+//   T3 = ||D V1||^2 - ||U1^T D V1||^2,
+// and ||P_U^perp D P_V^perp||_F^2 follows from ||G||_F^2.  T4 =
+// sum (sigma_i(P_U^perp D P_V^perp) - 1)_+^2 replaces the (m-r) x (n-r) SVD of the
+// paper by block power iteration on M^T M with M = P_U^perp D P_V^perp, applied
+// as P_V^perp (D^T D x' - B B^T x'), x' = P_V^perp x, B = D^T U1: one left and one
+// right sweep per iteration.  Ritz values are lower bounds of the singular
+// values; T4 is reported as an estimate with the iteration count.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "rpca_internal.h"
+#include "smalllinalg.h"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int THREADS = 256;
+constexpr int WAVES = 4;
+constexpr int BP = 8;      // columns per pass of a thin product
+constexpr int RJT = 4;     // 16-column tiles per chunk of the right sweep
+
+enum { SRC_RESID = 0, SRC_DATA = 1 };
+
+struct GArgs {
+  const float* X;
+  const uint32_t* mask;
+  int64_t m, n;
+  int32_t k, mw;
+  float lam_s;
+  const float* U;  // residual source only
+  const float* V;
+  const double* W;  // left: n x ldw
+  int32_t ldw;
+  double* Y;        // left: output m x ldy; right: input m x ldy
+  int32_t ldy;
+  int32_t col0, bw;  // columns [col0, col0 + bw) of this pass (bw <= BP)
+  double* part;      // right: [row_groups][n * BP]
+  int32_t strips_per_wg, nchunks, row_groups;
+};
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Operator values for the 4 rows i0+4g+r of column j (held by lane (g, c)).
+template <int SRC, bool MASKED>
+__device__ __forceinline__ void op_tile(const GArgs& a, int64_t i0, int64_t j, bool jok,
+                                        const float (&ua)[8], int KS, float (&G)[4]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  float x[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + 4 * g + r;
+    x[r] = (jok && i < a.m) ? a.X[j * a.m + i] : 0.f;
+  }
+  uint32_t bits = 0xFu;
+  if (MASKED) {
+    bits = 0u;
+    if (jok) bits = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
+  }
+  if (SRC == SRC_RESID) {
+    f4 acc = f4{-x[0], -x[1], -x[2], -x[3]};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < KS) {
+        const int kk = 4 * q + g;
+        const float vb = (jok && kk < a.k) ? a.V[j * a.k + kk] : 0.f;
+        acc = mfma4(ua[q], vb, acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(acc[r], -a.lam_s), a.lam_s);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[r] = x[r];
+  }
+  (void)c;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (MASKED && !((bits >> r) & 1u)) G[r] = 0.f;
+}
+
+template <int SRC>
+__device__ __forceinline__ void load_ua(const GArgs& a, int64_t i0, int KS, float (&ua)[8]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kk = 4 * q + g;
+    const int64_t i = i0 + c;
+    ua[q] = (SRC == SRC_RESID && q < KS && kk < a.k && i < a.m) ? a.U[i * a.k + kk] : 0.f;
+  }
+}
+
+template <int SRC, bool MASKED>
+__global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int KS = (a.k + 3) >> 2;
+  const int64_t nstrips = (a.m + 15) >> 4;
+  const int64_t s_begin = (int64_t)blockIdx.x * a.strips_per_wg;
+  int64_t s_end = s_begin + a.strips_per_wg;
+  if (s_end > nstrips) s_end = nstrips;
+  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
+    const int64_t i0 = s * 16;
+    float ua[8];
+    load_ua<SRC>(a, i0, KS, ua);
+    double acc[4][BP];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int p = 0; p < BP; ++p) acc[r][p] = 0.0;
+    for (int64_t j0 = 0; j0 < a.n; j0 += 16) {
+      const int64_t j = j0 + c;
+      const bool jok = j < a.n;
+      float G[4];
+      op_tile<SRC, MASKED>(a, i0, j, jok, ua, KS, G);
+      double w[BP];
+#pragma unroll
+      for (int p = 0; p < BP; ++p) w[p] = (jok && p < a.bw) ? a.W[j * a.ldw + a.col0 + p] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int p = 0; p < BP; ++p) acc[r][p] = fma((double)G[r], w[p], acc[r][p]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int p = 0; p < BP; ++p) {
+        double v = acc[r][p];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        acc[r][p] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 4 * g + r;
+      double sel = 0.0;
+#pragma unroll
+      for (int p = 0; p < BP; ++p) sel = (p == c) ? acc[r][p] : sel;
+      if (c < a.bw && i < a.m) a.Y[i * a.ldy + a.col0 + c] = sel;
+    }
+  }
+}
+
+template <int SRC, bool MASKED>
+__global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
+  __shared__ double sZ[RJT * 16 * BP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int KS = (a.k + 3) >> 2;
+  const int rg = blockIdx.x, ch = blockIdx.y;
+  const int64_t j_begin = (int64_t)ch * RJT * 16;
+  const int ncols = (int)((a.n - j_begin) < RJT * 16 ? (a.n - j_begin) : RJT * 16);
+  const int64_t nstrips = (a.m + 15) >> 4;
+  const int64_t s_begin = (int64_t)rg * a.strips_per_wg;
+  int64_t s_end = s_begin + a.strips_per_wg;
+  if (s_end > nstrips) s_end = nstrips;
+  double z[RJT][BP];
+#pragma unroll
+  for (int t = 0; t < RJT; ++t)
+#pragma unroll
+    for (int p = 0; p < BP; ++p) z[t][p] = 0.0;
+  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
+    const int64_t i0 = s * 16;
+    float ua[8];
+    load_ua<SRC>(a, i0, KS, ua);
+    double y[4][BP];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 4 * g + r;
+#pragma unroll
+      for (int p = 0; p < BP; ++p) y[r][p] = (i < a.m && p < a.bw) ? a.Y[i * a.ldy + a.col0 + p] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < RJT; ++t) {
+      if (t * 16 < ncols) {
+        const int64_t j = j_begin + t * 16 + c;
+        const bool jok = (t * 16 + c) < ncols;
+        float G[4];
+        op_tile<SRC, MASKED>(a, i0, j, jok, ua, KS, G);
+#pragma unroll
+        for (int p = 0; p < BP; ++p) {
+          double v = z[t][p];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v = fma((double)G[r], y[r][p], v);
+          z[t][p] = v;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RJT; ++t)
+#pragma unroll
+    for (int p = 0; p < BP; ++p) {
+      double v = z[t][p];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      z[t][p] = v;
+    }
+  for (int w = 0; w < WAVES; ++w) {
+    if (wave == w && g == 0) {
+#pragma unroll
+      for (int t = 0; t < RJT; ++t)
+#pragma unroll
+        for (int p = 0; p < BP; ++p) {
+          const int idx = (t * 16 + c) * BP + p;
+          sZ[idx] = (w == 0 ? 0.0 : sZ[idx]) + z[t][p];
+        }
+    }
+    __syncthreads();
+  }
+  double* out = a.part + (int64_t)rg * a.n * BP;
+  for (int idx = threadIdx.x; idx < ncols * BP; idx += THREADS)
+    out[(j_begin + idx / BP) * BP + idx % BP] = sZ[idx];
+}
+
+__global__ void k_right_reduce(const double* part, int row_groups, int64_t n, double* Z, int ldz,
+                               int col0, int bw) {
+  const int64_t o = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (o >= n * BP) return;
+  const int p = (int)(o % BP);
+  if (p >= bw) return;
+  double s = 0.0;
+  for (int r = 0; r < row_groups; ++r) s += part[(int64_t)r * n * BP + o];
+  Z[(o / BP) * ldz + col0 + p] = s;
+}
+
+// Gram matrices of thin row sets, FP64.  mode 0: row i = [A_i, B_i - lam A_i]
+// (A, B are FP32 rows of width k); mode 1: row i = D_i (FP64, width w).
+struct GramArgs {
+  int64_t rows;
+  int32_t w, mode, k, ldd;
+  float lam;
+  const float* A;
+  const float* B;
+  const double* D;
+  double* part;  // [blocks][w*w]
+};
+
+__global__ __launch_bounds__(THREADS) void k_gram(GramArgs a) {
+  constexpr int TR = 32;
+  __shared__ double tile[TR][64];
+  const int w = a.w, ww = w * w;
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * TR; r0 < a.rows; r0 += (int64_t)gridDim.x * TR) {
+    for (int idx = threadIdx.x; idx < TR * w; idx += THREADS) {
+      const int rr = idx / w, cc = idx % w;
+      const int64_t i = r0 + rr;
+      double v = 0.0;
+      if (i < a.rows) {
+        if (a.mode == 0) {
+          if (cc < a.k) v = a.A[i * a.k + cc];
+          else v = (double)a.B[i * a.k + cc - a.k] - (double)a.lam * (double)a.A[i * a.k + cc - a.k];
+        } else {
+          v = a.D[i * a.ldd + cc];
+        }
+      }
+      tile[rr][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = threadIdx.x + e * THREADS;
+      if (idx < ww) {
+        const int p = idx / w, q = idx % w;
+        double s = acc[e];
+        for (int rr = 0; rr < TR; ++rr) s = fma(tile[rr][p], tile[rr][q], s);
+        acc[e] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int idx = threadIdx.x + e * THREADS;
+    if (idx < ww) a.part[(int64_t)blockIdx.x * ww + idx] = acc[e];
+  }
+}
+
+// out_i = in_i T  (in: FP64 rows of width win, ld ldi; T: win x wout FP64 in global;
+// out: FP64 (ld ldo) or FP32 (ld ldo) rows of width wout).
+__global__ void k_row_transform(const double* in, int ldi, int win, const double* T, int wout,
+                                int64_t rows, double* out64, float* out32, int ldo) {
+  const int64_t o = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (o >= rows * wout) return;
+  const int64_t i = o / wout;
+  const int cc = (int)(o % wout);
+  double s = 0.0;
+  for (int t = 0; t < win; ++t) s = fma(in[i * ldi + t], T[t * wout + cc], s);
+  if (out64) out64[i * ldo + cc] = s;
+  else out32[i * ldo + cc] = (float)s;
+}
+
+// ----------------------------------------------------------------------------
+// Host helpers.
+
+struct Workspace {
+  double* Wd;    // n x LMAX
+  double* Yd;    // m x LMAX
+  double* Y2;    // m x LMAX
+  double* Zd;    // n x LMAX
+  double* part;  // right-sweep partials
+  double* gram;  // gram partials
+  double* T;     // small transform (64 x 64)
+  float* gU;     // m x k
+  float* gV;     // n x k
+  float* zU;     // zeros m x k
+  float* zV;     // zeros n x k
+  double* scal;  // 16 doubles
+  int rg_left, spw_left, rg_right, spw_right, nch_right, gram_blocks;
+};
+
+constexpr int LMAX = 48;
+
+int64_t align_up(int64_t v) { return (v + 63) / 64 * 64; }
+
+int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s);
+
+hipError_t left_product(const rpca::CtxView& cv, const Workspace& w, const float* X, int src,
+                        const float* U, const float* V, const double* W, int ldw, double* Y,
+                        int ldy, int l, hipStream_t s) {
+  GArgs a;
+  memset(&a, 0, sizeof(a));
+  a.X = X;
+  a.mask = cv.mask;
+  a.m = cv.m;
+  a.n = cv.n;
+  a.k = cv.k;
+  a.mw = cv.mw;
+  a.lam_s = (float)cv.lam_s;
+  a.U = U;
+  a.V = V;
+  a.W = W;
+  a.ldw = ldw;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.strips_per_wg = w.spw_left;
+  for (int col0 = 0; col0 < l; col0 += BP) {
+    a.col0 = col0;
+    a.bw = std::min(BP, l - col0);
+    const dim3 grid(w.rg_left);
+    if (src == SRC_RESID) {
+      if (cv.mask) hipLaunchKernelGGL((k_left<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_left<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
+    } else {
+      if (cv.mask) hipLaunchKernelGGL((k_left<SRC_DATA, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_left<SRC_DATA, false>), grid, dim3(THREADS), 0, s, a);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const float* X, int src,
+                         const float* U, const float* V, double* Y, int ldy, double* Z, int ldz,
+                         int l, hipStream_t s) {
+  GArgs a;
+  memset(&a, 0, sizeof(a));
+  a.X = X;
+  a.mask = cv.mask;
+  a.m = cv.m;
+  a.n = cv.n;
+  a.k = cv.k;
+  a.mw = cv.mw;
+  a.lam_s = (float)cv.lam_s;
+  a.U = U;
+  a.V = V;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.part = w.part;
+  a.strips_per_wg = w.spw_right;
+  a.nchunks = w.nch_right;
+  a.row_groups = w.rg_right;
+  for (int col0 = 0; col0 < l; col0 += BP) {
+    a.col0 = col0;
+    a.bw = std::min(BP, l - col0);
+    const dim3 grid(w.rg_right, w.nch_right);
+    if (src == SRC_RESID) {
+      if (cv.mask) hipLaunchKernelGGL((k_right<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_right<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
+    } else {
+      if (cv.mask) hipLaunchKernelGGL((k_right<SRC_DATA, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_right<SRC_DATA, false>), grid, dim3(THREADS), 0, s, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t outs = cv.n * BP;
+    hipLaunchKernelGGL(k_right_reduce, dim3((unsigned)((outs + THREADS - 1) / THREADS)), dim3(THREADS),
+                       0, s, (const double*)w.part, w.rg_right, cv.n, Z, ldz, col0, a.bw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Gram of rows (synchronous; result on the host, w x w row-major).
+int gram_host(const Workspace& ws, const GramArgs& ga_in, std::vector<double>& out, hipStream_t s) {
+  GramArgs ga = ga_in;
+  ga.part = ws.gram;
+  const int blocks = ws.gram_blocks;
+  hipLaunchKernelGGL(k_gram, dim3(blocks), dim3(THREADS), 0, s, ga);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  const int ww = ga.w * ga.w;
+  std::vector<double> h((size_t)blocks * ww);
+  if (hipMemcpyAsync(h.data(), ws.gram, h.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  out.assign(ww, 0.0);
+  for (int b = 0; b < blocks; ++b)
+    for (int e = 0; e < ww; ++e) out[e] += h[(size_t)b * ww + e];
+  return RPCA_OK;
+}
+
+// Orthonormalise the columns of an FP64 device matrix (rows x l, ld) in place:
+// Q = Y W Lambda^{-1/2} from the eigen-decomposition of Y^T Y, twice.  Columns
+// in directions with eigenvalue below 1e-13 of the largest become zero.
+int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows, int l, int ld,
+                       hipStream_t s) {
+  for (int pass = 0; pass < 2; ++pass) {
+    GramArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.rows = rows;
+    ga.w = l;
+    ga.mode = 1;
+    ga.D = Y;
+    ga.ldd = ld;
+    std::vector<double> G;
+    int rc = gram_host(ws, ga, G, s);
+    if (rc) return rc;
+    std::vector<double> ev(l), W((size_t)l * l), T((size_t)l * l, 0.0);
+    rpca::la::sym_eig(G.data(), l, ev.data(), W.data());
+    const double top = std::max(ev[0], 0.0);
+    for (int j = 0; j < l; ++j) {
+      const double sc = (ev[j] > 1e-13 * top && ev[j] > 0) ? 1.0 / sqrt(ev[j]) : 0.0;
+      for (int i = 0; i < l; ++i) T[(size_t)i * l + j] = W[(size_t)i * l + j] * sc;
+    }
+    if (hipMemcpyAsync(ws.T, T.data(), T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    const int64_t outs = rows * l;
+    hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((outs + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
+                       (const double*)Y, ld, l, (const double*)ws.T, l, rows, tmp, (float*)nullptr, ld);
+    if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+    if (hipMemcpyAsync(Y, tmp, (size_t)rows * ld * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return RPCA_EHIP;
+  }
+  return RPCA_OK;
+}
+
+// Counter-based normal deviates: SplitMix64 (Steele, Lea & Flood 2014) feeding
+// Box-Muller.  Deviate number `idx` of stream `seed`.
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+double normal_deviate(uint64_t seed, uint64_t idx) {
+  const uint64_t a = splitmix64(seed * 0x100000001B3ull + 2 * idx);
+  const uint64_t b = splitmix64(seed * 0x100000001B3ull + 2 * idx + 1);
+  const double u1 = ((a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((b >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+}  // namespace
+
+
+namespace {
+
+int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
+  const rpca::CtxView cv = rpca::ctx_view(c);
+  const int64_t m = cv.m, n = cv.n, k = cv.k;
+  const int64_t nstrips = (m + 15) / 16;
+  // left sweep: ~1024 workgroups of 4 waves
+  int64_t spw = std::max<int64_t>(4, ((nstrips + 1023) / 1024 + 3) / 4 * 4);
+  w->spw_left = (int)spw;
+  w->rg_left = (int)((nstrips + spw - 1) / spw);
+  w->nch_right = (int)((n + RJT * 16 - 1) / (RJT * 16));
+  int64_t target = std::max<int64_t>(1, 1024 / w->nch_right);
+  int64_t spr = std::max<int64_t>(4, ((nstrips + target - 1) / target + 3) / 4 * 4);
+  w->spw_right = (int)spr;
+  w->rg_right = (int)((nstrips + spr - 1) / spr);
+  w->gram_blocks = 256;
+  size_t off = 0;
+  const size_t sz_W = align_up(n * LMAX) * 8, sz_Y = align_up(m * LMAX) * 8;
+  const size_t sz_part = align_up((int64_t)w->rg_right * n * BP) * 8;
+  const size_t sz_gram = align_up((int64_t)w->gram_blocks * 64 * 64) * 8;
+  const size_t sz_T = 64 * 64 * 8;
+  const size_t sz_gU = align_up(m * k) * 4, sz_gV = align_up(n * k) * 4;
+  const size_t total = sz_W * 2 + sz_Y * 2 + sz_part + sz_gram + sz_T + sz_gU * 2 + sz_gV * 2 + 256;
+  int fresh = 0;
+  char* base = (char*)rpca::ctx_workspace(c, total, &fresh);
+  if (!base) return RPCA_ENOMEM;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += bytes;
+    return p;
+  };
+  w->Wd = (double*)take(sz_W);
+  w->Zd = (double*)take(sz_W);
+  w->Yd = (double*)take(sz_Y);
+  w->Y2 = (double*)take(sz_Y);
+  w->part = (double*)take(sz_part);
+  w->gram = (double*)take(sz_gram);
+  w->T = (double*)take(sz_T);
+  w->gU = (float*)take(sz_gU);
+  w->zU = (float*)take(sz_gU);
+  w->gV = (float*)take(sz_gV);
+  w->zV = (float*)take(sz_gV);
+  w->scal = (double*)take(256);
+  if (fresh) {  // zero factors used for phi(0)
+    if (hipMemsetAsync(w->zU, 0, sz_gU, s) != hipSuccess) return RPCA_EHIP;
+    if (hipMemsetAsync(w->zV, 0, sz_gV, s) != hipSuccess) return RPCA_EHIP;
+  }
+  return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, const float* V,
+                                rpca_cert* out, void* stream) {
+  if (!c || !X || !U || !V || !out) return RPCA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const rpca::CtxView cv = rpca::ctx_view(c);
+  const int64_t m = cv.m, n = cv.n;
+  const int k = cv.k;
+  const double lam_l = cv.lam_l;
+  Workspace ws;
+  int rc = get_workspace(c, &ws, s);
+  if (rc) return rc;
+  memset(out, 0, sizeof(*out));
+  // 1. phi(0) from a sweep at U = V = 0, then one sweep at (U, V): G V, G^T U,
+  //    phi(L), ||U||^2, ||V||^2, ||G||^2
+  rc = rpca::ctx_objgrad_aux(c, X, ws.zU, ws.zV, ws.scal + 8, ws.scal + 9, ws.gU, ws.gV, s);
+  if (rc) return rc;
+  rc = rpca::ctx_objgrad_aux(c, X, U, V, ws.scal, ws.scal + 1, ws.gU, ws.gV, s);
+  if (rc) return rc;
+  double scal[16];
+  if (hipMemcpyAsync(scal, ws.scal, sizeof(scal), hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  const double phiL = scal[1], g2 = scal[4], phi0 = scal[9];
+  // 2. Gram matrices [U, G V] (m rows) and [V, G^T U] (n rows), 2k x 2k
+  std::vector<double> GU, GV;
+  GramArgs ga;
+  memset(&ga, 0, sizeof(ga));
+  ga.rows = m;
+  ga.w = 2 * k;
+  ga.mode = 0;
+  ga.k = k;
+  ga.lam = (float)lam_l;
+  ga.A = U;
+  ga.B = ws.gU;
+  if ((rc = gram_host(ws, ga, GU, s))) return rc;
+  ga.rows = n;
+  ga.A = V;
+  ga.B = ws.gV;
+  if ((rc = gram_host(ws, ga, GV, s))) return rc;
+  const int w2 = 2 * k;
+  auto blk = [&](const std::vector<double>& G, int bi, int bj, std::vector<double>& o) {
+    o.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) o[(size_t)i * k + j] = G[(size_t)(bi * k + i) * w2 + bj * k + j];
+  };
+  std::vector<double> UtU, UtA, AtA, VtV, VtB, BtB;  // A = G V, B = G^T U
+  blk(GU, 0, 0, UtU);
+  blk(GU, 0, 1, UtA);
+  blk(GU, 1, 1, AtA);
+  blk(GV, 0, 0, VtV);
+  blk(GV, 0, 1, VtB);
+  blk(GV, 1, 1, BtB);
+  // 3. factor SVD: U = Q_U R_U with R_U = Lam^{1/2} W^T (eigen of U^T U), same for V
+  std::vector<double> eu(k), Wu((size_t)k * k), evv(k), Wv((size_t)k * k);
+  rpca::la::sym_eig(UtU.data(), k, eu.data(), Wu.data());
+  rpca::la::sym_eig(VtV.data(), k, evv.data(), Wv.data());
+  std::vector<double> Ru((size_t)k * k), Rv((size_t)k * k), Pu((size_t)k * k, 0.0), Pv((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      Ru[(size_t)i * k + j] = sqrt(std::max(eu[i], 0.0)) * Wu[(size_t)j * k + i];
+      Rv[(size_t)i * k + j] = sqrt(std::max(evv[i], 0.0)) * Wv[(size_t)j * k + i];
+    }
+  // Pu = W_U Lam_U^{-1/2} (pseudo-inverse on tiny eigenvalues): Q_U = U Pu
+  for (int j = 0; j < k; ++j) {
+    const double su = (eu[j] > 1e-14 * std::max(eu[0], 0.0) && eu[j] > 0) ? 1.0 / sqrt(eu[j]) : 0.0;
+    const double sv = (evv[j] > 1e-14 * std::max(evv[0], 0.0) && evv[j] > 0) ? 1.0 / sqrt(evv[j]) : 0.0;
+    for (int i = 0; i < k; ++i) {
+      Pu[(size_t)i * k + j] = Wu[(size_t)i * k + j] * su;
+      Pv[(size_t)i * k + j] = Wv[(size_t)i * k + j] * sv;
+    }
+  }
+  // SVD of Mk = R_U R_V^T via the eigen-decomposition of Mk^T Mk (k x k, FP64)
+  std::vector<double> Mk((size_t)k * k), MtM((size_t)k * k), sig2(k), VR((size_t)k * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double sacc = 0.0;
+      for (int t = 0; t < k; ++t) sacc += Ru[(size_t)i * k + t] * Rv[(size_t)j * k + t];
+      Mk[(size_t)i * k + j] = sacc;
+    }
+  rpca::la::matmul_tn(Mk.data(), Mk.data(), MtM.data(), k, k, k);
+  rpca::la::sym_eig(MtM.data(), k, sig2.data(), VR.data());
+  std::vector<double> sig(k);
+  for (int i = 0; i < k; ++i) sig[i] = sqrt(std::max(sig2[i], 0.0));
+  const double tau = 1e-6;  // FP32 factors: rank threshold relative to sigma_1
+  int r = 0;
+  for (int i = 0; i < k; ++i)
+    if (sig[i] > tau * sig[0] && sig[0] > 0) ++r;
+  // U_R = Mk V_R Sigma^{-1} (first r columns)
+  std::vector<double> UR((size_t)k * std::max(r, 1), 0.0), VRr((size_t)k * std::max(r, 1), 0.0);
+  for (int j = 0; j < r; ++j)
+    for (int i = 0; i < k; ++i) {
+      double sacc = 0.0;
+      for (int t = 0; t < k; ++t) sacc += Mk[(size_t)i * k + t] * VR[(size_t)t * k + j];
+      UR[(size_t)i * r + j] = sacc / sig[j];
+      VRr[(size_t)i * r + j] = VR[(size_t)i * k + j];
+    }
+  // T_U = Pu U_R, T_V = Pv V_R  (U1 = U T_U, V1 = V T_V)
+  std::vector<double> TU((size_t)k * std::max(r, 1), 0.0), TV((size_t)k * std::max(r, 1), 0.0);
+  if (r) {
+    rpca::la::matmul(Pu.data(), UR.data(), TU.data(), k, k, r);
+    rpca::la::matmul(Pv.data(), VRr.data(), TV.data(), k, k, r);
+  }
+  // 4. cheap terms
+  auto quad = [&](const std::vector<double>& Gm, const std::vector<double>& Ta,
+                  const std::vector<double>& Tb, std::vector<double>& o) {  // o = Ta^T Gm Tb (r x r)
+    std::vector<double> tmp((size_t)k * std::max(r, 1));
+    rpca::la::matmul(Gm.data(), Tb.data(), tmp.data(), k, k, r);
+    o.assign((size_t)r * r, 0.0);
+    rpca::la::matmul_tn(Ta.data(), tmp.data(), o.data(), k, r, r);
+  };
+  std::vector<double> Cm, DV1n, DU1n;
+  double T1 = 0, T2 = 0, T3 = 0, nC = 0, nDV1 = 0, nDtU1 = 0;
+  if (r) {
+    quad(UtA, TU, TV, Cm);  // U1^T (G V) T_V = lam_l * U1^T D V1
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        const double cij = Cm[(size_t)i * r + j] / lam_l;
+        nC += cij * cij;
+        const double e = (i == j ? 1.0 : 0.0) + cij;
+        T1 += e * e;
+      }
+    quad(AtA, TV, TV, DV1n);  // T_V^T A^T A T_V
+    quad(BtB, TU, TU, DU1n);  // T_U^T B^T B T_U
+    for (int i = 0; i < r; ++i) {
+      nDV1 += DV1n[(size_t)i * r + i] / (lam_l * lam_l);
+      nDtU1 += DU1n[(size_t)i * r + i] / (lam_l * lam_l);
+    }
+    T2 = std::max(nDtU1 - nC, 0.0);
+    T3 = std::max(nDV1 - nC, 0.0);
+  }
+  const double nD2 = g2 / (lam_l * lam_l);
+  const double normM2 = std::max(nD2 - nDtU1 - nDV1 + nC, 0.0);
+  // 5. T4 by block power iteration on M^T M (host-side projections, n x b).  The
+  //    block grows (8 -> 16 -> 32) while its smallest Ritz value is still above 1,
+  //    so that every singular value above 1 is captured when there are at most 31.
+  const int bmax = (int)std::min<int64_t>(32, std::max<int64_t>(1, n - r));
+  int b = std::min(8, bmax);
+  std::vector<double> Vh((size_t)n * k), Bh((size_t)n * k);
+  {
+    std::vector<float> tmpV((size_t)n * k), tmpB((size_t)n * k);
+    if (hipMemcpyAsync(tmpV.data(), V, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+    if (hipMemcpyAsync(tmpB.data(), ws.gV, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+    for (size_t i = 0; i < tmpV.size(); ++i) {
+      Vh[i] = tmpV[i];
+      Bh[i] = (double)tmpB[i] - lam_l * (double)tmpV[i];  // G^T U
+    }
+  }
+  // V1 (n x r) and Bn = D^T U1 = (G^T U) T_U / lam_l (n x r)
+  std::vector<double> V1((size_t)n * std::max(r, 1), 0.0), Bn((size_t)n * std::max(r, 1), 0.0);
+  if (r) {
+    rpca::la::matmul(Vh.data(), TV.data(), V1.data(), (int)n, k, r);
+    rpca::la::matmul(Bh.data(), TU.data(), Bn.data(), (int)n, k, r);
+    for (auto& x : Bn) x /= lam_l;
+  }
+  auto proj_v = [&](std::vector<double>& Xb, int bb) {  // Xb (n x bb) <- P_V^perp Xb
+    if (!r) return;
+    std::vector<double> coef((size_t)r * bb);
+    rpca::la::matmul_tn(V1.data(), Xb.data(), coef.data(), (int)n, r, bb);
+    for (int64_t i = 0; i < n; ++i)
+      for (int p = 0; p < bb; ++p) {
+        double sacc = 0.0;
+        for (int t = 0; t < r; ++t) sacc += V1[(size_t)i * r + t] * coef[(size_t)t * bb + p];
+        Xb[(size_t)i * bb + p] -= sacc;
+      }
+  };
+  auto orth_host = [&](std::vector<double>& Xb, int bb) {  // modified Gram-Schmidt, twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (int p = 0; p < bb; ++p) {
+        for (int q = 0; q < p; ++q) {
+          double d = 0.0;
+          for (int64_t i = 0; i < n; ++i) d += Xb[(size_t)i * bb + p] * Xb[(size_t)i * bb + q];
+          for (int64_t i = 0; i < n; ++i) Xb[(size_t)i * bb + p] -= d * Xb[(size_t)i * bb + q];
+        }
+        double nn = 0.0;
+        for (int64_t i = 0; i < n; ++i) nn += Xb[(size_t)i * bb + p] * Xb[(size_t)i * bb + p];
+        nn = sqrt(nn);
+        for (int64_t i = 0; i < n; ++i) Xb[(size_t)i * bb + p] = nn > 0 ? Xb[(size_t)i * bb + p] / nn : 0.0;
+      }
+  };
+  std::vector<double> Xb((size_t)n * b), Zb, ritz(b, 0.0);
+  for (int64_t i = 0; i < n * b; ++i) Xb[i] = normal_deviate(0xC0FFEEull, (uint64_t)i);
+  int it_total = 0;
+  const int max_it = 300;
+  for (;;) {
+    proj_v(Xb, b);
+    orth_host(Xb, b);
+    std::vector<double> prev(b, -1.0);
+    ritz.assign(b, 0.0);
+    Zb.assign((size_t)n * b, 0.0);
+    for (int it = 0; it < max_it; ++it) {
+      ++it_total;
+      if (hipMemcpyAsync(ws.Wd, Xb.data(), Xb.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+      if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, b, ws.Yd, b, b, s) != hipSuccess) return RPCA_EHIP;
+      if (right_product(cv, ws, X, SRC_RESID, U, V, ws.Yd, b, ws.Zd, b, b, s) != hipSuccess) return RPCA_EHIP;
+      if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+      for (auto& z : Zb) z /= (lam_l * lam_l);
+      if (r) {  // Z -= Bn (Bn^T X)
+        std::vector<double> coef((size_t)r * b);
+        rpca::la::matmul_tn(Bn.data(), Xb.data(), coef.data(), (int)n, r, b);
+        for (int64_t i = 0; i < n; ++i)
+          for (int p = 0; p < b; ++p) {
+            double sacc = 0.0;
+            for (int t = 0; t < r; ++t) sacc += Bn[(size_t)i * r + t] * coef[(size_t)t * b + p];
+            Zb[(size_t)i * b + p] -= sacc;
+          }
+      }
+      proj_v(Zb, b);
+      // Rayleigh-Ritz on span(X): H = X^T Z
+      std::vector<double> H((size_t)b * b), hw(b), HW((size_t)b * b);
+      rpca::la::matmul_tn(Xb.data(), Zb.data(), H.data(), (int)n, b, b);
+      for (int p = 0; p < b; ++p)
+        for (int q = p + 1; q < b; ++q) {
+          const double avg = 0.5 * (H[(size_t)p * b + q] + H[(size_t)q * b + p]);
+          H[(size_t)p * b + q] = H[(size_t)q * b + p] = avg;
+        }
+      rpca::la::sym_eig(H.data(), b, hw.data(), HW.data());
+      double dmax = 0.0;
+      for (int p = 0; p < b; ++p) {
+        ritz[p] = std::max(hw[p], 0.0);
+        dmax = std::max(dmax, fabs(ritz[p] - prev[p]));
+      }
+      const double d0 = fabs(ritz[0] - prev[0]);
+      for (int p = 0; p < b; ++p) prev[p] = ritz[p];
+      Xb = Zb;
+      orth_host(Xb, b);
+      const bool all_conv = dmax <= 1e-8 * std::max(ritz[0], 1e-300);
+      const bool below_one = ritz[0] < 0.98 * 0.98 && d0 <= 1e-7 * ritz[0];
+      if (it > 2 && (all_conv || below_one)) break;
+    }
+    if (sqrt(ritz[b - 1]) > 1.0 && b < bmax) {
+      // grow the block, keeping the current subspace and adding fresh directions
+      const int nb = std::min(2 * b, bmax);
+      std::vector<double> Xn((size_t)n * nb);
+      for (int64_t i = 0; i < n; ++i)
+        for (int p = 0; p < nb; ++p)
+          Xn[(size_t)i * nb + p] = p < b ? Xb[(size_t)i * b + p]
+                                         : normal_deviate(0xC0FFEEull + nb, (uint64_t)(i * nb + p));
+      Xb.swap(Xn);
+      b = nb;
+      continue;
+    }
+    break;
+  }
+  double T4 = 0.0, sum_t2 = 0.0;
+  for (int p = 0; p < b; ++p) {
+    const double th = sqrt(ritz[p]);
+    if (p < 32) out->theta[p] = th;
+    if (p < b - 1 || b == 1) {
+      T4 += std::max(th - 1.0, 0.0) * std::max(th - 1.0, 0.0);
+      sum_t2 += th * th;
+    }
+  }
+  if (b > 1) {
+    const double thb = sqrt(ritz[b - 1]);
+    if (thb > 1.0) {
+      // more than b-1 singular values may exceed 1: bound the rest by
+      // (sigma - 1)_+ <= sigma (1 - 1/theta_b) for sigma <= theta_b
+      const double tail = std::max(normM2 - sum_t2, 0.0);
+      T4 += (1.0 - 1.0 / thb) * (1.0 - 1.0 / thb) * tail;
+    } else {
+      T4 += std::max(thb - 1.0, 0.0) * std::max(thb - 1.0, 0.0);
+    }
+  }
+  const int it = it_total;
+  // 6. gap bound (eq. Fbound)
+  double nuc = 0.0, normL2 = 0.0, trunc2 = 0.0;
+  for (int i = 0; i < k; ++i) {
+    nuc += sig[i];
+    normL2 += sig[i] * sig[i];
+    if (i >= r) trunc2 += sig[i] * sig[i];
+  }
+  const double E = sqrt(std::max(T1 + T2 + T3 + T4, 0.0)) + sqrt(trunc2) / lam_l;
+  const double F = lam_l * nuc + phiL;
+  double* best = cv.best_F;
+  if (F < *best) *best = F;
+  const double Fb = std::min(std::min(F, phi0), *best);
+  const double normL = sqrt(normL2);
+  out->T1 = T1;
+  out->T2 = T2;
+  out->T3 = T3;
+  out->T4 = T4;
+  out->E = E;
+  out->F = F;
+  out->phi = phiL;
+  out->phi0 = phi0;
+  out->F_bound = Fb;
+  out->normL = normL;
+  out->gap = E * (lam_l * normL + Fb);
+  out->rel_gap = F > 0 ? out->gap / F : (out->gap == 0 ? 0.0 : INFINITY);
+  out->normM2 = normM2;
+  for (int i = 0; i < k && i < 64; ++i) out->sigma[i] = sig[i];
+  out->r = r;
+  out->power_iters = it;
+  out->block = b;
+  out->certified = out->rel_gap <= 1e-3;
+  return RPCA_OK;
+}
+
+extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s, int32_t oversample,
+                              int32_t power_steps, uint64_t seed, float* U, float* V, void* stream) {
+  if (!c || !X || !U || !V) return RPCA_EINVAL;
+  if (oversample < 0 || power_steps < 0 || power_steps > 16) return RPCA_EINVAL;
+  const rpca::CtxView cv = rpca::ctx_view(c);
+  const int64_t m = cv.m, n = cv.n;
+  const int k = cv.k;
+  const int l = (int)std::min<int64_t>(std::min<int64_t>(k + oversample, LMAX), std::min(m, n));
+  if (l < k) return RPCA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Workspace ws;
+  int rc = get_workspace(c, &ws, s);
+  if (rc) return rc;
+  // test matrix Omega_s (n x l) in FP64
+  std::vector<double> Om((size_t)n * l);
+  if (Omega_s) {
+    std::vector<float> tmp((size_t)n * l);
+    if (hipMemcpyAsync(tmp.data(), Omega_s, tmp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+    for (size_t i = 0; i < tmp.size(); ++i) Om[i] = tmp[i];
+  } else {
+    for (size_t i = 0; i < Om.size(); ++i) Om[i] = normal_deviate(seed, i);
+  }
+  if (hipMemcpyAsync(ws.Wd, Om.data(), Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  // Y = A Omega, Q = orth(Y)
+  if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+  if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+  for (int q = 0; q < power_steps; ++q) {
+    if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
+    if ((rc = orthonormalize_dev(ws, ws.Zd, ws.Wd, n, l, l, s))) return rc;
+    if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Zd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+    if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+  }
+  // B^T = A^T Q (n x l); B B^T = W Lam W^T
+  if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
+  std::vector<double> Zb((size_t)n * l);
+  if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  std::vector<double> BBt((size_t)l * l), lam(l), W((size_t)l * l);
+  rpca::la::matmul_tn(Zb.data(), Zb.data(), BBt.data(), (int)n, l, l);
+  rpca::la::sym_eig(BBt.data(), l, lam.data(), W.data());
+  // U0 = Q W_k Sigma^{1/2}, V0 = B^T W_k Sigma^{-1/2}
+  std::vector<double> TU((size_t)l * k, 0.0), TV((size_t)l * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    const double sg = sqrt(std::max(lam[j], 0.0));
+    const double rs = sqrt(sg);
+    const double irs = rs > 0 ? 1.0 / rs : 0.0;
+    for (int i = 0; i < l; ++i) {
+      TU[(size_t)i * k + j] = W[(size_t)i * l + j] * rs;
+      TV[(size_t)i * k + j] = W[(size_t)i * l + j] * irs;
+    }
+  }
+  if (hipMemcpyAsync(ws.T, TU.data(), TU.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((m * k + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
+                     (const double*)ws.Yd, l, l, (const double*)ws.T, k, m, (double*)nullptr, U, k);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  std::vector<float> V0((size_t)n * k);
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < k; ++j) {
+      double sacc = 0.0;
+      for (int t = 0; t < l; ++t) sacc += Zb[(size_t)i * l + t] * TV[(size_t)t * k + j];
+      V0[(size_t)i * k + j] = (float)sacc;
+    }
+  if (hipMemcpyAsync(V, V0.data(), V0.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  return RPCA_OK;
+}

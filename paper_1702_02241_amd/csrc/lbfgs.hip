@@ -1,0 +1,366 @@
+// Device-resident L-BFGS (memory <= 15) for the flat vector x = [vec(U); vec(V)].
+//
+// The paper's solver is L-BFGS with 10 pairs in memory (Sec. 5.1, Table 1).  On
+// the GPU the two-loop recursion would need 2*mem dependent grid-wide
+// reductions per iteration, so the direction uses the equivalent compact form
+// of the inverse Hessian (Byrd, Nocedal & Schnabel 1994, Thm. 2.2) with H0 = gamma I:
+//
+//   H g = gamma g + S p + gamma Y q,   q = -R^{-1} a,
+//   p   = R^{-T} ( (Dg + gamma Y^T Y) R^{-1} a - gamma b ),   a = S^T g, b = Y^T g,
+//
+// where R is the upper triangle of S^T Y and Dg its diagonal.  One pass over
+// the history ("update") computes every inner product the small matrices need
+// in FP64; a second pass ("direction") forms d = -H g.  Both passes end in a
+// last-block reduction that runs the small (mem x mem) algebra on one
+// thread, so the whole iteration stays on the device.
+#include "rpca_internal.h"
+
+#include <math.h>
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int THREADS = 256;
+constexpr int WAVES = THREADS / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ double dot4(f4 a, f4 b) {
+  return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2] + (double)a[3] * b[3];
+}
+
+// Reduce NV per-thread values over the block, write them value-major to part[v*nb + block],
+// then let the last block sum them over blocks into out[] (shared).  Returns true in the
+// last block (after out[] is valid in every thread).
+template <int NV>
+__device__ bool reduce_partials(const double (&acc)[NV], const bool (&is_max)[NV], double* part,
+                                unsigned int* counter, double* out) {
+  __shared__ double sh[WAVES][NV];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double r = is_max[v] ? wave_max(acc[v]) : wave_sum(acc[v]);
+    if (lane == 0) sh[wave][v] = r;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < NV; v += THREADS) {
+    double r = sh[0][v];
+    for (int w = 1; w < WAVES; ++w) r = is_max[v] ? fmax(r, sh[w][v]) : r + sh[w][v];
+    part[(int64_t)v * nb + blockIdx.x] = r;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == (unsigned)nb - 1u);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  for (int v = 0; v < NV; ++v) {
+    double r = is_max[v] ? 0.0 : 0.0;
+    for (int b = threadIdx.x; b < nb; b += THREADS) {
+      const double x = part[(int64_t)v * nb + b];
+      r = is_max[v] ? fmax(r, x) : r + x;
+    }
+    r = is_max[v] ? wave_max(r) : wave_sum(r);
+    if (lane == 0) sh[wave][v] = r;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < NV; v += THREADS) {
+    double r = sh[0][v];
+    for (int w = 1; w < WAVES; ++w) r = is_max[v] ? fmax(r, sh[w][v]) : r + sh[w][v];
+    out[v] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+// Indices into the dot vector of the update pass.
+constexpr int D_SY = 4 * RPCA_MEMMAX + 0;  // s_new . y_new
+constexpr int D_YY = D_SY + 1;             // y_new . y_new
+constexpr int D_SG = D_SY + 2;             // s_new . g_new
+constexpr int D_YG = D_SY + 3;             // y_new . g_new
+constexpr int D_GG = D_SY + 4;             // g_new . g_new
+constexpr int D_GINF = D_SY + 5;           // max |g_new|
+constexpr int D_G1 = D_SY + 6;             // sum |g_new|
+constexpr int D_SS = D_SY + 7;             // s_new . s_new
+
+// Compact-form coefficients from the ordered small matrices (one thread).
+__device__ void compact_coefficients(SolverState* st, const double* a_ord, const double* b_ord) {
+  const int h = st->count;
+  double u[RPCA_MEMMAX], w[RPCA_MEMMAX], p[RPCA_MEMMAX];
+  const double gamma = st->gamma;
+  // u = R^{-1} a  (R upper triangular, R_ij = s_i^T y_j for i <= j)
+  for (int i = h - 1; i >= 0; --i) {
+    double s = a_ord[i];
+    for (int j = i + 1; j < h; ++j) s -= st->SY[st->order[i]][st->order[j]] * u[j];
+    u[i] = s / st->SY[st->order[i]][st->order[i]];
+  }
+  // w = Dg u + gamma Y^T Y u - gamma b
+  for (int i = 0; i < h; ++i) {
+    double s = st->SY[st->order[i]][st->order[i]] * u[i] - gamma * b_ord[i];
+    for (int j = 0; j < h; ++j) s += gamma * st->YY[st->order[i]][st->order[j]] * u[j];
+    w[i] = s;
+  }
+  // p = R^{-T} w  (forward substitution with R^T lower triangular)
+  for (int i = 0; i < h; ++i) {
+    double s = w[i];
+    for (int j = 0; j < i; ++j) s -= st->SY[st->order[j]][st->order[i]] * p[j];
+    p[i] = s / st->SY[st->order[i]][st->order[i]];
+  }
+  for (int i = 0; i < RPCA_MEMMAX; ++i) {
+    st->coef_s[i] = 0.0;
+    st->coef_y[i] = 0.0;
+  }
+  for (int i = 0; i < h; ++i) {
+    st->coef_s[st->order[i]] = p[i];
+    st->coef_y[st->order[i]] = -gamma * u[i];
+  }
+}
+
+__device__ void update_small_math(SolverState* st, const double* D) {
+  const int cnt = st->count;
+  const double sy = D[D_SY], yy = D[D_YY], ss = D[D_SS];
+  st->iter += 1;
+  st->gnorm_inf = D[D_GINF];
+  st->gnorm1 = D[D_G1];
+  st->gg = D[D_GG];
+  double a_ord[RPCA_MEMMAX], b_ord[RPCA_MEMMAX];
+  for (int i = 0; i < cnt; ++i) {
+    a_ord[i] = D[4 * i + 0];
+    b_ord[i] = D[4 * i + 1];
+  }
+  const bool keep = sy > 1e-10 * sqrt(ss * yy) && isfinite(sy) && isfinite(yy);
+  if (keep) {
+    const int sn = st->spare;
+    for (int i = 0; i < cnt; ++i) {
+      const int so = st->order[i];
+      st->SY[so][sn] = D[4 * i + 2];
+      st->YY[so][sn] = D[4 * i + 3];
+      st->YY[sn][so] = D[4 * i + 3];
+    }
+    st->SY[sn][sn] = sy;
+    st->YY[sn][sn] = yy;
+    int h = cnt;
+    int next_spare;
+    if (h < st->mem) {
+      st->order[h] = sn;
+      a_ord[h] = D[D_SG];
+      b_ord[h] = D[D_YG];
+      h += 1;
+      next_spare = h;
+    } else {
+      next_spare = st->order[0];
+      for (int i = 0; i + 1 < h; ++i) {
+        st->order[i] = st->order[i + 1];
+        a_ord[i] = a_ord[i + 1];
+        b_ord[i] = b_ord[i + 1];
+      }
+      st->order[h - 1] = sn;
+      a_ord[h - 1] = D[D_SG];
+      b_ord[h - 1] = D[D_YG];
+    }
+    st->count = h;
+    st->spare = next_spare;
+    st->newest = sn;
+    st->gamma = sy / yy;
+  }
+  if (st->count > 0) compact_coefficients(st, a_ord, b_ord);
+  // stopping tests
+  const double f = st->f;
+  for (int i = 0; i < 7; ++i) st->fhist[i] = st->fhist[i + 1];
+  st->fhist[7] = f;
+  if (f < st->best_f) st->best_f = f;
+  int stop = STOP_NONE;
+  if (!isfinite(f) || !isfinite(D[D_GG])) stop = STOP_NONFINITE;
+  else if (D[D_GINF] <= st->gtol * fmax(1.0, fabs(f))) stop = STOP_GTOL;
+  else if (st->iter >= 5 && (st->fhist[2] - f) <= st->ftol * fmax(1.0, fabs(f))) stop = STOP_FTOL;
+  else if (st->iter >= st->max_iter) stop = STOP_MAXITER;
+  st->stop = stop;
+  st->phase = (stop == STOP_NONE) ? PH_DIRECTION : PH_DONE;
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
+  SolverState* st = a.st;
+  if (st->phase != PH_UPDATE) return;
+  constexpr int NV = 4 * RPCA_MEMMAX + 8;
+  const int cur = st->cur;
+  const int64_t n4 = a.N >> 2;
+  const f4* gn = reinterpret_cast<const f4*>(a.g[cur]);
+  const f4* go = reinterpret_cast<const f4*>(a.g[1 - cur]);
+  const f4* dd = reinterpret_cast<const f4*>(a.d);
+  const float alpha = (float)st->alpha;
+  const int cnt = st->count;
+  int slot[MEM];
+#pragma unroll
+  for (int i = 0; i < MEM; ++i) slot[i] = (i < cnt) ? st->order[i] : 0;
+  f4* Ssp = reinterpret_cast<f4*>(a.S + (int64_t)st->spare * a.N);
+  f4* Ysp = reinterpret_cast<f4*>(a.Y + (int64_t)st->spare * a.N);
+  double acc[NV];
+  bool is_max[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    acc[v] = 0.0;
+    is_max[v] = (v == D_GINF);
+  }
+  const int64_t stride = (int64_t)gridDim.x * THREADS;
+  for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
+    const f4 g1 = gn[e];
+    const f4 y = g1 - go[e];
+    const f4 s = alpha * dd[e];
+    Ssp[e] = s;
+    Ysp[e] = y;
+#pragma unroll
+    for (int i = 0; i < MEM; ++i) {
+      if (i < cnt) {
+        const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
+        const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
+        acc[4 * i + 0] += dot4(Si, g1);
+        acc[4 * i + 1] += dot4(Yi, g1);
+        acc[4 * i + 2] += dot4(Si, y);
+        acc[4 * i + 3] += dot4(Yi, y);
+      }
+    }
+    acc[D_SY] += dot4(s, y);
+    acc[D_YY] += dot4(y, y);
+    acc[D_SG] += dot4(s, g1);
+    acc[D_YG] += dot4(y, g1);
+    acc[D_GG] += dot4(g1, g1);
+    acc[D_SS] += dot4(s, s);
+    const double m4 = fmax(fmax(fabs((double)g1[0]), fabs((double)g1[1])),
+                           fmax(fabs((double)g1[2]), fabs((double)g1[3])));
+    acc[D_GINF] = fmax(acc[D_GINF], m4);
+    acc[D_G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
+  }
+  __shared__ double D[NV];
+  if (!reduce_partials<NV>(acc, is_max, a.part, a.counter, D)) return;
+  if (threadIdx.x == 0) update_small_math(st, D);
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
+  SolverState* st = a.st;
+  if (st->phase != PH_DIRECTION) return;
+  const int cur = st->cur;
+  const int64_t n4 = a.N >> 2;
+  const f4* g = reinterpret_cast<const f4*>(a.g[cur]);
+  f4* d = reinterpret_cast<f4*>(a.d);
+  const int cnt = st->count;
+  const float gamma = cnt > 0 ? (float)st->gamma : 1.0f;
+  int slot[MEM];
+  float cs[MEM], cy[MEM];
+#pragma unroll
+  for (int i = 0; i < MEM; ++i) {
+    slot[i] = (i < cnt) ? st->order[i] : 0;
+    cs[i] = (i < cnt) ? (float)st->coef_s[slot[i]] : 0.f;
+    cy[i] = (i < cnt) ? (float)st->coef_y[slot[i]] : 0.f;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  const bool is_max[3] = {false, false, false};
+  const int64_t stride = (int64_t)gridDim.x * THREADS;
+  for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
+    const f4 gv = g[e];
+    f4 h = gamma * gv;
+#pragma unroll
+    for (int i = 0; i < MEM; ++i) {
+      if (i < cnt) {
+        const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
+        const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
+        h += cs[i] * Si + cy[i] * Yi;
+      }
+    }
+    const f4 dv = -h;
+    d[e] = dv;
+    acc[0] += dot4(gv, dv);
+    acc[1] += dot4(dv, dv);
+    acc[2] += fabs((double)gv[0]) + fabs((double)gv[1]) + fabs((double)gv[2]) + fabs((double)gv[3]);
+  }
+  __shared__ double D[3];
+  if (!reduce_partials<3>(acc, is_max, a.part, a.counter, D)) return;
+  if (threadIdx.x == 0) {
+    const double gd = D[0];
+    st->dd = D[1];
+    if (!(gd < 0.0) || !isfinite(gd)) {
+      if (cnt > 0) {
+        // not a descent direction: drop the memory, steepest descent next slot
+        st->count = 0;
+        st->spare = 0;
+        st->newest = -1;
+      } else {
+        st->stop = isfinite(gd) ? STOP_GTOL : STOP_NONFINITE;
+        st->phase = PH_DONE;
+      }
+      return;
+    }
+    st->dphi0 = gd;
+    st->alpha = st->first_iter ? fmin(1.0, 1.0 / D[2]) : 1.0;
+    st->first_iter = 0;
+    st->ls_stage = 0;
+    st->ls_trials = 0;
+    st->a_prev = 0.0;
+    st->f_prev = st->f;
+    st->d_prev = gd;
+    st->phase = PH_TRIAL;
+  }
+}
+
+}  // namespace
+
+namespace rpca {
+
+int lbfgs_blocks(int64_t N) {
+  int64_t b = (N / 4 + THREADS * 4 - 1) / (THREADS * 4);
+  if (b < 1) b = 1;
+  if (b > 512) b = 512;
+  return (int)b;
+}
+
+#define RPCA_MEM_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
+hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream) {
+  const dim3 grid(lbfgs_blocks(a.N));
+  switch (mem) {
+#define CASE(M)                                                                        \
+  case M:                                                                              \
+    hipLaunchKernelGGL((k_lbfgs_update<M>), grid, dim3(THREADS), 0, stream, a);       \
+    break;
+    RPCA_MEM_CASES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream) {
+  const dim3 grid(lbfgs_blocks(a.N));
+  switch (mem) {
+#define CASE(M)                                                                        \
+  case M:                                                                              \
+    hipLaunchKernelGGL((k_lbfgs_direction<M>), grid, dim3(THREADS), 0, stream, a);    \
+    break;
+    RPCA_MEM_CASES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rpca

@@ -1,0 +1,165 @@
+// Internal declarations shared by the HIP translation units of librpca.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rpca.h"
+
+#define RPCA_MEMMAX 16      // ring slots for (s, y): up to 15 pairs plus one spare
+#define RPCA_NSCAL 8        // scalar partial slots per workgroup of a sweep
+
+// Control phases of the device-resident L-BFGS state machine.  Every kernel of
+// a solver slot reads `phase` first and does nothing unless the phase is its own.
+enum {
+  PH_TRIAL = 0,     // evaluate f, grad at x + alpha d (line-search trial)
+  PH_UPDATE = 1,    // trial accepted: store the (s, y) pair, form the compact matrices
+  PH_DIRECTION = 2, // form d = -H g
+  PH_DONE = 3
+};
+
+// Reasons the device loop stops (state.stop).
+enum {
+  STOP_NONE = 0,
+  STOP_GTOL = 1,
+  STOP_FTOL = 2,
+  STOP_MAXITER = 3,
+  STOP_LINESEARCH = 4,
+  STOP_NONFINITE = 5
+};
+
+// Device-resident solver state.  One instance per context (in device memory);
+// the host initialises it and reads it back between batches of trials.
+struct SolverState {
+  int phase;
+  int cur;              // which x/g buffer holds the current iterate
+  int stop;
+  int iter;             // accepted iterations
+  int evals;            // objective+gradient evaluations
+  int max_iter;
+  int mem;              // pairs to keep
+  int count;            // pairs stored
+  int newest;           // ring slot of the newest pair (-1 if none)
+  int spare;            // ring slot written by the next update
+  int order[RPCA_MEMMAX];   // ring slots from oldest to newest
+  int ls_stage;         // 0 = bracketing, 1 = zoom
+  int ls_trials;        // trials in the current search
+  int restarted;        // memory already reset once in this search
+  int first_iter;
+  int mode_bf16;        // products in BF16 for the current phase
+  int pad0;
+  double c1, c2, gtol, ftol;
+  double eps_f;         // relative rounding level of f for the approximate-Wolfe test
+  double f;             // objective at the current iterate
+  double dphi0;         // g^T d at the current iterate
+  double gnorm_inf, gnorm1, gg;
+  double alpha;         // step of the pending trial
+  double a_prev, f_prev, d_prev;
+  double a_lo, f_lo, d_lo, a_hi, f_hi, d_hi;
+  double f_t, dphi_t;   // last trial
+  double dd;            // d^T d
+  double gamma;
+  double SY[RPCA_MEMMAX][RPCA_MEMMAX];  // s_i^T y_j by slot
+  double YY[RPCA_MEMMAX][RPCA_MEMMAX];  // y_i^T y_j by slot
+  double coef_s[RPCA_MEMMAX];           // d = -(gamma g + sum coef_s[slot] s_slot + sum coef_y[slot] y_slot)
+  double coef_y[RPCA_MEMMAX];
+  double fhist[8];
+  double best_f;
+};
+
+// Arguments of the fused objective/gradient sweep.
+struct SweepArgs {
+  const float* X;
+  const uint32_t* mask;   // column-major bitmask, word (j*mw + i/32), or null
+  int64_t m, n;
+  int32_t k, mw;
+  float lam_s, lam_l;
+  // base point: U[cur], V[cur]; trial point = base + alpha * d
+  const float* U[2];
+  const float* V[2];
+  const float* dU;
+  const float* dV;
+  SolverState* st;        // null for a plain evaluation (alpha = 0, cur = 0)
+  float* Ut[2];           // trial point written to Ut[1-cur] (solver) or nothing
+  float* Vt[2];
+  float* gU[2];           // gradient output for the evaluated point (index: out slot)
+  float* gupart;          // [chunks][m*k] partial G V when n spans several chunks
+  float* gvpart;          // [row_groups][n*k] partial G^T U
+  double* spart;          // [row_groups*chunks][RPCA_NSCAL] scalar partials
+  int32_t strips_per_wg;  // 16-row strips handled by one workgroup
+  int32_t chunk_w;        // columns per chunk (multiple of 16)
+  int32_t nchunks;
+  int32_t row_groups;
+};
+
+// Arguments of the finishing reduction (gV, f, g^T d, line-search step).
+struct FinishArgs {
+  int64_t m, n;
+  int32_t k;
+  float lam_l;
+  const float* U[2];      // point that was evaluated (index = out slot)
+  const float* V[2];
+  const float* dU;
+  const float* dV;
+  SolverState* st;
+  const float* gupart;
+  const float* gvpart;
+  const double* spart;
+  float* gU[2];
+  float* gV[2];
+  double* level2;         // [segs][n*k] second-level partial sums of G^T U
+  double* fpart;          // [blocks] partials of this kernel
+  unsigned int* counter;  // last-block counter (zero between launches)
+  double* f_out;          // plain mode: receives f
+  double* aux_out;        // plain mode, optional: phi, ||U||^2, ||V||^2, ||G||_F^2
+  int32_t nchunks, row_groups, sweep_wgs;
+  int32_t segs, rows_per_seg;  // row groups are summed in segs segments of rows_per_seg
+  int32_t gv_blocks;      // set by the launcher
+};
+
+// Flat N-vector kernels of L-BFGS.  x, g, d, S, Y all hold N = (m+n)k floats,
+// the U part first (row-major) then the V part.
+struct LbfgsArgs {
+  int64_t N;
+  SolverState* st;
+  float* x[2];
+  float* g[2];
+  float* d;
+  float* S;               // [RPCA_MEMMAX][N]
+  float* Y;               // [RPCA_MEMMAX][N]
+  double* part;           // [blocks][RPCA_NDOT]
+  unsigned int* counter;
+};
+
+#define RPCA_NDOT (4 * RPCA_MEMMAX + 8)
+
+// Host-side launchers (defined in the .hip files).
+namespace rpca {
+int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wg,
+                     int* chunk_w, int* nchunks);
+hipError_t launch_objgrad(const SweepArgs& sa, const FinishArgs& fa, bool trial, bool bf16,
+                          hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream);
+hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream);
+hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream);
+hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream);
+int lbfgs_blocks(int64_t N);
+}  // namespace rpca
+
+// Context internals needed by the certificate / initialisation module.
+struct rpca_ctx;
+namespace rpca {
+struct CtxView {
+  int64_t m, n;
+  int k;
+  double lam_s, lam_l;
+  const uint32_t* mask;
+  int mw;
+  double* best_F;
+};
+CtxView ctx_view(rpca_ctx* c);
+int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V, double* f_dev,
+                    double* aux_dev, float* gU, float* gV, hipStream_t s);
+// Device workspace owned by the context, grown on demand; *fresh = 1 when newly allocated.
+void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh);
+}  // namespace rpca

@@ -1,0 +1,164 @@
+"""ctypes binding of librpca (the C ABI in include/rpca.h).
+
+Argument marshalling only: every step of the method runs inside the HIP
+library.  Device buffers are passed as integer addresses (``tensor.data_ptr()``)
+and streams as ``torch.cuda.current_stream().cuda_stream``; torch is only the
+allocator and stream provider.  Loading fails loudly when the library has not
+been built -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpca.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rpca.h")
+
+RPCA_OK, RPCA_ENOTCONV, RPCA_ELINESEARCH, RPCA_ENOTCERT = 0, 1, 2, 3
+RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP, RPCA_ENONFINITE = -1, -2, -3, -4
+RPCA_PREC_FP32, RPCA_PREC_BF16_POLISH, RPCA_PREC_BF16 = 0, 1, 2
+RPCA_INIT_GIVEN, RPCA_INIT_RSVD = 0, 1
+
+
+class rpca_opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("mem", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("init", ctypes.c_int32),
+        ("gtol", ctypes.c_double),
+        ("ftol", ctypes.c_double),
+        ("bf16_gtol", ctypes.c_double),
+        ("c1", ctypes.c_double),
+        ("c2", ctypes.c_double),
+        ("certify", ctypes.c_int32),
+        ("cert_tol", ctypes.c_double),
+        ("rsvd_oversample", ctypes.c_int32),
+        ("rsvd_power", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("slots_per_sync", ctypes.c_int32),
+    ]
+
+
+class rpca_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("evals", ctypes.c_int32),
+        ("iters_bf16", ctypes.c_int32),
+        ("f", ctypes.c_double),
+        ("gnorm_inf", ctypes.c_double),
+        ("rel_gap", ctypes.c_double),
+        ("certified", ctypes.c_int32),
+        ("cert_rounds", ctypes.c_int32),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+class rpca_cert(ctypes.Structure):
+    _fields_ = [
+        ("T1", ctypes.c_double), ("T2", ctypes.c_double), ("T3", ctypes.c_double),
+        ("T4", ctypes.c_double), ("E", ctypes.c_double), ("F", ctypes.c_double),
+        ("phi", ctypes.c_double), ("phi0", ctypes.c_double), ("F_bound", ctypes.c_double),
+        ("normL", ctypes.c_double), ("gap", ctypes.c_double), ("rel_gap", ctypes.c_double),
+        ("normM2", ctypes.c_double),
+        ("theta", ctypes.c_double * 32),
+        ("sigma", ctypes.c_double * 64),
+        ("r", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("block", ctypes.c_int32),
+        ("certified", ctypes.c_int32),
+    ]
+
+
+class rpca_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
+
+
+RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION = 0, 1, 2, 3
+
+_lib = None
+
+
+def lib():
+    """Load librpca.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1702_02241_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+        sig = {
+            "rpca_default_opts": (None, [ctypes.POINTER(rpca_opts)]),
+            "rpca_create": (I32, [I64, I64, I32, D, D, P, ctypes.POINTER(P)]),
+            "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
+            "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
+            "rpca_certificate": (I32, [P, P, P, P, ctypes.POINTER(rpca_cert), P]),
+            "rpca_init_rsvd": (I32, [P, P, P, I32, I32, U64, P, P, P]),
+            "rpca_destroy": (None, [P]),
+            "rpca_status_string": (ctypes.c_char_p, [I32]),
+            "rpca_profile_enable": (I32, [P, I32]),
+            "rpca_profile_read": (I32, [P, ctypes.POINTER(rpca_profile), I32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_opts():
+    o = rpca_opts()
+    lib().rpca_default_opts(ctypes.byref(o))
+    return o
+
+
+def rpca_create(m, n, k, lam_s, lam_l, mask=None):
+    """mask: None or a host numpy uint8 array (m x n, Fortran order or any order;
+    it is converted to column-major bytes).  Returns (status, ctx)."""
+    ctx = ctypes.c_void_p()
+    mptr = None
+    keep = None
+    if mask is not None:
+        import numpy as np
+        keep = np.asfortranarray(np.asarray(mask) != 0, dtype=np.uint8)
+        mptr = keep.ctypes.data
+    rc = lib().rpca_create(m, n, k, lam_s, lam_l, mptr, ctypes.byref(ctx))
+    return rc, ctx
+
+
+def rpca_objgrad(ctx, X, U, V, f, gU, gV, stream=0):
+    return lib().rpca_objgrad(ctx, X, U, V, f, gU, gV, stream)
+
+
+def rpca_solve(ctx, X, U, V, opts=None, stream=0):
+    info = rpca_info()
+    rc = lib().rpca_solve(ctx, X, U, V, ctypes.byref(opts) if opts is not None else None,
+                          ctypes.byref(info), stream)
+    return rc, info
+
+
+def rpca_certificate(ctx, X, U, V, stream=0):
+    cert = rpca_cert()
+    rc = lib().rpca_certificate(ctx, X, U, V, ctypes.byref(cert), stream)
+    return rc, cert
+
+
+def rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream=0):
+    return lib().rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream)
+
+
+def rpca_destroy(ctx):
+    lib().rpca_destroy(ctx)
+
+
+def rpca_status_string(status):
+    return lib().rpca_status_string(status).decode()
+
+
+def rpca_profile_enable(ctx, on):
+    return lib().rpca_profile_enable(ctx, 1 if on else 0)
+
+
+def rpca_profile_read(ctx, reset=False):
+    prof = rpca_profile()
+    rc = lib().rpca_profile_read(ctx, ctypes.byref(prof), 1 if reset else 0)
+    return rc, prof

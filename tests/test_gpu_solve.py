@@ -1,0 +1,131 @@
+"""GPU solve, certificate and rSVD start against the FP64 oracle.
+
+Bars: the FP32 solve reaches |f_oracle(U_gpu, V_gpu) - f*| / f* <= 1e-5 with
+f* from the oracle's converged L-BFGS; L = U V^T is compared through U V^T
+(factors are unique only up to an orthogonal Q, Theorem 1); certificate
+terms are compared with the oracle's exact certificate at the same factors.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import certificate as ce
+from oracle import lbfgs as lb
+from oracle import objective as ob
+from oracle import rsvd as rs
+from paper_1702_02241_amd import synth
+from paper_1702_02241_amd import torch_api as T
+
+from gpu_common import device, f32, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = synth.gaussian_rpca()  # 256 x 200, rank 5, 5% outliers, k = 10
+    Om = synth.gaussian_matrix(p.n, p.k + 10, 11)
+    U0, V0 = rs.rsvd_factors(p.X, p.k, Om)
+    res = lb.lbfgs(ob.make_fg(p.X, p.lam_s, p.lam_l, p.k), ob.pack(U0, V0))
+    Us, Vs = ob.unpack(res["x"], p.m, p.n, p.k)
+    return p, U0, V0, Om, res["f"], Us, Vs
+
+
+def test_solve_small_matches_oracle(small):
+    p, U0, V0, Om, fstar, Us, Vs = small
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    U, V = T.to_device_factor(U0, dev), T.to_device_factor(V0, dev)
+    rc, info = ctx.solve(Xcm, U, V, gtol=1e-6, certify=1)
+    torch.cuda.synchronize()
+    Ug, Vg = U.cpu().numpy().astype(np.float64), V.cpu().numpy().astype(np.float64)
+    f_at = ob.objective(Ug, Vg, p.X, p.lam_s, p.lam_l)
+    ef = abs(f_at - fstar) / fstar
+    eL = rel(Ug @ Vg.T, Us @ Vs.T)
+    print(f"[solve small] rc={rc} iters={info.iters} evals={info.evals} f_gpu={info.f:.10g} "
+          f"f_oracle(U_gpu)={f_at:.12g} f*={fstar:.12g} rel={ef:.2e} L rel={eL:.2e} "
+          f"rel_gap={info.rel_gap:.2e} certified={info.certified} t={info.seconds:.3f}s")
+    assert rc >= 0
+    assert ef <= 1e-5
+    assert eL <= 1e-3
+    assert info.certified == 1
+
+
+def test_certificate_matches_oracle_exact(small):
+    p, U0, V0, Om, fstar, Us, Vs = small
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    for label, (U, V) in (("optimum", (Us, Vs)), ("rsvd-start", (U0, V0))):
+        c = ctx.certificate(Xcm, T.to_device_factor(U, dev), T.to_device_factor(V, dev))
+        o = ce.certificate(f32(U), f32(V), f32(p.X), p.lam_s, p.lam_l, tau=1e-6)
+        print(f"[cert {label}] gpu T=({c.T1:.3e},{c.T2:.3e},{c.T3:.3e},{c.T4:.3e}) r={c.r} "
+              f"E={c.E:.3e} gap={c.gap:.3e} rel_gap={c.rel_gap:.3e} it={c.power_iters} | oracle "
+              f"T=({o['T1']:.3e},{o['T2']:.3e},{o['T3']:.3e},{o['T4']:.3e}) r={o['r']} E={o['E']:.3e} "
+              f"rel_gap={o['rel_gap']:.3e}")
+        assert c.r == o["r"]
+        assert abs(c.F - o["F"]) <= 1e-5 * o["F"]
+        assert abs(c.phi0 - o["phi0"]) <= 1e-5 * o["phi0"]
+        for key in ("T1", "T2", "T3"):
+            a, b = getattr(c, key), o[key]
+            assert abs(a - b) <= 1e-3 * max(b, 1.0) + 1e-5, key
+        # T4: exact when every singular value above 1 fits in the block, otherwise the
+        # tail term makes it an over-estimate (never certifies a worse point)
+        n_above = int(np.sum(o["sv_perp"] > 1.0))
+        if n_above < c.block:
+            assert abs(c.T4 - o["T4"]) <= 1e-3 * max(o["T4"], 1.0) + 1e-5
+        else:
+            assert c.T4 >= o["T4"] * (1 - 1e-3)
+        # the leading Ritz value, and every one that matters for T4 (near or above 1),
+        # matches the exact singular values of the projected gradient
+        sv = o["sv_perp"]
+        for i in range(min(c.block, sv.size)):
+            if i == 0 or sv[i] > 0.98:
+                assert abs(c.theta[i] - sv[i]) <= 1e-3 * sv[i] + 1e-5, (i, c.theta[i], sv[i])
+        assert abs(c.normM2 - o["normM2"]) <= 1e-4 * max(o["normM2"], 1.0)
+        if label == "optimum":
+            assert c.rel_gap <= 1e-3
+        else:
+            assert abs(c.E - o["E"]) <= 1e-3 * o["E"]
+
+
+def test_certificate_at_zero_matches_spectral_formula():
+    p = synth.gaussian_rpca(m=300, n=120, r=3, k=6, seed=41, lam_l=0.05)
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    Z1, Z2 = torch.zeros(p.m, p.k, device=dev), torch.zeros(p.n, p.k, device=dev)
+    c = ctx.certificate(Xcm, Z1, Z2)
+    o = ce.certificate(np.zeros((p.m, p.k)), np.zeros((p.n, p.k)), f32(p.X), p.lam_s, p.lam_l)
+    b = c.block
+    th = np.array(list(c.theta)[:b])
+    top = o["sv_perp"][:b]
+    print(f"[cert zero] block={b} it={c.power_iters} gpu theta {th[:6]} oracle sv {top[:6]} "
+          f"T4 gpu {c.T4:.6e} oracle {o['T4']:.6e}")
+    assert c.r == 0
+    # Ritz values are lower bounds of the singular values and the leading ones converge
+    assert np.all(th <= top * (1 + 1e-6) + 1e-9)
+    assert np.allclose(th[: max(1, b // 2)], top[: max(1, b // 2)], rtol=1e-3)
+    n_above = int(np.sum(o["sv_perp"] > 1.0))
+    if n_above < b:
+        assert abs(c.T4 - o["T4"]) <= 1e-3 * max(o["T4"], 1.0)
+    else:
+        assert c.T4 >= o["T4"] * (1 - 1e-3)
+
+
+def test_rsvd_matches_oracle_with_same_sketch():
+    p = synth.gaussian_rpca(m=700, n=180, r=5, k=8, seed=51)
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    Om = synth.gaussian_matrix(p.n, p.k + 10, 52)
+    U, V = ctx.init_rsvd(Xcm, torch.from_numpy(Om.astype(np.float32)).to(dev), power_steps=2)
+    torch.cuda.synchronize()
+    Uo, Vo = rs.rsvd_factors(f32(p.X), p.k, Om, q=2)
+    Lg = U.cpu().numpy().astype(np.float64) @ V.cpu().numpy().astype(np.float64).T
+    e = rel(Lg, Uo @ Vo.T)
+    bal = rel(U.cpu().numpy().T @ U.cpu().numpy(), V.cpu().numpy().T @ V.cpu().numpy())
+    print(f"[rsvd] U0V0^T rel {e:.2e} balance {bal:.2e}")
+    assert e <= 1e-4
+    assert bal <= 1e-4
