@@ -132,6 +132,12 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
 int rpca_objgrad(rpca_ctx* ctx, const float* X, const float* U, const float* V,
                  double* f, float* gU, float* gV, void* stream);
 
+/* rpca_objgrad with a choice of product precision: RPCA_PREC_FP32 (same as
+ * rpca_objgrad) or RPCA_PREC_BF16 (U, V and G rounded to bf16 for the MFMA
+ * products, FP32 accumulation and residual, FP64 sums). */
+int rpca_objgrad_ex(rpca_ctx* ctx, const float* X, const float* U, const float* V,
+                    double* f, float* gU, float* gV, int32_t precision, void* stream);
+
 /* Minimise f from (U, V) with L-BFGS + strong-Wolfe line search (Sec. 5.1).
  * X: device.  U, V: device, in = start (ignored with RPCA_INIT_RSVD), out =
  * solution.  opts: host, NULL = defaults.  info: host, may be NULL.

@@ -19,11 +19,10 @@ struct rpca_ctx {
   uint32_t* mask = nullptr;  // device bitmask or null
   int mw = 0;
   // sweep configuration
-  int row_groups = 0, spw = 0, chunk_w = 0, nchunks = 0, sweep_wgs = 0, segs = 0, rps = 0;
+  int row_groups = 0, spw = 0, chunk_w = 0, nchunks = 0, sweep_wgs = 0;
   float* gvpart = nullptr;
   float* gupart = nullptr;
   double* spart = nullptr;
-  double* level2 = nullptr;
   double* fpart = nullptr;
   unsigned int* counters = nullptr;  // [0] finish, [1] update, [2] direction, [3..] spare
   // solver workspace
@@ -86,10 +85,11 @@ SweepArgs make_sweep_args(const rpca_ctx* c, const float* X) {
   a.mw = c->mw;
   a.lam_s = (float)c->lam_s;
   a.lam_l = (float)c->lam_l;
+  a.xvec = (c->m % 4 == 0) && (((uintptr_t)X & 15u) == 0);
   a.gupart = c->gupart;
   a.gvpart = c->gvpart;
   a.spart = c->spart;
-  a.strips_per_wg = c->spw;
+  a.strips_per_wave = c->spw;
   a.chunk_w = c->chunk_w;
   a.nchunks = c->nchunks;
   a.row_groups = c->row_groups;
@@ -106,14 +106,11 @@ FinishArgs make_finish_args(const rpca_ctx* c) {
   f.gupart = c->gupart;
   f.gvpart = c->gvpart;
   f.spart = c->spart;
-  f.level2 = c->level2;
   f.fpart = c->fpart;
   f.counter = c->counters + 0;
   f.nchunks = c->nchunks;
   f.row_groups = c->row_groups;
   f.sweep_wgs = c->sweep_wgs;
-  f.segs = c->segs;
-  f.rows_per_seg = c->rps;
   return f;
 }
 
@@ -262,7 +259,6 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->gvpart);
   dfree(c->gupart);
   dfree(c->spart);
-  dfree(c->level2);
   dfree(c->fpart);
   dfree(c->counters);
   dfree(c->x[0]);
@@ -320,18 +316,10 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, con
     }
   }
   c->sweep_wgs = rpca::sweep_blocks_for(m, n, k, &c->row_groups, &c->spw, &c->chunk_w, &c->nchunks);
-  c->rps = 32;
-  c->segs = (c->row_groups + c->rps - 1) / c->rps;
   TRY(dalloc(&c->gvpart, (size_t)c->row_groups * n * k));
   if (c->nchunks > 1) TRY(dalloc(&c->gupart, (size_t)c->nchunks * m * k));
   TRY(dalloc(&c->spart, (size_t)c->sweep_wgs * RPCA_NSCAL));
-  TRY(dalloc(&c->level2, (size_t)c->segs * n * k));
-  {
-    // finishing-reduction grid: ceil(nk/256) + (multi-chunk: <= 1024) blocks per segment
-    const int64_t gvb = (n * k + 255) / 256;
-    const int64_t gub = c->nchunks > 1 ? 1024 : 0;
-    TRY(dalloc(&c->fpart, (size_t)((gvb + gub) * c->segs + 64)));
-  }
+  TRY(dalloc(&c->fpart, (size_t)rpca::finish_blocks(m, n, k, c->nchunks, nullptr) * 3 + 16));
   TRY(dalloc(&c->counters, 16));
   if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess) {
     rpca_destroy(c);
@@ -346,7 +334,7 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, con
   TRY(dalloc(&c->d, c->N));
   TRY(dalloc(&c->S, (size_t)RPCA_MEMMAX * c->N));
   TRY(dalloc(&c->Y, (size_t)RPCA_MEMMAX * c->N));
-  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 512));
+  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 1024));
   TRY(dalloc(&c->st, 1));
   TRY(dalloc(&c->dscratch, 64));
   void* hp = nullptr;
@@ -375,7 +363,13 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, con
 
 int rpca_objgrad(rpca_ctx* c, const float* X, const float* U, const float* V, double* f, float* gU,
                  float* gV, void* stream) {
+  return rpca_objgrad_ex(c, X, U, V, f, gU, gV, RPCA_PREC_FP32, stream);
+}
+
+int rpca_objgrad_ex(rpca_ctx* c, const float* X, const float* U, const float* V, double* f,
+                    float* gU, float* gV, int32_t precision, void* stream) {
   if (!c || !X || !U || !V || !f || !gU || !gV) return RPCA_EINVAL;
+  if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16) return RPCA_EINVAL;
   SweepArgs sa = make_sweep_args(c, X);
   FinishArgs fa = make_finish_args(c);
   sa.U[0] = sa.U[1] = U;
@@ -386,7 +380,7 @@ int rpca_objgrad(rpca_ctx* c, const float* X, const float* U, const float* V, do
   fa.gU[0] = fa.gU[1] = gU;
   fa.gV[0] = fa.gV[1] = gV;
   fa.f_out = f;
-  HIPCHK(objgrad_launch(c, sa, fa, false, false, (hipStream_t)stream));
+  HIPCHK(objgrad_launch(c, sa, fa, false, precision == RPCA_PREC_BF16, (hipStream_t)stream));
   return RPCA_OK;
 }
 
@@ -465,6 +459,43 @@ static int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16,
 
 }  // namespace rpca
 
+namespace rpca {
+
+// Plain evaluation at the current iterate x[cur]: g[cur] and state.f (device).
+static int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s) {
+  const int64_t mk = c->m * c->k;
+  SweepArgs sa = make_sweep_args(c, X);
+  FinishArgs fa = make_finish_args(c);
+  sa.U[0] = sa.U[1] = c->x[cur];
+  sa.V[0] = sa.V[1] = c->x[cur] + mk;
+  sa.gU[0] = sa.gU[1] = c->g[cur];
+  fa.U[0] = fa.U[1] = c->x[cur];
+  fa.V[0] = fa.V[1] = c->x[cur] + mk;
+  fa.gU[0] = fa.gU[1] = c->g[cur];
+  fa.gV[0] = fa.gV[1] = c->g[cur] + mk;
+  fa.f_out = &c->st->f;
+  HIPCHK(objgrad_launch(c, sa, fa, false, bf16, s));
+  return RPCA_OK;
+}
+
+// Restart the device loop from the current iterate after a phase change:
+// keep the L-BFGS memory, clear the stop flag and the f history.
+static int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
+  SolverState* h = c->st_host;
+  HIPCHK(hipMemcpyAsync(h, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h->phase = PH_DIRECTION;
+  h->stop = STOP_NONE;
+  h->gtol = gtol;
+  h->ftol = ftol;
+  h->restarted = 0;
+  for (int i = 0; i < 8; ++i) h->fhist[i] = INFINITY;
+  HIPCHK(hipMemcpyAsync(c->st, h, sizeof(SolverState), hipMemcpyHostToDevice, s));
+  return RPCA_OK;
+}
+
+}  // namespace rpca
+
 extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts* opts,
                           rpca_info* info, void* stream) {
   if (!c || !X || !U || !V) return RPCA_EINVAL;
@@ -472,7 +503,8 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   if (opts) o = *opts;
   else rpca_default_opts(&o);
   if (o.mem < 1 || o.mem > RPCA_MEMMAX - 1 || o.max_iter < 0 || !(o.c1 > 0) || !(o.c2 > o.c1) ||
-      !(o.c2 < 1) || !(o.gtol >= 0) || !(o.ftol >= 0))
+      !(o.c2 < 1) || !(o.gtol >= 0) || !(o.ftol >= 0) || o.precision < 0 || o.precision > 2 ||
+      !(o.bf16_gtol >= 0) || !(o.cert_tol > 0))
     return RPCA_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
@@ -481,25 +513,21 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
     const int rc = rpca_init_rsvd(c, X, nullptr, o.rsvd_oversample, o.rsvd_power, o.seed, U, V, stream);
     if (rc != RPCA_OK) return rc;
   }
+  // precision phases: (bf16, gtol)
+  struct Phase {
+    bool bf16;
+    double gtol;
+  };
+  Phase phases[2];
+  int nph = 0;
+  if (o.precision == RPCA_PREC_FP32) phases[nph++] = {false, o.gtol};
+  else if (o.precision == RPCA_PREC_BF16) phases[nph++] = {true, o.gtol};
+  else {
+    phases[nph++] = {true, o.bf16_gtol};
+    phases[nph++] = {false, o.gtol};
+  }
   HIPCHK(hipMemcpyAsync(c->x[0], U, mk * 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(c->x[0] + mk, V, nk * 4, hipMemcpyDeviceToDevice, s));
-  // f and g at the start
-  {
-    SweepArgs sa = make_sweep_args(c, X);
-    FinishArgs fa = make_finish_args(c);
-    sa.U[0] = sa.U[1] = c->x[0];
-    sa.V[0] = sa.V[1] = c->x[0] + mk;
-    sa.gU[0] = sa.gU[1] = c->g[0];
-    fa.U[0] = fa.U[1] = c->x[0];
-    fa.V[0] = fa.V[1] = c->x[0] + mk;
-    fa.gU[0] = fa.gU[1] = c->g[0];
-    fa.gV[0] = fa.gV[1] = c->g[0] + mk;
-    fa.f_out = c->dscratch;
-    HIPCHK(objgrad_launch(c, sa, fa, false, false, s));
-  }
-  double f0 = 0.0;
-  HIPCHK(hipMemcpyAsync(&f0, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
   SolverState* h = c->st_host;
   memset(h, 0, sizeof(*h));
   h->phase = PH_DIRECTION;
@@ -510,42 +538,61 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   h->first_iter = 1;
   h->c1 = o.c1;
   h->c2 = o.c2;
-  h->gtol = o.gtol;
+  h->gtol = phases[0].gtol;
   h->ftol = o.ftol;
   h->eps_f = 1e-7;
-  h->f = f0;
-  h->best_f = f0;
   for (int i = 0; i < 8; ++i) h->fhist[i] = INFINITY;
+  h->best_f = INFINITY;
   h->gamma = 1.0;
   h->evals = 1;
   HIPCHK(hipMemcpyAsync(c->st, h, sizeof(SolverState), hipMemcpyHostToDevice, s));
-  int status = RPCA_OK;
-  int rc = rpca::run_lbfgs(c, X, &o, false, s);
-  if (rc != RPCA_OK) return rc;
-  const SolverState fin = *c->st_host;
-  const int cur = fin.cur;
-  HIPCHK(hipMemcpyAsync(U, c->x[cur], mk * 4, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(V, c->x[cur] + mk, nk * 4, hipMemcpyDeviceToDevice, s));
+  int rc = rpca::eval_current(c, X, 0, phases[0].bf16, s);
+  if (rc) return rc;
+  rc = rpca::run_lbfgs(c, X, &o, phases[0].bf16, s);
+  if (rc) return rc;
+  int iters_bf16 = phases[0].bf16 ? c->st_host->iter : 0;
+  bool final_bf16 = phases[0].bf16;
+  for (int ph = 1; ph < nph; ++ph) {
+    if (c->st_host->stop == STOP_NONFINITE || c->st_host->stop == STOP_MAXITER) break;
+    if ((rc = rpca::resume_state(c, phases[ph].gtol, o.ftol, s))) return rc;
+    if ((rc = rpca::eval_current(c, X, c->st_host->cur, phases[ph].bf16, s))) return rc;
+    if ((rc = rpca::run_lbfgs(c, X, &o, phases[ph].bf16, s))) return rc;
+    final_bf16 = phases[ph].bf16;
+  }
+  double rel_gap = NAN;
+  int certified = 0, rounds = 0;
+  double gtol = phases[nph - 1].gtol, ftol = o.ftol;
+  for (;;) {
+    const int cur = c->st_host->cur;
+    HIPCHK(hipMemcpyAsync(U, c->x[cur], mk * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(V, c->x[cur] + mk, nk * 4, hipMemcpyDeviceToDevice, s));
+    const int stop = c->st_host->stop;
+    if (!o.certify || stop == STOP_NONFINITE) break;
+    rpca_cert cert;
+    const int crc = rpca_certificate(c, X, U, V, &cert, stream);
+    if (crc < 0) return crc;
+    ++rounds;
+    rel_gap = cert.rel_gap;
+    certified = rel_gap <= o.cert_tol;
+    if (certified || stop == STOP_MAXITER || rounds >= 5) break;
+    // not certified yet: tighten the stopping tests and continue from here
+    gtol *= 0.1;
+    ftol *= 0.01;
+    if ((rc = rpca::resume_state(c, gtol, ftol, s))) return rc;
+    if ((rc = rpca::run_lbfgs(c, X, &o, final_bf16, s))) return rc;
+  }
   HIPCHK(hipStreamSynchronize(s));
+  const SolverState fin = *c->st_host;
+  int status;
   switch (fin.stop) {
-    case STOP_GTOL:
-    case STOP_FTOL: status = RPCA_OK; break;
     case STOP_MAXITER: status = RPCA_ENOTCONV; break;
     case STOP_LINESEARCH: status = RPCA_ELINESEARCH; break;
     case STOP_NONFINITE: status = RPCA_ENONFINITE; break;
     default: status = RPCA_OK;
   }
-  double rel_gap = NAN;
-  int certified = 0, rounds = 0;
-  if (o.certify && status >= 0) {
-    rpca_cert cert;
-    const int crc = rpca_certificate(c, X, U, V, &cert, stream);
-    if (crc < 0) return crc;
-    rounds = 1;
-    rel_gap = cert.rel_gap;
-    certified = rel_gap <= o.cert_tol;
+  if (o.certify && status != RPCA_ENONFINITE) {
     // the certificate is the judge: a search that stalled at the rounding level of
-    // the FP32 objective is a normal end when the point is certified
+    // the objective is a normal end when the point is certified
     if (certified) status = RPCA_OK;
     else if (status == RPCA_OK) status = RPCA_ENOTCERT;
   }
@@ -553,7 +600,7 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
     info->status = status;
     info->iters = fin.iter;
     info->evals = fin.evals;
-    info->iters_bf16 = 0;
+    info->iters_bf16 = iters_bf16;
     info->f = fin.f;
     info->gnorm_inf = fin.gnorm_inf;
     info->rel_gap = rel_gap;

@@ -39,25 +39,26 @@ __device__ __forceinline__ double dot4(f4 a, f4 b) {
   return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2] + (double)a[3] * b[3];
 }
 
-// Reduce NV per-thread values over the block, write them value-major to part[v*nb + block],
-// then let the last block sum them over blocks into out[] (shared).  Returns true in the
-// last block (after out[] is valid in every thread).
-template <int NV>
-__device__ bool reduce_partials(const double (&acc)[NV], const bool (&is_max)[NV], double* part,
-                                unsigned int* counter, double* out) {
+// Reduce NV per-thread values over the block (value IMAX, if in range, is a max,
+// the others sums), write them value-major to part[v*nb + block], then let the
+// last block combine them over blocks into out[] (shared).  Returns true in the
+// last block, after out[] is valid in every thread.  Fixed order throughout.
+template <int NV, int IMAX>
+__device__ bool reduce_partials(const double (&acc)[NV], double* part, unsigned int* counter,
+                                double* out) {
   __shared__ double sh[WAVES][NV];
   __shared__ int s_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nb = gridDim.x;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double r = is_max[v] ? wave_max(acc[v]) : wave_sum(acc[v]);
+    const double r = (v == IMAX) ? wave_max(acc[v]) : wave_sum(acc[v]);
     if (lane == 0) sh[wave][v] = r;
   }
   __syncthreads();
   for (int v = threadIdx.x; v < NV; v += THREADS) {
     double r = sh[0][v];
-    for (int w = 1; w < WAVES; ++w) r = is_max[v] ? fmax(r, sh[w][v]) : r + sh[w][v];
+    for (int w = 1; w < WAVES; ++w) r = (v == IMAX) ? fmax(r, sh[w][v]) : r + sh[w][v];
     part[(int64_t)v * nb + blockIdx.x] = r;
   }
   __threadfence();
@@ -69,35 +70,46 @@ __device__ bool reduce_partials(const double (&acc)[NV], const bool (&is_max)[NV
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = 0; v < NV; ++v) {
-    double r = is_max[v] ? 0.0 : 0.0;
-    for (int b = threadIdx.x; b < nb; b += THREADS) {
+  double r[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) r[v] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += THREADS) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
       const double x = part[(int64_t)v * nb + b];
-      r = is_max[v] ? fmax(r, x) : r + x;
+      r[v] = (v == IMAX) ? fmax(r[v], x) : r[v] + x;
     }
-    r = is_max[v] ? wave_max(r) : wave_sum(r);
-    if (lane == 0) sh[wave][v] = r;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double q = (v == IMAX) ? wave_max(r[v]) : wave_sum(r[v]);
+    if (lane == 0) sh[wave][v] = q;
   }
   __syncthreads();
   for (int v = threadIdx.x; v < NV; v += THREADS) {
-    double r = sh[0][v];
-    for (int w = 1; w < WAVES; ++w) r = is_max[v] ? fmax(r, sh[w][v]) : r + sh[w][v];
-    out[v] = r;
+    double q = sh[0][v];
+    for (int w = 1; w < WAVES; ++w) q = (v == IMAX) ? fmax(q, sh[w][v]) : q + sh[w][v];
+    out[v] = q;
   }
   __syncthreads();
   if (threadIdx.x == 0) *counter = 0u;
   return true;
 }
 
-// Indices into the dot vector of the update pass.
-constexpr int D_SY = 4 * RPCA_MEMMAX + 0;  // s_new . y_new
-constexpr int D_YY = D_SY + 1;             // y_new . y_new
-constexpr int D_SG = D_SY + 2;             // s_new . g_new
-constexpr int D_YG = D_SY + 3;             // y_new . g_new
-constexpr int D_GG = D_SY + 4;             // g_new . g_new
-constexpr int D_GINF = D_SY + 5;           // max |g_new|
-constexpr int D_G1 = D_SY + 6;             // sum |g_new|
-constexpr int D_SS = D_SY + 7;             // s_new . s_new
+// Layout of the dot vector of the update pass: 4 per stored pair (s_i.g, y_i.g,
+// s_i.y, y_i.y), then the new pair's scalars.
+template <int MEM>
+struct DotIdx {
+  static constexpr int SY = 4 * MEM + 0;  // s_new . y_new
+  static constexpr int YY = SY + 1;       // y_new . y_new
+  static constexpr int SG = SY + 2;       // s_new . g_new
+  static constexpr int YG = SY + 3;       // y_new . g_new
+  static constexpr int GG = SY + 4;       // g_new . g_new
+  static constexpr int GINF = SY + 5;     // max |g_new|
+  static constexpr int G1 = SY + 6;       // sum |g_new|
+  static constexpr int SS = SY + 7;       // s_new . s_new
+  static constexpr int NV = SY + 8;
+};
 
 // Compact-form coefficients from the ordered small matrices (one thread).
 __device__ void compact_coefficients(SolverState* st, const double* a_ord, const double* b_ord) {
@@ -132,13 +144,15 @@ __device__ void compact_coefficients(SolverState* st, const double* a_ord, const
   }
 }
 
+template <int MEM>
 __device__ void update_small_math(SolverState* st, const double* D) {
+  using I = DotIdx<MEM>;
   const int cnt = st->count;
-  const double sy = D[D_SY], yy = D[D_YY], ss = D[D_SS];
+  const double sy = D[I::SY], yy = D[I::YY], ss = D[I::SS];
   st->iter += 1;
-  st->gnorm_inf = D[D_GINF];
-  st->gnorm1 = D[D_G1];
-  st->gg = D[D_GG];
+  st->gnorm_inf = D[I::GINF];
+  st->gnorm1 = D[I::G1];
+  st->gg = D[I::GG];
   double a_ord[RPCA_MEMMAX], b_ord[RPCA_MEMMAX];
   for (int i = 0; i < cnt; ++i) {
     a_ord[i] = D[4 * i + 0];
@@ -159,8 +173,8 @@ __device__ void update_small_math(SolverState* st, const double* D) {
     int next_spare;
     if (h < st->mem) {
       st->order[h] = sn;
-      a_ord[h] = D[D_SG];
-      b_ord[h] = D[D_YG];
+      a_ord[h] = D[I::SG];
+      b_ord[h] = D[I::YG];
       h += 1;
       next_spare = h;
     } else {
@@ -171,8 +185,8 @@ __device__ void update_small_math(SolverState* st, const double* D) {
         b_ord[i] = b_ord[i + 1];
       }
       st->order[h - 1] = sn;
-      a_ord[h - 1] = D[D_SG];
-      b_ord[h - 1] = D[D_YG];
+      a_ord[h - 1] = D[I::SG];
+      b_ord[h - 1] = D[I::YG];
     }
     st->count = h;
     st->spare = next_spare;
@@ -186,8 +200,8 @@ __device__ void update_small_math(SolverState* st, const double* D) {
   st->fhist[7] = f;
   if (f < st->best_f) st->best_f = f;
   int stop = STOP_NONE;
-  if (!isfinite(f) || !isfinite(D[D_GG])) stop = STOP_NONFINITE;
-  else if (D[D_GINF] <= st->gtol * fmax(1.0, fabs(f))) stop = STOP_GTOL;
+  if (!isfinite(f) || !isfinite(D[I::GG])) stop = STOP_NONFINITE;
+  else if (D[I::GINF] <= st->gtol * fmax(1.0, fabs(f))) stop = STOP_GTOL;
   else if (st->iter >= 5 && (st->fhist[2] - f) <= st->ftol * fmax(1.0, fabs(f))) stop = STOP_FTOL;
   else if (st->iter >= st->max_iter) stop = STOP_MAXITER;
   st->stop = stop;
@@ -196,9 +210,10 @@ __device__ void update_small_math(SolverState* st, const double* D) {
 
 template <int MEM>
 __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
+  using I = DotIdx<MEM>;
+  constexpr int NV = I::NV;
   SolverState* st = a.st;
   if (st->phase != PH_UPDATE) return;
-  constexpr int NV = 4 * RPCA_MEMMAX + 8;
   const int cur = st->cur;
   const int64_t n4 = a.N >> 2;
   const f4* gn = reinterpret_cast<const f4*>(a.g[cur]);
@@ -206,18 +221,19 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
   const f4* dd = reinterpret_cast<const f4*>(a.d);
   const float alpha = (float)st->alpha;
   const int cnt = st->count;
-  int slot[MEM];
+  const f4* Sp[MEM];
+  const f4* Yp[MEM];
 #pragma unroll
-  for (int i = 0; i < MEM; ++i) slot[i] = (i < cnt) ? st->order[i] : 0;
+  for (int i = 0; i < MEM; ++i) {
+    const int slot = (i < cnt) ? st->order[i] : 0;
+    Sp[i] = reinterpret_cast<const f4*>(a.S + (int64_t)slot * a.N);
+    Yp[i] = reinterpret_cast<const f4*>(a.Y + (int64_t)slot * a.N);
+  }
   f4* Ssp = reinterpret_cast<f4*>(a.S + (int64_t)st->spare * a.N);
   f4* Ysp = reinterpret_cast<f4*>(a.Y + (int64_t)st->spare * a.N);
   double acc[NV];
-  bool is_max[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    acc[v] = 0.0;
-    is_max[v] = (v == D_GINF);
-  }
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * THREADS;
   for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
     const f4 g1 = gn[e];
@@ -228,28 +244,28 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
       if (i < cnt) {
-        const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
-        const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
+        const f4 Si = Sp[i][e];
+        const f4 Yi = Yp[i][e];
         acc[4 * i + 0] += dot4(Si, g1);
         acc[4 * i + 1] += dot4(Yi, g1);
         acc[4 * i + 2] += dot4(Si, y);
         acc[4 * i + 3] += dot4(Yi, y);
       }
     }
-    acc[D_SY] += dot4(s, y);
-    acc[D_YY] += dot4(y, y);
-    acc[D_SG] += dot4(s, g1);
-    acc[D_YG] += dot4(y, g1);
-    acc[D_GG] += dot4(g1, g1);
-    acc[D_SS] += dot4(s, s);
+    acc[I::SY] += dot4(s, y);
+    acc[I::YY] += dot4(y, y);
+    acc[I::SG] += dot4(s, g1);
+    acc[I::YG] += dot4(y, g1);
+    acc[I::GG] += dot4(g1, g1);
+    acc[I::SS] += dot4(s, s);
     const double m4 = fmax(fmax(fabs((double)g1[0]), fabs((double)g1[1])),
                            fmax(fabs((double)g1[2]), fabs((double)g1[3])));
-    acc[D_GINF] = fmax(acc[D_GINF], m4);
-    acc[D_G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
+    acc[I::GINF] = fmax(acc[I::GINF], m4);
+    acc[I::G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
   }
   __shared__ double D[NV];
-  if (!reduce_partials<NV>(acc, is_max, a.part, a.counter, D)) return;
-  if (threadIdx.x == 0) update_small_math(st, D);
+  if (!reduce_partials<NV, I::GINF>(acc, a.part, a.counter, D)) return;
+  if (threadIdx.x == 0) update_small_math<MEM>(st, D);
 }
 
 template <int MEM>
@@ -271,7 +287,6 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     cy[i] = (i < cnt) ? (float)st->coef_y[slot[i]] : 0.f;
   }
   double acc[3] = {0.0, 0.0, 0.0};
-  const bool is_max[3] = {false, false, false};
   const int64_t stride = (int64_t)gridDim.x * THREADS;
   for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
     const f4 gv = g[e];
@@ -291,7 +306,7 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     acc[2] += fabs((double)gv[0]) + fabs((double)gv[1]) + fabs((double)gv[2]) + fabs((double)gv[3]);
   }
   __shared__ double D[3];
-  if (!reduce_partials<3>(acc, is_max, a.part, a.counter, D)) return;
+  if (!reduce_partials<3, -1>(acc, a.part, a.counter, D)) return;
   if (threadIdx.x == 0) {
     const double gd = D[0];
     st->dd = D[1];
@@ -324,9 +339,10 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
 namespace rpca {
 
 int lbfgs_blocks(int64_t N) {
-  int64_t b = (N / 4 + THREADS * 4 - 1) / (THREADS * 4);
+  // about one float4 per thread, at most 1024 blocks
+  int64_t b = (N / 4 + THREADS - 1) / THREADS;
   if (b < 1) b = 1;
-  if (b > 512) b = 512;
+  if (b > 1024) b = 1024;
   return (int)b;
 }
 

@@ -74,6 +74,7 @@ struct SweepArgs {
   int64_t m, n;
   int32_t k, mw;
   float lam_s, lam_l;
+  int32_t xvec;           // 1: X is 16-byte aligned and m % 4 == 0 (vector loads allowed)
   // base point: U[cur], V[cur]; trial point = base + alpha * d
   const float* U[2];
   const float* V[2];
@@ -84,12 +85,12 @@ struct SweepArgs {
   float* Vt[2];
   float* gU[2];           // gradient output for the evaluated point (index: out slot)
   float* gupart;          // [chunks][m*k] partial G V when n spans several chunks
-  float* gvpart;          // [row_groups][n*k] partial G^T U
+  float* gvpart;          // [row_groups][n*k] partial G^T U (one per workgroup row)
   double* spart;          // [row_groups*chunks][RPCA_NSCAL] scalar partials
-  int32_t strips_per_wg;  // 16-row strips handled by one workgroup
+  int32_t strips_per_wave;  // 16-row strips per wave (contiguous)
   int32_t chunk_w;        // columns per chunk (multiple of 16)
   int32_t nchunks;
-  int32_t row_groups;
+  int32_t row_groups;     // workgroups along the rows (grid.x)
 };
 
 // Arguments of the finishing reduction (gV, f, g^T d, line-search step).
@@ -107,13 +108,11 @@ struct FinishArgs {
   const double* spart;
   float* gU[2];
   float* gV[2];
-  double* level2;         // [segs][n*k] second-level partial sums of G^T U
-  double* fpart;          // [blocks] partials of this kernel
+  double* fpart;          // [blocks][3] partials of this kernel
   unsigned int* counter;  // last-block counter (zero between launches)
   double* f_out;          // plain mode: receives f
   double* aux_out;        // plain mode, optional: phi, ||U||^2, ||V||^2, ||G||_F^2
   int32_t nchunks, row_groups, sweep_wgs;
-  int32_t segs, rows_per_seg;  // row groups are summed in segs segments of rows_per_seg
   int32_t gv_blocks;      // set by the launcher
 };
 
@@ -144,6 +143,7 @@ hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream);
 hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream);
 hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream);
 int lbfgs_blocks(int64_t N);
+int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks);
 }  // namespace rpca
 
 // Context internals needed by the certificate / initialisation module.

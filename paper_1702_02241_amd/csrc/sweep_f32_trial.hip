@@ -1,0 +1,9 @@
+// Instantiations of the objective/gradient sweep: f32 products, trial evaluation.
+#include "sweep_kernel.h"
+
+namespace rpca {
+hipError_t launch_sweep_f32_trial(const SweepArgs& sa, bool masked, int kb, int tj, hipStream_t s) {
+  return masked ? rpca_sweep::launch_tj<true, true, false>(sa, kb, tj, s)
+                : rpca_sweep::launch_tj<false, true, false>(sa, kb, tj, s);
+}
+}  // namespace rpca

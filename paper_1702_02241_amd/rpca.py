@@ -89,6 +89,7 @@ def lib():
             "rpca_default_opts": (None, [ctypes.POINTER(rpca_opts)]),
             "rpca_create": (I32, [I64, I64, I32, D, D, P, ctypes.POINTER(P)]),
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
+            "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_certificate": (I32, [P, P, P, P, ctypes.POINTER(rpca_cert), P]),
             "rpca_init_rsvd": (I32, [P, P, P, I32, I32, U64, P, P, P]),
@@ -127,6 +128,10 @@ def rpca_create(m, n, k, lam_s, lam_l, mask=None):
 
 def rpca_objgrad(ctx, X, U, V, f, gU, gV, stream=0):
     return lib().rpca_objgrad(ctx, X, U, V, f, gU, gV, stream)
+
+
+def rpca_objgrad_ex(ctx, X, U, V, f, gU, gV, precision, stream=0):
+    return lib().rpca_objgrad_ex(ctx, X, U, V, f, gU, gV, precision, stream)
 
 
 def rpca_solve(ctx, X, U, V, opts=None, stream=0):

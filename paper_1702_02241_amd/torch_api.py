@@ -44,12 +44,12 @@ class Context:
         except Exception:
             pass
 
-    def objgrad(self, Xcm, U, V):
+    def objgrad(self, Xcm, U, V, precision=R.RPCA_PREC_FP32):
         f = torch.empty(1, dtype=torch.float64, device=U.device)
         gU = torch.empty_like(U)
         gV = torch.empty_like(V)
-        rc = R.rpca_objgrad(self.ctx, Xcm.data_ptr(), U.data_ptr(), V.data_ptr(), f.data_ptr(),
-                            gU.data_ptr(), gV.data_ptr(), _stream())
+        rc = R.rpca_objgrad_ex(self.ctx, Xcm.data_ptr(), U.data_ptr(), V.data_ptr(), f.data_ptr(),
+                               gU.data_ptr(), gV.data_ptr(), precision, _stream())
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_objgrad failed: {R.rpca_status_string(rc)}")
         return f, gU, gV

@@ -18,12 +18,12 @@ from gpu_common import device, f32, rel
 pytestmark = pytest.mark.gpu
 
 
-def _check(p, U, V, tol_f=1e-5, tol_g=1e-5, label=""):
+def _check(p, U, V, tol_f=1e-5, tol_g=1e-5, label="", precision=0):
     dev = device()
     ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l, p.mask)
     Xcm = T.to_device_X(p.X, dev)
     Ud, Vd = T.to_device_factor(U, dev), T.to_device_factor(V, dev)
-    f, gU, gV = ctx.objgrad(Xcm, Ud, Vd)
+    f, gU, gV = ctx.objgrad(Xcm, Ud, Vd, precision)
     torch.cuda.synchronize()
     fr, gUr, gVr = ob.objgrad(f32(U), f32(V), f32(p.X), p.lam_s, p.lam_l, p.mask)
     ef = abs(float(f.item()) - fr) / abs(fr)
@@ -35,7 +35,8 @@ def _check(p, U, V, tol_f=1e-5, tol_g=1e-5, label=""):
           f"f rel {ef:.2e}  gU rel {eu:.2e} (max {mu:.2e})  gV rel {ev:.2e} (max {mv:.2e})")
     assert ef <= tol_f
     assert eu <= tol_g and ev <= tol_g
-    assert mu <= 10 * tol_g and mv <= 10 * tol_g
+    if precision == 0:
+        assert mu <= 10 * tol_g and mv <= 10 * tol_g
     ctx.close()
     return f, gU, gV
 
@@ -88,3 +89,19 @@ def test_objgrad_bitwise_deterministic():
     b = ctx.objgrad(Xcm, Ud, Vd)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("m,n,k,masked", [(256, 200, 10, False), (2000, 333, 20, False),
+                                          (76800, 200, 10, False), (1024, 600, 25, True)])
+def test_bf16_objgrad_within_form_tolerance(m, n, k, masked):
+    """BF16 products (FP32 accumulation and residual): relative gradient error
+    <= 1e-2 at non-stationary points, the BF16 bar; f to 1e-2 as well."""
+    if masked:
+        p = synth.partial_rpca(m=m, n=n, r=min(20, k), k=k, p_obs=0.3, seed=300 + m)
+    elif m == 76800:
+        p = synth.video()
+    else:
+        p = synth.gaussian_rpca(m=m, n=n, r=min(5, k), k=k, seed=400 + m)
+    for seed in range(3):
+        U, V = synth.random_factors(p.m, p.n, p.k, 500 + seed, scale=0.5 if m != 76800 else 0.2)
+        _check(p, U, V, tol_f=1e-2, tol_g=1e-2, label=f"bf16 seed{seed}", precision=2)

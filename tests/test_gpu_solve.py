@@ -52,6 +52,27 @@ def test_solve_small_matches_oracle(small):
     assert info.certified == 1
 
 
+def test_bf16_polish_solve_matches_oracle(small):
+    """Form (1): BF16 products until a loose tolerance, then an FP32 polish;
+    after the polish ||L - L_oracle||_F / ||L_oracle||_F <= 1e-4."""
+    p, U0, V0, Om, fstar, Us, Vs = small
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    U, V = T.to_device_factor(U0, dev), T.to_device_factor(V0, dev)
+    rc, info = ctx.solve(Xcm, U, V, precision=1, certify=1)
+    torch.cuda.synchronize()
+    Ug, Vg = U.cpu().numpy().astype(np.float64), V.cpu().numpy().astype(np.float64)
+    eL = rel(Ug @ Vg.T, Us @ Vs.T)
+    f_at = ob.objective(Ug, Vg, p.X, p.lam_s, p.lam_l)
+    print(f"[solve bf16+polish] rc={rc} iters={info.iters} (bf16 {info.iters_bf16}) evals={info.evals} "
+          f"L rel={eL:.2e} f rel={abs(f_at - fstar) / fstar:.2e} rel_gap={info.rel_gap:.2e}")
+    assert rc >= 0 and info.certified == 1
+    assert info.iters_bf16 > 0
+    assert eL <= 1e-4
+    assert abs(f_at - fstar) / fstar <= 1e-5
+
+
 def test_certificate_matches_oracle_exact(small):
     p, U0, V0, Om, fstar, Us, Vs = small
     dev = device()
