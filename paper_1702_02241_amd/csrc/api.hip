@@ -19,11 +19,12 @@ struct rpca_ctx {
   uint32_t* mask = nullptr;  // device bitmask or null
   int mw = 0;
   // sweep configuration
-  int row_groups = 0, spw = 0, chunk_w = 0, nchunks = 0, sweep_wgs = 0;
+  int row_groups = 0, spw = 0, chunk_w = 0, nchunks = 0, sweep_wgs = 0, segs = 0, rps = 16;
   float* gvpart = nullptr;
   float* gupart = nullptr;
   double* spart = nullptr;
   double* fpart = nullptr;
+  double* level2 = nullptr;
   unsigned int* counters = nullptr;  // [0] finish, [1] update, [2] direction, [3..] spare
   // solver workspace
   int64_t N = 0;  // (m + n) k padded to a multiple of 256
@@ -107,6 +108,9 @@ FinishArgs make_finish_args(const rpca_ctx* c) {
   f.gvpart = c->gvpart;
   f.spart = c->spart;
   f.fpart = c->fpart;
+  f.level2 = c->level2;
+  f.segs = c->segs;
+  f.rows_per_seg = c->rps;
   f.counter = c->counters + 0;
   f.nchunks = c->nchunks;
   f.row_groups = c->row_groups;
@@ -260,6 +264,7 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->gupart);
   dfree(c->spart);
   dfree(c->fpart);
+  dfree(c->level2);
   dfree(c->counters);
   dfree(c->x[0]);
   dfree(c->x[1]);
@@ -320,6 +325,9 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, con
   if (c->nchunks > 1) TRY(dalloc(&c->gupart, (size_t)c->nchunks * m * k));
   TRY(dalloc(&c->spart, (size_t)c->sweep_wgs * RPCA_NSCAL));
   TRY(dalloc(&c->fpart, (size_t)rpca::finish_blocks(m, n, k, c->nchunks, nullptr) * 3 + 16));
+  c->rps = 16;
+  c->segs = (c->row_groups + c->rps - 1) / c->rps;
+  TRY(dalloc(&c->level2, (size_t)c->segs * n * k));
   TRY(dalloc(&c->counters, 16));
   if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess) {
     rpca_destroy(c);

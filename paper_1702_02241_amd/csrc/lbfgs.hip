@@ -39,15 +39,11 @@ __device__ __forceinline__ double dot4(f4 a, f4 b) {
   return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2] + (double)a[3] * b[3];
 }
 
-// Reduce NV per-thread values over the block (value IMAX, if in range, is a max,
-// the others sums), write them value-major to part[v*nb + block], then let the
-// last block combine them over blocks into out[] (shared).  Returns true in the
-// last block, after out[] is valid in every thread.  Fixed order throughout.
+// Reduce NV per-thread values over the block (value IMAX, if in range, is a
+// max, the others sums) and write them value-major to part[v*nb + block].
 template <int NV, int IMAX>
-__device__ bool reduce_partials(const double (&acc)[NV], double* part, unsigned int* counter,
-                                double* out) {
+__device__ void block_partials(const double (&acc)[NV], double* part) {
   __shared__ double sh[WAVES][NV];
-  __shared__ int s_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nb = gridDim.x;
 #pragma unroll
@@ -61,15 +57,13 @@ __device__ bool reduce_partials(const double (&acc)[NV], double* part, unsigned 
     for (int w = 1; w < WAVES; ++w) r = (v == IMAX) ? fmax(r, sh[w][v]) : r + sh[w][v];
     part[(int64_t)v * nb + blockIdx.x] = r;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == (unsigned)nb - 1u);
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
+}
+
+// One block: combine the nb block partials of NV values in a fixed order into out[] (LDS).
+template <int NV, int IMAX>
+__device__ void combine_partials(const double* part, int nb, double* out) {
+  __shared__ double sh[WAVES][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double r[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) r[v] = 0.0;
@@ -92,8 +86,6 @@ __device__ bool reduce_partials(const double (&acc)[NV], double* part, unsigned 
     out[v] = q;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
 }
 
 // Layout of the dot vector of the update pass: 4 per stored pair (s_i.g, y_i.g,
@@ -241,16 +233,16 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
     const f4 s = alpha * dd[e];
     Ssp[e] = s;
     Ysp[e] = y;
+    // every slot is read (unused ones point at slot 0 and their dots are ignored),
+    // so the loads carry no branch and can all be in flight together
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
-      if (i < cnt) {
-        const f4 Si = Sp[i][e];
-        const f4 Yi = Yp[i][e];
-        acc[4 * i + 0] += dot4(Si, g1);
-        acc[4 * i + 1] += dot4(Yi, g1);
-        acc[4 * i + 2] += dot4(Si, y);
-        acc[4 * i + 3] += dot4(Yi, y);
-      }
+      const f4 Si = Sp[i][e];
+      const f4 Yi = Yp[i][e];
+      acc[4 * i + 0] += dot4(Si, g1);
+      acc[4 * i + 1] += dot4(Yi, g1);
+      acc[4 * i + 2] += dot4(Si, y);
+      acc[4 * i + 3] += dot4(Yi, y);
     }
     acc[I::SY] += dot4(s, y);
     acc[I::YY] += dot4(y, y);
@@ -263,9 +255,25 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
     acc[I::GINF] = fmax(acc[I::GINF], m4);
     acc[I::G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
   }
+  block_partials<NV, I::GINF>(acc, a.part);
+}
+
+// One block: combine the update partials and run the small (mem x mem) algebra on
+// an LDS copy of the state (global latency per access would dominate otherwise).
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final(LbfgsArgs a, int nb) {
+  using I = DotIdx<MEM>;
+  constexpr int NV = I::NV;
+  SolverState* st = a.st;
+  if (st->phase != PH_UPDATE) return;
   __shared__ double D[NV];
-  if (!reduce_partials<NV, I::GINF>(acc, a.part, a.counter, D)) return;
-  if (threadIdx.x == 0) update_small_math<MEM>(st, D);
+  combine_partials<NV, I::GINF>(a.part, nb, D);
+  __shared__ SolverState sst;
+  copy_state_block(&sst, st);
+  __syncthreads();
+  if (threadIdx.x == 0) update_small_math<MEM>(&sst, D);
+  __syncthreads();
+  copy_state_block(st, &sst);
 }
 
 template <int MEM>
@@ -293,11 +301,10 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     f4 h = gamma * gv;
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
-      if (i < cnt) {
-        const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
-        const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
-        h += cs[i] * Si + cy[i] * Yi;
-      }
+      // unused slots carry zero coefficients; no branch around the loads
+      const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
+      const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
+      h += cs[i] * Si + cy[i] * Yi;
     }
     const f4 dv = -h;
     d[e] = dv;
@@ -305,13 +312,20 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     acc[1] += dot4(dv, dv);
     acc[2] += fabs((double)gv[0]) + fabs((double)gv[1]) + fabs((double)gv[2]) + fabs((double)gv[3]);
   }
+  block_partials<3, -1>(acc, a.part);
+}
+
+// One block: g^T d, d^T d, ||g||_1 from the direction partials; first trial step.
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final(LbfgsArgs a, int nb) {
+  SolverState* st = a.st;
+  if (st->phase != PH_DIRECTION) return;
   __shared__ double D[3];
-  if (!reduce_partials<3, -1>(acc, a.part, a.counter, D)) return;
+  combine_partials<3, -1>(a.part, nb, D);
   if (threadIdx.x == 0) {
     const double gd = D[0];
     st->dd = D[1];
     if (!(gd < 0.0) || !isfinite(gd)) {
-      if (cnt > 0) {
+      if (st->count > 0) {
         // not a descent direction: drop the memory, steepest descent next slot
         st->count = 0;
         st->spare = 0;
@@ -350,11 +364,14 @@ int lbfgs_blocks(int64_t N) {
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
 hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream) {
-  const dim3 grid(lbfgs_blocks(a.N));
+  const int nb = lbfgs_blocks(a.N);
+  const dim3 grid(nb);
   switch (mem) {
-#define CASE(M)                                                                        \
-  case M:                                                                              \
-    hipLaunchKernelGGL((k_lbfgs_update<M>), grid, dim3(THREADS), 0, stream, a);       \
+#define CASE(M)                                                                              \
+  case M:                                                                                    \
+    hipLaunchKernelGGL((k_lbfgs_update<M>), grid, dim3(THREADS), 0, stream, a);             \
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                      \
+    hipLaunchKernelGGL((k_lbfgs_update_final<M>), dim3(1), dim3(THREADS), 0, stream, a, nb); \
     break;
     RPCA_MEM_CASES(CASE)
 #undef CASE
@@ -365,7 +382,8 @@ hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream) 
 }
 
 hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream) {
-  const dim3 grid(lbfgs_blocks(a.N));
+  const int nb = lbfgs_blocks(a.N);
+  const dim3 grid(nb);
   switch (mem) {
 #define CASE(M)                                                                        \
   case M:                                                                              \
@@ -376,6 +394,8 @@ hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t strea
     default:
       return hipErrorInvalidValue;
   }
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  hipLaunchKernelGGL(k_lbfgs_direction_final, dim3(1), dim3(THREADS), 0, stream, a, nb);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #include "linesearch.h"
 #include "rpca_internal.h"
+#include "sweep_kernel.h"
 
 namespace {
 
@@ -46,16 +47,39 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// Finishing reduction in one launch:
-//   blocks [0, gv_blocks): 64 outputs of G^T U each; the 4 waves split the
-//     workgroup partials (rows w, w+4, ...) and are combined in a fixed order;
-//     gV = sum + lam_l V_t.
-//   blocks [gv_blocks, ...): multi-chunk only, gU = sum over chunks + lam_l U_t.
-//   the last block to arrive: f, g^T d and, in solver mode, one line-search step.
+// Finishing reduction, two launches (no grid-wide fence in the wide one):
+//   k_reduce1: grid (ceil(nk/256), segs); thread o of block (bx, by) sums the
+//     G^T U partials of workgroup rows [by*rps, (by+1)*rps) -> level2[by][o].
+//   k_reduce2: blocks < gv_blocks: gV = sum_by level2 + lam_l V_t (fixed order);
+//     further blocks (several chunks only): gU = sum over chunks + lam_l U_t.
+//     Each block publishes three scalar partials; the last block to arrive
+//     (thread-0 fence + counter over a handful of blocks) forms f and g^T d
+//     and, in solver mode, runs one step of the line search.
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce1(FinishArgs a) {
+  const int64_t nk = a.n * a.k;
+  const int64_t o = (int64_t)blockIdx.x * FIN_THREADS + threadIdx.x;
+  if (o >= nk) return;
+  const int r0 = blockIdx.y * a.rows_per_seg;
+  int r1 = r0 + a.rows_per_seg;
+  if (r1 > a.row_groups) r1 = a.row_groups;
+  const float* src = a.gvpart + o;
+  double s = 0.0;
+  int r = r0;
+  for (; r + 3 < r1; r += 4) {
+    const float x0 = src[(int64_t)r * nk], x1 = src[(int64_t)(r + 1) * nk];
+    const float x2 = src[(int64_t)(r + 2) * nk], x3 = src[(int64_t)(r + 3) * nk];
+    s += (double)x0;
+    s += (double)x1;
+    s += (double)x2;
+    s += (double)x3;
+  }
+  for (; r < r1; ++r) s += (double)src[(int64_t)r * nk];
+  a.level2[(int64_t)blockIdx.y * nk + o] = s;
+}
+
 template <bool TRIAL>
-__global__ __launch_bounds__(FIN_THREADS) void k_finish(FinishArgs a) {
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
   __shared__ double sh[FIN_THREADS / 64];
-  __shared__ double sPart[4][64];
   __shared__ int s_last;
   int outi = 0;
   SolverState* st = a.st;
@@ -67,31 +91,15 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(FinishArgs a) {
   const float lam_l = a.lam_l;
   const float* Vt = a.V[outi];
   const float* Ut = a.U[outi];
-  const int bx = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int bx = blockIdx.x, tid = threadIdx.x;
   double vv = 0.0, gvd = 0.0, gud = 0.0;
   if (bx < a.gv_blocks) {
-    const int64_t o = (int64_t)bx * 64 + lane;
-    double s = 0.0;
+    const int64_t o = (int64_t)bx * FIN_THREADS + tid;
     if (o < nk) {
-      const float* src = a.gvpart + o;
-      int r = w;
-      for (; r + 12 < a.row_groups; r += 16) {
-        const float x0 = src[(int64_t)r * nk], x1 = src[(int64_t)(r + 4) * nk];
-        const float x2 = src[(int64_t)(r + 8) * nk], x3 = src[(int64_t)(r + 12) * nk];
-        s += (double)x0;
-        s += (double)x1;
-        s += (double)x2;
-        s += (double)x3;
-      }
-      for (; r < a.row_groups; r += 4) s += (double)src[(int64_t)r * nk];
-    }
-    sPart[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && o < nk) {
-      const double tot = sPart[0][lane] + sPart[1][lane] + sPart[2][lane] + sPart[3][lane];
+      double s = 0.0;
+      for (int q = 0; q < a.segs; ++q) s += a.level2[(int64_t)q * nk + o];
       const float v = Vt[o];
-      const float gvv = (float)(tot + (double)lam_l * (double)v);
+      const float gvv = (float)(s + (double)lam_l * (double)v);
       a.gV[outi][o] = gvv;
       vv = (double)v * (double)v;
       if (TRIAL) gvd = (double)gvv * (double)a.dV[o];
@@ -113,10 +121,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(FinishArgs a) {
     a.fpart[bx * 3 + 0] = b0;
     a.fpart[bx * 3 + 1] = b1;
     a.fpart[bx * 3 + 2] = b2;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
+    __threadfence();
     const unsigned prev = atomicAdd(a.counter, 1u);
     s_last = (prev == gridDim.x - 1u);
   }
@@ -142,52 +147,50 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finish(FinishArgs a) {
   p0 = block_sum<FIN_THREADS>(p0, sh);
   p1 = block_sum<FIN_THREADS>(p1, sh);
   p2 = block_sum<FIN_THREADS>(p2, sh);
-  if (tid == 0) {
-    const double f = fd + 0.5 * (double)lam_l * (uu + p0);
-    const double dphi = gd1 + p1 + p2;
-    if (!TRIAL) {
-      *a.f_out = f;
+  if (!TRIAL) {
+    if (tid == 0) {
+      *a.f_out = fd + 0.5 * (double)lam_l * (uu + p0);
       if (a.aux_out) {
         a.aux_out[0] = fd;  // phi(U V^T)
         a.aux_out[1] = uu;  // ||U||^2
         a.aux_out[2] = p0;  // ||V||^2
         a.aux_out[3] = g2;  // ||G||_F^2
       }
-    } else {
-      rpca_ls::line_search_step(st, f, dphi);
+      *a.counter = 0u;
     }
+    return;
+  }
+  // line-search step on an LDS copy of the state (one thread), written back by the block
+  __shared__ SolverState sst;
+  copy_state_block(&sst, st);
+  __syncthreads();
+  if (tid == 0) {
+    rpca_ls::line_search_step(&sst, fd + 0.5 * (double)lam_l * (uu + p0), gd1 + p1 + p2);
     *a.counter = 0u;
   }
+  __syncthreads();
+  copy_state_block(st, &sst);
 }
 
 }  // namespace
 
 namespace rpca {
 
-hipError_t launch_sweep_f32_plain(const SweepArgs&, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f32_trial(const SweepArgs&, bool, int, int, hipStream_t);
-hipError_t launch_sweep_bf16_plain(const SweepArgs&, bool, int, int, hipStream_t);
-hipError_t launch_sweep_bf16_trial(const SweepArgs&, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f32_plain(const SweepArgs&, bool, hipStream_t);
+hipError_t launch_sweep_f32_trial(const SweepArgs&, bool, hipStream_t);
+hipError_t launch_sweep_bf16_plain(const SweepArgs&, bool, hipStream_t);
+hipError_t launch_sweep_bf16_trial(const SweepArgs&, bool, hipStream_t);
 
-// Column chunk (16*TJ columns) and the wave/workgroup split of the rows.
+// Column chunks (each fitting the sweep's LDS budget) and the wave/workgroup
+// split of the rows.
 int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wave,
                      int* chunk_w, int* nchunks) {
-  static const int tj1[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 16};
-  static const int tj2[] = {1, 2, 3, 4, 6, 8};
-  const int KB = (k + 15) / 16;
-  const int* tjs = KB == 1 ? tj1 : tj2;
-  const int ntj = KB == 1 ? 10 : 6;
-  const int tmax = tjs[ntj - 1];
-  const int64_t tiles = (n + 15) / 16;
-  int tj = tmax;
-  if (tiles < tmax)
-    for (int i = 0; i < ntj; ++i)
-      if (tjs[i] >= tiles) {
-        tj = tjs[i];
-        break;
-      }
-  const int cw = 16 * tj;
-  const int nch = (int)((n + cw - 1) / cw);
+  const int kb = (k + 15) / 16;
+  const int cmax = rpca_sweep::max_chunk(kb, k);
+  int nch = (int)((n + cmax - 1) / cmax);
+  int cw = (int)(((n + nch - 1) / nch + 15) / 16) * 16;
+  if (cw > cmax) cw = cmax;
+  nch = (int)((n + cw - 1) / cw);
   const int64_t nstrips = (m + 15) / 16;
   // about eight waves per compute unit over all chunks
   int64_t target = (2048 + nch - 1) / nch;
@@ -195,7 +198,7 @@ int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_p
   if (target < 1) target = 1;
   const int64_t spw = (nstrips + target - 1) / target;
   const int64_t waves = (nstrips + spw - 1) / spw;
-  const int64_t wgs = (waves + 3) / 4;
+  const int64_t wgs = (waves + rpca_sweep::WAVES - 1) / rpca_sweep::WAVES;
   *row_groups = (int)wgs;
   *strips_per_wave = (int)spw;
   *chunk_w = cw;
@@ -204,18 +207,14 @@ int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_p
 }
 
 hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream) {
-  const int kb = (sa.k + 15) / 16;
-  const int tj = sa.chunk_w / 16;
   const bool masked = sa.mask != nullptr;
   if (bf16)
-    return trial ? launch_sweep_bf16_trial(sa, masked, kb, tj, stream)
-                 : launch_sweep_bf16_plain(sa, masked, kb, tj, stream);
-  return trial ? launch_sweep_f32_trial(sa, masked, kb, tj, stream)
-               : launch_sweep_f32_plain(sa, masked, kb, tj, stream);
+    return trial ? launch_sweep_bf16_trial(sa, masked, stream) : launch_sweep_bf16_plain(sa, masked, stream);
+  return trial ? launch_sweep_f32_trial(sa, masked, stream) : launch_sweep_f32_plain(sa, masked, stream);
 }
 
 int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks) {
-  const int gvb = (int)((n * k + 63) / 64);
+  const int gvb = (int)((n * k + FIN_THREADS - 1) / FIN_THREADS);
   int gub = 0;
   if (nchunks > 1) {
     gub = (int)((m * k + FIN_THREADS * 8 - 1) / (FIN_THREADS * 8));
@@ -228,10 +227,14 @@ int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks) {
 hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream) {
   FinishArgs f2 = fa;
   const int blocks = finish_blocks(fa.m, fa.n, fa.k, fa.nchunks, &f2.gv_blocks);
+  const int gvb = (int)((fa.n * fa.k + FIN_THREADS - 1) / FIN_THREADS);
+  hipLaunchKernelGGL(k_reduce1, dim3(gvb, fa.segs), dim3(FIN_THREADS), 0, stream, f2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (trial)
-    hipLaunchKernelGGL((k_finish<true>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
+    hipLaunchKernelGGL((k_reduce2<true>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
   else
-    hipLaunchKernelGGL((k_finish<false>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
+    hipLaunchKernelGGL((k_reduce2<false>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
   return hipGetLastError();
 }
 

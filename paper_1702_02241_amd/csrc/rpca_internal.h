@@ -67,6 +67,15 @@ struct SolverState {
   double best_f;
 };
 
+// Block-cooperative copy of the solver state in 8-byte words (used to stage the
+// state in LDS before one thread runs the scalar algebra on it).
+__device__ __forceinline__ void copy_state_block(SolverState* dst, const SolverState* src) {
+  static_assert(sizeof(SolverState) % 8 == 0, "state size");
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 8); i += blockDim.x) d[i] = s[i];
+}
+
 // Arguments of the fused objective/gradient sweep.
 struct SweepArgs {
   const float* X;
@@ -108,11 +117,13 @@ struct FinishArgs {
   const double* spart;
   float* gU[2];
   float* gV[2];
-  double* fpart;          // [blocks][3] partials of this kernel
+  double* level2;         // [segs][n*k] first-level sums of the G^T U partials
+  double* fpart;          // [blocks][3] partials of the second reduction
   unsigned int* counter;  // last-block counter (zero between launches)
   double* f_out;          // plain mode: receives f
   double* aux_out;        // plain mode, optional: phi, ||U||^2, ||V||^2, ||G||_F^2
   int32_t nchunks, row_groups, sweep_wgs;
+  int32_t segs, rows_per_seg;  // workgroup rows are summed in segs segments
   int32_t gv_blocks;      // set by the launcher
 };
 

@@ -2,8 +2,8 @@
 #include "sweep_kernel.h"
 
 namespace rpca {
-hipError_t launch_sweep_bf16_plain(const SweepArgs& sa, bool masked, int kb, int tj, hipStream_t s) {
-  return masked ? rpca_sweep::launch_tj<true, false, true>(sa, kb, tj, s)
-                : rpca_sweep::launch_tj<false, false, true>(sa, kb, tj, s);
+hipError_t launch_sweep_bf16_plain(const SweepArgs& sa, bool masked, hipStream_t s) {
+  return masked ? rpca_sweep::launch_kb<true, false, true>(sa, s)
+                : rpca_sweep::launch_kb<false, false, true>(sa, s);
 }
 }  // namespace rpca

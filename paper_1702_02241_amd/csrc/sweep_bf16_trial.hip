@@ -2,8 +2,8 @@
 #include "sweep_kernel.h"
 
 namespace rpca {
-hipError_t launch_sweep_bf16_trial(const SweepArgs& sa, bool masked, int kb, int tj, hipStream_t s) {
-  return masked ? rpca_sweep::launch_tj<true, true, true>(sa, kb, tj, s)
-                : rpca_sweep::launch_tj<false, true, true>(sa, kb, tj, s);
+hipError_t launch_sweep_bf16_trial(const SweepArgs& sa, bool masked, hipStream_t s) {
+  return masked ? rpca_sweep::launch_kb<true, true, true>(sa, s)
+                : rpca_sweep::launch_kb<false, true, true>(sa, s);
 }
 }  // namespace rpca

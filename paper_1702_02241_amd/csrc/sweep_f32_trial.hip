@@ -2,8 +2,8 @@
 #include "sweep_kernel.h"
 
 namespace rpca {
-hipError_t launch_sweep_f32_trial(const SweepArgs& sa, bool masked, int kb, int tj, hipStream_t s) {
-  return masked ? rpca_sweep::launch_tj<true, true, false>(sa, kb, tj, s)
-                : rpca_sweep::launch_tj<false, true, false>(sa, kb, tj, s);
+hipError_t launch_sweep_f32_trial(const SweepArgs& sa, bool masked, hipStream_t s) {
+  return masked ? rpca_sweep::launch_kb<true, true, false>(sa, s)
+                : rpca_sweep::launch_kb<false, true, false>(sa, s);
 }
 }  // namespace rpca

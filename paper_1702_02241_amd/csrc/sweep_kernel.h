@@ -6,26 +6,29 @@
 //   G^T U and G V                 (the two gradient products, chain rule on eq. smoothNC)
 // so neither R nor G is ever written to memory.
 //
-// Work split.  The columns are cut into chunks of 16*TJ (grid.y); every wave
-// owns a contiguous run of 16-row strips and, for each strip, walks all TJ
-// column tiles of its chunk in a fully unrolled loop with no branches (padded
-// columns compute zeros), so the compiler can issue the X loads of many tiles
-// ahead.  Per 16x16 tile:
+// Work split.  The columns are cut into chunks (grid.y) small enough for the
+// LDS budget below; every wave owns a contiguous run of 16-row strips and, for
+// each strip, walks the chunk's 16-column tiles in groups of four.  The X loads
+// of the next group are issued before the current group is computed and pinned
+// there with a scheduling barrier, so about eight tiles per wave are in flight
+// while registers stay independent of the chunk width.  Per 16x16 tile:
 //   * R on MFMA with the accumulator seeded by -X.  In the MFMA output layout
 //     (column j = lane%16, rows 4*(lane/16)+r) G is already the A operand of
-//     G^T U with the K index running over rows: G^T U accumulates in registers
-//     per tile across all strips of the wave and is combined over the
-//     workgroup's waves once, at the end, in a fixed order.
+//     G^T U with the K index running over rows.  The tile's G^T U is added into
+//     the wave's private LDS accumulator (one writer per address, so no
+//     atomics); the waves' accumulators are summed in a fixed order at the end.
 //   * G V contracts over columns: G goes through a 16x17 per-wave LDS tile to
 //     the transposed layout and into MFMA; the strip's G V accumulates in
-//     registers across its tiles and is complete when the strip ends (one
-//     chunk) or written as a per-chunk partial.
+//     registers over the chunk and is complete when the strip ends (one chunk)
+//     or written as a per-chunk partial.
 // FP32 mode uses v_mfma_f32_16x16x4_f32; BF16 mode rounds U, V and G to bf16 and
-// uses v_mfma_f32_16x16x16_bf16 (FP32 accumulation, FP32 residual).  All
-// cross-workgroup sums run in a fixed order: results are bitwise reproducible.
+// uses v_mfma_f32_16x16x16_bf16 (FP32 accumulation, FP32 residual).  Every
+// cross-wave and cross-workgroup sum runs in a fixed order: bitwise reproducible.
 #pragma once
 
 #include <math.h>
+
+#include <type_traits>
 
 #include "rpca_internal.h"
 
@@ -36,7 +39,9 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 
 constexpr int WAVES = 4;
 constexpr int NT = 64 * WAVES;
-constexpr int LDT = 17;  // padded row of the per-wave transpose tile
+constexpr int LDT = 17;   // padded row of the per-wave transpose tile
+constexpr int PF = 4;     // tiles per load group
+constexpr int LDS_LIMIT_FLOATS = 16384;  // 64 KB per workgroup
 
 __device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -68,23 +73,23 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// LDS: sVt[16 TJ][KMAX+1] (V_t of the chunk) | per-wave transpose tile [WAVES][16*LDT].
-// At the end the G^T U combine buffer [16 TJ][KMAX] reuses the sVt space.
-template <int KB, int TJ>
-constexpr int lds_floats() {
-  return 16 * TJ * (16 * KB + 1) + WAVES * 16 * LDT;
+// Dynamic LDS (floats): sVt[cwp][KMAX+1] | sGV[WAVES][cwp][k] | sT[WAVES][16*LDT]
+__host__ __device__ constexpr int lds_floats(int kb, int k, int cwp) {
+  return cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * 16 * LDT;
 }
 
-template <int KB, int TJ, bool MASKED, bool TRIAL, bool BF16>
+// Widest chunk (multiple of 16 columns) whose staging fits the LDS budget.
+__host__ __device__ constexpr int max_chunk(int kb, int k) {
+  return 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)));
+}
+
+template <int KB, bool MASKED, bool TRIAL, bool BF16>
 __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   constexpr int KMAX = 16 * KB;
   constexpr int KQ = 4 * KB;
   constexpr int LDV = KMAX + 1;
-  constexpr int CW = 16 * TJ;
-  __shared__ float lds[lds_floats<KB, TJ>()];
+  extern __shared__ float lds[];
   __shared__ double sRed[WAVES];
-  float* sVt = lds;
-  float* sT = lds + CW * LDV;
 
   int cur = 0, outi = 0;
   float alpha = 0.f;
@@ -105,13 +110,18 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   const float* __restrict__ V = a.V[cur];
   const float* __restrict__ X = a.X;
   const float* __restrict__ dU = a.dU;
-  float* myT = sT + w * 16 * LDT;
 
-  const int64_t j_begin = (int64_t)ch * CW;
-  const int ncols = (int)((n - j_begin) < CW ? (n - j_begin) : CW);
+  const int64_t j_begin = (int64_t)ch * a.chunk_w;
+  const int ncols = (int)((n - j_begin) < a.chunk_w ? (n - j_begin) : a.chunk_w);
+  const int ntiles = (ncols + 15) >> 4;
+  const int cwp = ntiles * 16;
+  float* sVt = lds;
+  float* sGVall = lds + cwp * LDV;
+  float* sGV = sGVall + w * cwp * k;
+  float* myT = sGVall + WAVES * cwp * k + w * 16 * LDT;
 
-  // Stage the (trial) V rows of this chunk, zero padded.
-  for (int idx = tid; idx < CW * KMAX; idx += NT) {
+  // Stage the (trial) V rows of this chunk (zero padded); clear the G^T U accumulators.
+  for (int idx = tid; idx < cwp * KMAX; idx += NT) {
     const int jl = idx / KMAX, kk = idx % KMAX;
     float v = 0.f;
     if (jl < ncols && kk < k) {
@@ -124,73 +134,66 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
     }
     sVt[jl * LDV + kk] = v;
   }
+  for (int idx = tid; idx < WAVES * cwp * k; idx += NT) sGVall[idx] = 0.f;
   __syncthreads();
 
-  f4 gv[TJ][KB];
-#pragma unroll
-  for (int t = 0; t < TJ; ++t)
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) gv[t][kb] = f4{0.f, 0.f, 0.f, 0.f};
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
-
   const int64_t nstrips = (m + 15) >> 4;
   const int64_t gw = (int64_t)blockIdx.x * WAVES + w;
   const int64_t s_begin = gw * a.strips_per_wave;
   int64_t s_end = s_begin + a.strips_per_wave;
   if (s_end > nstrips) s_end = nstrips;
   const bool vec = a.xvec != 0;
+  const int64_t tile_stride = 16 * m;  // floats between the same lane's columns in consecutive tiles
 
   for (int64_t s = s_begin; s < s_end; ++s) {
     const int64_t i0 = s * 16;
     const bool full = vec && (i0 + 16 <= m);
-    // U_t operands of the strip.
-    float ua[KQ];        // R:      A[i = c][kk = 4q + g]
-    float ub[4][KB];     // G^T U:  B[row 4g + r][kk = 16 kb + c]
-    float dub[4][KB];    // dU at the ub positions (trial)
+    // U_t operands of the strip (clamped addresses + selects: no branches).
+    const int64_t i_c = (i0 + c < m) ? i0 + c : m - 1;
+    const bool row_c_ok = i0 + c < m;
+    float ua[KQ];      // R:      A[i = c][kk = 4q + g]
+    float ub[4][KB];   // G^T U:  B[row 4g + r][kk = 16 kb + c]
+    float dub[4][KB];  // dU at the ub positions (trial)
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int kk = 4 * q + g;
-      const int64_t i = i0 + c;
-      float v = 0.f;
-      if (kk < k && i < m) {
-        v = U[i * k + kk];
-        if (TRIAL) v = fmaf(alpha, dU[i * k + kk], v);
-      }
-      ua[q] = v;
+      const int kkc = kk < k ? kk : k - 1;
+      float v = U[i_c * k + kkc];
+      if (TRIAL) v = fmaf(alpha, dU[i_c * k + kkc], v);
+      ua[q] = (kk < k && row_c_ok) ? v : 0.f;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 4 * g + r;
+      const int64_t ic = i < m ? i : m - 1;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         const int kk = 16 * kb + c;
-        const int64_t i = i0 + 4 * g + r;
-        float v = 0.f, dv = 0.f;
-        if (kk < k && i < m) {
-          v = U[i * k + kk];
-          if (TRIAL) {
-            dv = dU[i * k + kk];
-            v = fmaf(alpha, dv, v);
-          }
+        const int kkc = kk < k ? kk : k - 1;
+        const bool ok = kk < k && i < m;
+        float v = U[ic * k + kkc], dv = 0.f;
+        if (TRIAL) {
+          dv = dU[ic * k + kkc];
+          v = fmaf(alpha, dv, v);
         }
-        ub[r][kb] = v;
-        dub[r][kb] = dv;
+        ub[r][kb] = ok ? v : 0.f;
+        dub[r][kb] = ok ? dv : 0.f;
       }
+    }
+    // BF16 A operand of R: lane (c, g) holds U_t[i0 + c][16 kb + 4 g + e], e = 0..3
     s4 uab[KB], ubb[KB];
     if (BF16) {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        // A[i = c][kk = 16 kb + 4 g + e] = ua[4 kb + e] of lanes with the same c
         float t4[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int kk = 16 * kb + 4 * g + e;
-          const int64_t i = i0 + c;
-          float v = 0.f;
-          if (kk < k && i < m) {
-            v = U[i * k + kk];
-            if (TRIAL) v = fmaf(alpha, dU[i * k + kk], v);
-          }
-          t4[e] = v;
+          const int kkc = kk < k ? kk : k - 1;
+          float v = U[i_c * k + kkc];
+          if (TRIAL) v = fmaf(alpha, dU[i_c * k + kkc], v);
+          t4[e] = (kk < k && row_c_ok) ? v : 0.f;
         }
         uab[kb] = pack_bf16(t4[0], t4[1], t4[2], t4[3]);
         ubb[kb] = pack_bf16(ub[0][kb], ub[1][kb], ub[2][kb], ub[3][kb]);
@@ -200,79 +203,128 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) gu[kb] = f4{0.f, 0.f, 0.f, 0.f};
     float ftile = 0.f, gtile = 0.f;
+    // lane's column base (column c of tile 0 of the chunk, rows i0 + 4g .. +3)
+    const float* xbase = X + (j_begin + c) * m + i0 + 4 * g;
 
+    auto strip = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      auto load_group = [&](int t0, f4(&xr)[PF], uint32_t(&br)[PF]) {
 #pragma unroll
-    for (int t = 0; t < TJ; ++t) {
-      const int jl = 16 * t + c;
-      const bool jok = jl < ncols;
-      const int64_t j = j_begin + jl;
-      const float* xp = X + j * m + i0 + 4 * g;
-      f4 xv;
-      if (full) {
-        xv = jok ? *reinterpret_cast<const f4*>(xp) : f4{0.f, 0.f, 0.f, 0.f};
-      } else {
+        for (int u = 0; u < PF; ++u) {
+          const int jl = 16 * (t0 + u) + c;
+          // columns past the chunk re-read its last column (valid address; zeroed at use)
+          const int64_t off = (jl < ncols) ? (int64_t)(t0 + u) * tile_stride
+                                           : (int64_t)(ncols - 1 - c) * m;
+          if (FULL) {
+            xr[u] = *reinterpret_cast<const f4*>(xbase + off);
+          } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xv[r] = (jok && i0 + 4 * g + r < m) ? xp[r] : 0.f;
-      }
-      uint32_t bits = 0xFu;
-      if (MASKED) bits = jok ? (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu : 0u;
-      f4 acc = -xv;
-      if (!BF16) {
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) acc = mfma_f32(ua[q], sVt[jl * LDV + 4 * q + g], acc);
-      } else {
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const float* vr = sVt + jl * LDV + 16 * kb + 4 * g;
-          acc = mfma_bf16(uab[kb], pack_bf16(vr[0], vr[1], vr[2], vr[3]), acc);
+            for (int r = 0; r < 4; ++r) {
+              const int64_t i = i0 + 4 * g + r;
+              const float xv_r = xbase[off + ((i < m) ? r : (m - 1 - i0 - 4 * g))];
+              xr[u][r] = (i < m) ? xv_r : 0.f;
+            }
+          }
+          if (MASKED) {
+            const int64_t j = j_begin + ((jl < ncols) ? jl : ncols - 1);
+            br[u] = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
+          }
         }
-      }
-      float G[4];
+      };
+      auto tile = [&](int t, f4 xraw, uint32_t braw) {
+        const int jl = 16 * t + c;
+        const bool jok = jl < ncols;
+        const f4 xv = jok ? xraw : f4{0.f, 0.f, 0.f, 0.f};
+        const uint32_t bits = MASKED ? (jok ? braw : 0u) : 0xFu;
+        f4 acc = -xv;
+        if (!BF16) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float R = acc[r];
-        const float ar = fabsf(R);
-        float rho = (ar <= lam_s) ? 0.5f * R * R : lam_s * (ar - 0.5f * lam_s);
-        float gr = fminf(fmaxf(R, -lam_s), lam_s);
-        if (MASKED && !((bits >> r) & 1u)) {
-          rho = 0.f;
-          gr = 0.f;
+          for (int q = 0; q < KQ; ++q) acc = mfma_f32(ua[q], sVt[jl * LDV + 4 * q + g], acc);
+        } else {
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const float* vr = sVt + jl * LDV + 16 * kb + 4 * g;
+            acc = mfma_bf16(uab[kb], pack_bf16(vr[0], vr[1], vr[2], vr[3]), acc);
+          }
         }
-        ftile += rho;
-        gtile = fmaf(gr, gr, gtile);
-        G[r] = gr;
-        myT[(4 * g + r) * LDT + c] = gr;
-      }
-      // G^T U for this tile (K = the strip's 16 rows)
-      if (!BF16) {
+        float G[4];
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
+        for (int r = 0; r < 4; ++r) {
+          const float R = acc[r];
+          const float ar = fabsf(R);
+          float rho = (ar <= lam_s) ? 0.5f * R * R : lam_s * (ar - 0.5f * lam_s);
+          float gr = fminf(fmaxf(R, -lam_s), lam_s);
+          if (MASKED && !((bits >> r) & 1u)) {
+            rho = 0.f;
+            gr = 0.f;
+          }
+          ftile += rho;
+          gtile = fmaf(gr, gr, gtile);
+          G[r] = gr;
+          myT[(4 * g + r) * LDT + c] = gr;
+        }
+        // G^T U of the tile (K = the strip's 16 rows) into the wave's LDS accumulator
+        f4 gvt[KB];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) gv[t][kb] = mfma_f32(G[r], ub[r][kb], gv[t][kb]);
-      } else {
-        const s4 gb = pack_bf16(G[0], G[1], G[2], G[3]);
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) gv[t][kb] = mfma_bf16(gb, ubb[kb], gv[t][kb]);
-      }
-      // G V for this tile (K = the tile's 16 columns) from the transposed G
-      if (!BF16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float gt = myT[c * LDT + 4 * q + g];
+        for (int kb = 0; kb < KB; ++kb) gvt[kb] = f4{0.f, 0.f, 0.f, 0.f};
+        if (!BF16) {
 #pragma unroll
           for (int kb = 0; kb < KB; ++kb)
-            gu[kb] = mfma_f32(gt, sVt[(16 * t + 4 * q + g) * LDV + 16 * kb + c], gu[kb]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gvt[kb] = mfma_f32(G[r], ub[r][kb], gvt[kb]);
+        } else {
+          const s4 gb = pack_bf16(G[0], G[1], G[2], G[3]);
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) gvt[kb] = mfma_bf16(gb, ubb[kb], gvt[kb]);
         }
-      } else {
-        const float* tr = myT + c * LDT + 4 * g;
-        const s4 gtb = pack_bf16(tr[0], tr[1], tr[2], tr[3]);
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-          const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
-          gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
+          const int kk = 16 * kb + c;
+          if (kk < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sGV[(16 * t + 4 * g + r) * k + kk] += gvt[kb][r];
+          }
         }
+        // G V of the tile (K = the tile's 16 columns) from the transposed G
+        if (!BF16) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float gt = myT[c * LDT + 4 * q + g];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+              gu[kb] = mfma_f32(gt, sVt[(16 * t + 4 * q + g) * LDV + 16 * kb + c], gu[kb]);
+          }
+        } else {
+          const float* tr = myT + c * LDT + 4 * g;
+          const s4 gtb = pack_bf16(tr[0], tr[1], tr[2], tr[3]);
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
+            gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
+          }
+        }
+      };
+      f4 xa[PF], xb[PF];
+      uint32_t ba[PF] = {}, bb[PF] = {};
+      load_group(0, xa, ba);
+      for (int t0 = 0; t0 < ntiles; t0 += 2 * PF) {
+        // group t0 is in xa; issue group t0+PF into xb, compute xa; then the mirror
+        if (t0 + PF < ntiles) load_group(t0 + PF, xb, bb);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+          if (t0 + u < ntiles) tile(t0 + u, xa[u], ba[u]);
+        if (t0 + PF >= ntiles) break;
+        if (t0 + 2 * PF < ntiles) load_group(t0 + 2 * PF, xa, ba);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+          if (t0 + PF + u < ntiles) tile(t0 + PF + u, xb[u], bb[u]);
       }
-    }
+    };
+    if (full) strip(std::true_type{});
+    else strip(std::false_type{});
+
     f_acc += (double)ftile;
     gg_acc += (double)gtile;
     // Finish the strip's rows: lane (g, c) holds G V for rows i0+4g+r, column 16 kb + c.
@@ -300,27 +352,14 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
     }
   }
 
-  // Combine the waves' G^T U (fixed order) in the V staging space, write the partial.
+  // Sum the waves' G^T U accumulators in a fixed order and write the partial.
   __syncthreads();
-  float* sC = lds;
-  for (int ww = 0; ww < WAVES; ++ww) {
-    if (w == ww) {
-#pragma unroll
-      for (int t = 0; t < TJ; ++t)
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int idx = (16 * t + 4 * g + r) * KMAX + 16 * kb + c;
-            sC[idx] = (ww == 0 ? 0.f : sC[idx]) + gv[t][kb][r];
-          }
-    }
-    __syncthreads();
-  }
   float* gvp = a.gvpart + (int64_t)blockIdx.x * n * k;
   for (int idx = tid; idx < ncols * k; idx += NT) {
-    const int jl = idx / k, kk = idx - jl * k;
-    gvp[(j_begin + jl) * k + kk] = sC[jl * KMAX + kk];
+    float acc = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) acc += sGVall[ww * cwp * k + idx];
+    gvp[j_begin * k + idx] = acc;
   }
   double* sp = a.spart + ((int64_t)blockIdx.x * a.nchunks + ch) * RPCA_NSCAL;
   const double v0 = block_sum(f_acc, sRed);
@@ -335,24 +374,20 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   }
 }
 
-// Tile counts instantiated per rank block count (a chunk uses the smallest
-// count >= its 16-column tiles).
-constexpr int TJ1[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 16};
-constexpr int TJ2[] = {1, 2, 3, 4, 6, 8};
-
 template <bool MASKED, bool TRIAL, bool BF16>
-hipError_t launch_tj(const SweepArgs& sa, int kb, int tj, hipStream_t s) {
+hipError_t launch_kb(const SweepArgs& sa, hipStream_t s) {
+  const int kb = (sa.k + 15) / 16;
+  const int cwp = (int)(((sa.n < sa.chunk_w ? sa.n : sa.chunk_w) + 15) / 16) * 16;
+  const int lds = lds_floats(kb, sa.k, cwp);
+  if (lds > LDS_LIMIT_FLOATS || sa.chunk_w > max_chunk(kb, sa.k)) return hipErrorInvalidValue;
   const dim3 grid(sa.row_groups, sa.nchunks), block(NT);
-#define RPCA_CASE(KBV, TJV)                                                           \
-  if (kb == KBV && tj == TJV) {                                                       \
-    hipLaunchKernelGGL((k_sweep<KBV, TJV, MASKED, TRIAL, BF16>), grid, block, 0, s, sa); \
-    return hipGetLastError();                                                         \
-  }
-  RPCA_CASE(1, 1) RPCA_CASE(1, 2) RPCA_CASE(1, 3) RPCA_CASE(1, 4) RPCA_CASE(1, 5)
-  RPCA_CASE(1, 6) RPCA_CASE(1, 8) RPCA_CASE(1, 10) RPCA_CASE(1, 13) RPCA_CASE(1, 16)
-  RPCA_CASE(2, 1) RPCA_CASE(2, 2) RPCA_CASE(2, 3) RPCA_CASE(2, 4) RPCA_CASE(2, 6) RPCA_CASE(2, 8)
-#undef RPCA_CASE
-  return hipErrorInvalidValue;
+  if (kb == 1)
+    hipLaunchKernelGGL((k_sweep<1, MASKED, TRIAL, BF16>), grid, block, lds * sizeof(float), s, sa);
+  else if (kb == 2)
+    hipLaunchKernelGGL((k_sweep<2, MASKED, TRIAL, BF16>), grid, block, lds * sizeof(float), s, sa);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace rpca_sweep
