@@ -442,7 +442,7 @@ void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
 
 // Run the device-resident L-BFGS from x[cur] (whose f and g are valid) until the
 // device reports PH_DONE.  Returns an rpca_status.
-static int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStream_t s) {
+int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStream_t s) {
   SweepArgs sa = make_sweep_args(c, X);
   FinishArgs fa = make_finish_args(c);
   LbfgsArgs la;
@@ -470,7 +470,7 @@ static int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16,
 namespace rpca {
 
 // Plain evaluation at the current iterate x[cur]: g[cur] and state.f (device).
-static int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s) {
+int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s) {
   const int64_t mk = c->m * c->k;
   SweepArgs sa = make_sweep_args(c, X);
   FinishArgs fa = make_finish_args(c);
@@ -488,7 +488,7 @@ static int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStre
 
 // Restart the device loop from the current iterate after a phase change:
 // keep the L-BFGS memory, clear the stop flag and the f history.
-static int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
+int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
   SolverState* h = c->st_host;
   HIPCHK(hipMemcpyAsync(h, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -502,37 +502,75 @@ static int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
   return RPCA_OK;
 }
 
+// Everything a batched launch needs to run this context's solver slots:
+// arguments of the loop kernels and of a plain evaluation at x[cur], the
+// sweep's work decomposition and the block counts of the other kernels.
+void instance_args(rpca_ctx* c, const float* X, int cur, InstanceArgs* out) {
+  const int64_t mk = c->m * c->k;
+  out->sa_loop = make_sweep_args(c, X);
+  out->fa_loop = make_finish_args(c);
+  LbfgsArgs la;
+  solver_views(c, &out->sa_loop, &out->fa_loop, &la);
+  out->lu = la;
+  out->ld = la;
+  out->lu.counter = c->counters + 1;
+  out->ld.counter = c->counters + 2;
+  out->sa_eval = make_sweep_args(c, X);
+  out->fa_eval = make_finish_args(c);
+  SweepArgs& sa = out->sa_eval;
+  FinishArgs& fa = out->fa_eval;
+  sa.U[0] = sa.U[1] = c->x[cur];
+  sa.V[0] = sa.V[1] = c->x[cur] + mk;
+  sa.gU[0] = sa.gU[1] = c->g[cur];
+  fa.U[0] = fa.U[1] = c->x[cur];
+  fa.V[0] = fa.V[1] = c->x[cur] + mk;
+  fa.gU[0] = fa.gU[1] = c->g[cur];
+  fa.gV[0] = fa.gV[1] = c->g[cur] + mk;
+  fa.f_out = &c->st->f;
+  int gvb = 0;
+  out->fin2_blocks = finish_blocks(c->m, c->n, c->k, c->nchunks, &gvb);
+  out->fa_loop.gv_blocks = gvb;
+  out->fa_eval.gv_blocks = gvb;
+  out->fin1_blocks = gvb * c->segs;
+  out->lb_blocks = lbfgs_blocks(c->N);
+  out->row_groups = c->row_groups;
+  out->nchunks = c->nchunks;
+  out->chunk_w = c->chunk_w;
+  out->spw = c->spw;
+  out->masked = c->mask != nullptr;
+  out->state_dev = c->st;
+  out->state_host = c->st_host;
+}
+
 }  // namespace rpca
 
-extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts* opts,
-                          rpca_info* info, void* stream) {
-  if (!c || !X || !U || !V) return RPCA_EINVAL;
-  rpca_opts o;
-  if (opts) o = *opts;
-  else rpca_default_opts(&o);
-  if (o.mem < 1 || o.mem > RPCA_MEMMAX - 1 || o.max_iter < 0 || !(o.c1 > 0) || !(o.c2 > o.c1) ||
-      !(o.c2 < 1) || !(o.gtol >= 0) || !(o.ftol >= 0) || o.precision < 0 || o.precision > 2 ||
-      !(o.bf16_gtol >= 0) || !(o.cert_tol > 0))
-    return RPCA_EINVAL;
-  const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t s = (hipStream_t)stream;
+namespace rpca {
+
+bool valid_opts(const rpca_opts& o) {
+  return !(o.mem < 1 || o.mem > RPCA_MEMMAX - 1 || o.max_iter < 0 || !(o.c1 > 0) || !(o.c2 > o.c1) ||
+           !(o.c2 < 1) || !(o.gtol >= 0) || !(o.ftol >= 0) || o.precision < 0 || o.precision > 2 ||
+           !(o.bf16_gtol >= 0) || !(o.cert_tol > 0));
+}
+
+int solve_phases(const rpca_opts& o, SolvePhase* ph) {
+  int nph = 0;
+  if (o.precision == RPCA_PREC_FP32) ph[nph++] = {false, o.gtol};
+  else if (o.precision == RPCA_PREC_BF16) ph[nph++] = {true, o.gtol};
+  else {
+    ph[nph++] = {true, o.bf16_gtol};
+    ph[nph++] = {false, o.gtol};
+  }
+  return nph;
+}
+
+// Start of a solve: optional cold start, iterate x[0] = (U, V), fresh device state
+// (phase DIRECTION; the caller evaluates f and g at x[0] next).
+int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, double gtol0,
+                hipStream_t s) {
   const int64_t mk = c->m * c->k, nk = c->n * c->k;
   if (o.init == RPCA_INIT_RSVD) {
-    const int rc = rpca_init_rsvd(c, X, nullptr, o.rsvd_oversample, o.rsvd_power, o.seed, U, V, stream);
+    const int rc = rpca_init_rsvd(c, X, nullptr, o.rsvd_oversample, o.rsvd_power, o.seed, U, V, s);
     if (rc != RPCA_OK) return rc;
-  }
-  // precision phases: (bf16, gtol)
-  struct Phase {
-    bool bf16;
-    double gtol;
-  };
-  Phase phases[2];
-  int nph = 0;
-  if (o.precision == RPCA_PREC_FP32) phases[nph++] = {false, o.gtol};
-  else if (o.precision == RPCA_PREC_BF16) phases[nph++] = {true, o.gtol};
-  else {
-    phases[nph++] = {true, o.bf16_gtol};
-    phases[nph++] = {false, o.gtol};
   }
   HIPCHK(hipMemcpyAsync(c->x[0], U, mk * 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(c->x[0] + mk, V, nk * 4, hipMemcpyDeviceToDevice, s));
@@ -546,7 +584,7 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   h->first_iter = 1;
   h->c1 = o.c1;
   h->c2 = o.c2;
-  h->gtol = phases[0].gtol;
+  h->gtol = gtol0;
   h->ftol = o.ftol;
   h->eps_f = 1e-7;
   for (int i = 0; i < 8; ++i) h->fhist[i] = INFINITY;
@@ -554,22 +592,21 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   h->gamma = 1.0;
   h->evals = 1;
   HIPCHK(hipMemcpyAsync(c->st, h, sizeof(SolverState), hipMemcpyHostToDevice, s));
-  int rc = rpca::eval_current(c, X, 0, phases[0].bf16, s);
-  if (rc) return rc;
-  rc = rpca::run_lbfgs(c, X, &o, phases[0].bf16, s);
-  if (rc) return rc;
-  int iters_bf16 = phases[0].bf16 ? c->st_host->iter : 0;
-  bool final_bf16 = phases[0].bf16;
-  for (int ph = 1; ph < nph; ++ph) {
-    if (c->st_host->stop == STOP_NONFINITE || c->st_host->stop == STOP_MAXITER) break;
-    if ((rc = rpca::resume_state(c, phases[ph].gtol, o.ftol, s))) return rc;
-    if ((rc = rpca::eval_current(c, X, c->st_host->cur, phases[ph].bf16, s))) return rc;
-    if ((rc = rpca::run_lbfgs(c, X, &o, phases[ph].bf16, s))) return rc;
-    final_bf16 = phases[ph].bf16;
-  }
+  return RPCA_OK;
+}
+
+// End of a solve: copy the iterate out, certify (tightening the stopping tests
+// and continuing while the gap is above the target, at most five rounds), and
+// fill `info`.  Returns the rpca_status of the solve.
+int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
+                 double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
+                 hipStream_t s) {
+  const int64_t mk = c->m * c->k, nk = c->n * c->k;
   double rel_gap = NAN;
-  int certified = 0, rounds = 0;
-  double gtol = phases[nph - 1].gtol, ftol = o.ftol;
+  int certified = 0, rounds = 0, rc;
+  double ftol = o.ftol;
+  HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   for (;;) {
     const int cur = c->st_host->cur;
     HIPCHK(hipMemcpyAsync(U, c->x[cur], mk * 4, hipMemcpyDeviceToDevice, s));
@@ -577,7 +614,7 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
     const int stop = c->st_host->stop;
     if (!o.certify || stop == STOP_NONFINITE) break;
     rpca_cert cert;
-    const int crc = rpca_certificate(c, X, U, V, &cert, stream);
+    const int crc = rpca_certificate(c, X, U, V, &cert, s);
     if (crc < 0) return crc;
     ++rounds;
     rel_gap = cert.rel_gap;
@@ -586,8 +623,8 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
     // not certified yet: tighten the stopping tests and continue from here
     gtol *= 0.1;
     ftol *= 0.01;
-    if ((rc = rpca::resume_state(c, gtol, ftol, s))) return rc;
-    if ((rc = rpca::run_lbfgs(c, X, &o, final_bf16, s))) return rc;
+    if ((rc = resume_state(c, gtol, ftol, s))) return rc;
+    if ((rc = run_lbfgs(c, X, &o, final_bf16, s))) return rc;
   }
   HIPCHK(hipStreamSynchronize(s));
   const SolverState fin = *c->st_host;
@@ -617,4 +654,33 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return status;
+}
+
+}  // namespace rpca
+
+extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts* opts,
+                          rpca_info* info, void* stream) {
+  if (!c || !X || !U || !V) return RPCA_EINVAL;
+  rpca_opts o;
+  if (opts) o = *opts;
+  else rpca_default_opts(&o);
+  if (!rpca::valid_opts(o)) return RPCA_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  rpca::SolvePhase phases[2];
+  const int nph = rpca::solve_phases(o, phases);
+  int rc = rpca::solve_setup(c, X, U, V, o, phases[0].gtol, s);
+  if (rc) return rc;
+  if ((rc = rpca::eval_current(c, X, 0, phases[0].bf16, s))) return rc;
+  if ((rc = rpca::run_lbfgs(c, X, &o, phases[0].bf16, s))) return rc;
+  int iters_bf16 = phases[0].bf16 ? c->st_host->iter : 0;
+  bool final_bf16 = phases[0].bf16;
+  for (int ph = 1; ph < nph; ++ph) {
+    if (c->st_host->stop == STOP_NONFINITE || c->st_host->stop == STOP_MAXITER) break;
+    if ((rc = rpca::resume_state(c, phases[ph].gtol, o.ftol, s))) return rc;
+    if ((rc = rpca::eval_current(c, X, c->st_host->cur, phases[ph].bf16, s))) return rc;
+    if ((rc = rpca::run_lbfgs(c, X, &o, phases[ph].bf16, s))) return rc;
+    final_bf16 = phases[ph].bf16;
+  }
+  return rpca::solve_finish(c, X, U, V, o, final_bf16, phases[nph - 1].gtol, iters_bf16, t0, info, s);
 }

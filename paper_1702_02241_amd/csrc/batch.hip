@@ -1,0 +1,429 @@
+// Batched solver: many independent Split-SPCP instances of uneven shape
+// solved together.  Every step of an L-BFGS slot is ONE launch for the whole
+// batch:
+//   direction  (blocks of all instances in one grid, then one block per instance)
+//   sweep      (one persistent kernel pulling (instance, row group, chunk) items
+//               from a queue; items sorted by decreasing cost)
+//   finish     (two batched reductions with the line-search step per instance)
+//   update     (batched history pass, then one block per instance)
+// Per-instance solver states live in device memory and every kernel skips the
+// instances that are not in its phase, so converged instances cost nothing but
+// the phase test.  A group of slots is captured once in a hipGraph and
+// replayed until every instance reports done.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+#include <vector>
+
+#include "../../include/rpca_batch.h"
+#include "rpca_internal.h"
+
+namespace {
+
+__global__ void k_gather_phase(SolverState* const* st, int count, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = st[i]->phase;
+}
+
+template <typename T>
+bool dalloc(T** p, size_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, (count ? count : 1) * sizeof(T)) != hipSuccess) return false;
+  *p = static_cast<T*>(q);
+  return true;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+struct rpca_batch {
+  int count = 0;
+  std::vector<rpca_ctx*> ctx;
+  bool masked = false;
+  // decomposition (fixed by the shapes)
+  int nitems = 0, lds_max = 0;
+  int tot_fin1 = 0, tot_fin2 = 0, tot_lb = 0;
+  std::vector<int> off_fin1, off_fin2, off_lb;
+  SweepItem* d_items = nullptr;
+  int* d_off_fin1 = nullptr;
+  int* d_off_fin2 = nullptr;
+  int* d_off_lb = nullptr;
+  unsigned* d_head = nullptr;
+  // argument tables (rewritten by every call: they carry the X pointers)
+  SweepArgs* d_sa_loop = nullptr;
+  SweepArgs* d_sa_eval = nullptr;
+  FinishArgs* d_fa_loop = nullptr;
+  FinishArgs* d_fa_eval = nullptr;
+  LbfgsArgs* d_lu = nullptr;
+  LbfgsArgs* d_ld = nullptr;
+  SolverState** d_states = nullptr;
+  int* d_phase = nullptr;
+  int* h_phase = nullptr;  // pinned
+  // the batch runs on its own stream, ordered after / before the caller's by events
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // captured slot groups, keyed by (bf16, mem, slots)
+  struct Graph {
+    bool bf16;
+    int mem, slots;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  int sweep_grid[2] = {0, 0};  // persistent grid for FP32 / BF16
+  bool use_graphs = true;
+};
+
+namespace {
+
+void destroy_batch(rpca_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (rpca_ctx* c : b->ctx)
+    if (c) rpca_destroy(c);
+  dfree(b->d_items);
+  dfree(b->d_off_fin1);
+  dfree(b->d_off_fin2);
+  dfree(b->d_off_lb);
+  dfree(b->d_head);
+  dfree(b->d_sa_loop);
+  dfree(b->d_sa_eval);
+  dfree(b->d_fa_loop);
+  dfree(b->d_fa_eval);
+  dfree(b->d_lu);
+  dfree(b->d_ld);
+  dfree(b->d_states);
+  dfree(b->d_phase);
+  if (b->h_phase) (void)hipHostFree(b->h_phase);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// Upload the argument tables for the arrays of X pointers (evaluation at x[0]).
+hipError_t upload_args(rpca_batch* b, const float* const* X, std::vector<rpca::InstanceArgs>* ia) {
+  const int n = b->count;
+  ia->resize(n);
+  std::vector<SweepArgs> sl(n), se(n);
+  std::vector<FinishArgs> fl(n), fe(n);
+  std::vector<LbfgsArgs> lu(n), ld(n);
+  for (int i = 0; i < n; ++i) {
+    rpca::instance_args(b->ctx[i], X[i], 0, &(*ia)[i]);
+    sl[i] = (*ia)[i].sa_loop;
+    se[i] = (*ia)[i].sa_eval;
+    fl[i] = (*ia)[i].fa_loop;
+    fe[i] = (*ia)[i].fa_eval;
+    lu[i] = (*ia)[i].lu;
+    ld[i] = (*ia)[i].ld;
+  }
+  hipStream_t s = b->stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(b->d_sa_loop, sl.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_sa_eval, se.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_fa_loop, fl.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_fa_eval, fe.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_lu, lu.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_ld, ld.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
+  // the host vectors die with this frame: finish the copies first
+  return hipStreamSynchronize(s);
+}
+
+// One batched objective/gradient pass (plain: at x[0] into st->f and g[0]; trial: solver slot).
+hipError_t batched_objgrad(rpca_batch* b, bool trial, bool bf16) {
+  hipStream_t s = b->stream;
+  hipError_t e = rpca::launch_sweep_batch(trial ? b->d_sa_loop : b->d_sa_eval, b->d_items, b->nitems, b->d_head,
+                                          b->sweep_grid[bf16 ? 1 : 0], b->lds_max, b->masked, trial, bf16, s);
+  if (e != hipSuccess) return e;
+  return rpca::launch_finish_batch(trial ? b->d_fa_loop : b->d_fa_eval, b->d_off_fin1, b->tot_fin1,
+                                   b->d_off_fin2, b->tot_fin2, b->count, b->d_head, trial, s);
+}
+
+hipError_t batched_slot(rpca_batch* b, int mem, bool bf16) {
+  hipStream_t s = b->stream;
+  hipError_t e = rpca::launch_lbfgs_direction_batch(b->d_ld, b->d_off_lb, b->count, b->tot_lb, mem, s);
+  if (e != hipSuccess) return e;
+  if ((e = batched_objgrad(b, true, bf16)) != hipSuccess) return e;
+  return rpca::launch_lbfgs_update_batch(b->d_lu, b->d_off_lb, b->count, b->tot_lb, mem, s);
+}
+
+// The captured group of `slots` solver slots (built on first use).
+hipError_t slot_graph(rpca_batch* b, int mem, bool bf16, int slots, hipGraphExec_t* out) {
+  for (auto& g : b->graphs)
+    if (g.bf16 == bf16 && g.mem == mem && g.slots == slots) {
+      *out = g.exec;
+      return hipSuccess;
+    }
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int q = 0; q < slots && le == hipSuccess; ++q) le = batched_slot(b, mem, bf16);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(b->stream, &graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le != hipSuccess ? le : e;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  b->graphs.push_back({bf16, mem, slots, exec});
+  *out = exec;
+  return hipSuccess;
+}
+
+// Run slot groups until every instance is done.
+int batched_run(rpca_batch* b, const rpca_opts& o, bool bf16, bool use_graph) {
+  const int slots = o.slots_per_sync > 0 ? o.slots_per_sync : 16;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph && slot_graph(b, o.mem, bf16, slots, &exec) != hipSuccess) return RPCA_EHIP;
+  const int nb = (b->count + 255) / 256;
+  for (int guard = 0; guard < 1000000; ++guard) {
+    if (use_graph) {
+      if (hipGraphLaunch(exec, b->stream) != hipSuccess) return RPCA_EHIP;
+    } else {
+      for (int q = 0; q < slots; ++q)
+        if (batched_slot(b, o.mem, bf16) != hipSuccess) return RPCA_EHIP;
+    }
+    hipLaunchKernelGGL(k_gather_phase, dim3(nb), dim3(256), 0, b->stream, b->d_states, b->count, b->d_phase);
+    if (hipMemcpyAsync(b->h_phase, b->d_phase, b->count * sizeof(int), hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+      return RPCA_EHIP;
+    bool all = true;
+    for (int i = 0; i < b->count && all; ++i) all = b->h_phase[i] == PH_DONE;
+    if (all) return RPCA_OK;
+  }
+  return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const int32_t* k, const double* lam_s,
+                      const double* lam_l, rpca_batch** out) {
+  if (!out) return RPCA_EINVAL;
+  *out = nullptr;
+  if (count < 1 || count > 65536 || !m || !n || !k || !lam_s || !lam_l) return RPCA_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (m[i] < 1 || n[i] < 1 || k[i] < 1 || k[i] > 32 || k[i] > m[i] || k[i] > n[i] || !(lam_s[i] > 0) ||
+        !(lam_l[i] > 0) || !isfinite(lam_s[i]) || !isfinite(lam_l[i]))
+      return RPCA_EINVAL;
+  rpca_batch* b = new rpca_batch;
+  b->count = count;
+  b->ctx.assign(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    const int rc = rpca_create(m[i], n[i], k[i], lam_s[i], lam_l[i], nullptr, &b->ctx[i]);
+    if (rc != RPCA_OK) {
+      destroy_batch(b);
+      return rc;
+    }
+  }
+  // decomposition: sweep items (sorted by decreasing cost) and block offsets
+  std::vector<rpca::InstanceArgs> ia(count);
+  std::vector<SweepItem> items;
+  std::vector<double> cost;
+  b->off_fin1.assign(count + 1, 0);
+  b->off_fin2.assign(count + 1, 0);
+  b->off_lb.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    rpca::instance_args(b->ctx[i], nullptr, 0, &ia[i]);
+    const int kb = (k[i] + 15) / 16;
+    const int64_t nstrips = (m[i] + 15) / 16;
+    for (int rg = 0; rg < ia[i].row_groups; ++rg)
+      for (int ch = 0; ch < ia[i].nchunks; ++ch) {
+        items.push_back({i, rg, ch, kb});
+        int64_t s0 = (int64_t)rg * 4 * ia[i].spw, s1 = s0 + 4 * (int64_t)ia[i].spw;
+        if (s1 > nstrips) s1 = nstrips;
+        const int64_t c0 = (int64_t)ch * ia[i].chunk_w;
+        const int64_t cols = std::min<int64_t>(ia[i].chunk_w, n[i] - c0);
+        cost.push_back((double)std::max<int64_t>(s1 - s0, 0) * (double)cols * (1.0 + 0.6 * (kb - 1)));
+      }
+    const int cwp = (int)((std::min<int64_t>(n[i], ia[i].chunk_w) + 15) / 16) * 16;
+    b->lds_max = std::max(b->lds_max, rpca::sweep_lds_floats(kb, k[i], cwp));
+    b->off_fin1[i + 1] = b->off_fin1[i] + ia[i].fin1_blocks;
+    b->off_fin2[i + 1] = b->off_fin2[i] + ia[i].fin2_blocks;
+    b->off_lb[i + 1] = b->off_lb[i] + ia[i].lb_blocks;
+  }
+  std::vector<int> ord(items.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<SweepItem> sorted(items.size());
+  for (size_t j = 0; j < ord.size(); ++j) sorted[j] = items[ord[j]];
+  b->nitems = (int)sorted.size();
+  b->tot_fin1 = b->off_fin1[count];
+  b->tot_fin2 = b->off_fin2[count];
+  b->tot_lb = b->off_lb[count];
+  std::vector<SolverState*> states(count);
+  for (int i = 0; i < count; ++i) states[i] = ia[i].state_dev;
+  bool ok = dalloc(&b->d_items, sorted.size()) && dalloc(&b->d_off_fin1, count + 1) &&
+            dalloc(&b->d_off_fin2, count + 1) && dalloc(&b->d_off_lb, count + 1) && dalloc(&b->d_head, 1) &&
+            dalloc(&b->d_sa_loop, count) && dalloc(&b->d_sa_eval, count) && dalloc(&b->d_fa_loop, count) &&
+            dalloc(&b->d_fa_eval, count) && dalloc(&b->d_lu, count) && dalloc(&b->d_ld, count) &&
+            dalloc(&b->d_states, count) && dalloc(&b->d_phase, count) &&
+            hipHostMalloc((void**)&b->h_phase, count * sizeof(int), 0) == hipSuccess;
+  if (!ok) {
+    destroy_batch(b);
+    return RPCA_ENOMEM;
+  }
+  ok = hipMemcpy(b->d_items, sorted.data(), sorted.size() * sizeof(SweepItem), hipMemcpyHostToDevice) ==
+           hipSuccess &&
+       hipMemcpy(b->d_off_fin1, b->off_fin1.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) ==
+           hipSuccess &&
+       hipMemcpy(b->d_off_fin2, b->off_fin2.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) ==
+           hipSuccess &&
+       hipMemcpy(b->d_off_lb, b->off_lb.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(b->d_states, states.data(), count * sizeof(SolverState*), hipMemcpyHostToDevice) ==
+           hipSuccess &&
+       hipMemset(b->d_head, 0, sizeof(unsigned)) == hipSuccess &&
+       hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
+       hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    destroy_batch(b);
+    return RPCA_EHIP;
+  }
+  b->sweep_grid[0] = std::min(b->nitems, rpca::sweep_batch_grid(b->lds_max, false, true, false));
+  b->sweep_grid[1] = std::min(b->nitems, rpca::sweep_batch_grid(b->lds_max, false, true, true));
+  *out = b;
+  return RPCA_OK;
+}
+
+int rpca_batch_objgrad(rpca_batch* b, const float* const* X, const float* const* U, const float* const* V,
+                       double* const* f, float* const* gU, float* const* gV, int32_t precision, void* stream) {
+  if (!b || !X || !U || !V || !f || !gU || !gV) return RPCA_EINVAL;
+  if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16) return RPCA_EINVAL;
+  for (int i = 0; i < b->count; ++i)
+    if (!X[i] || !U[i] || !V[i] || !f[i] || !gU[i] || !gV[i]) return RPCA_EINVAL;
+  hipStream_t cs = (hipStream_t)stream;
+  if (hipEventRecord(b->ev_in, cs) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)
+    return RPCA_EHIP;
+  // plain evaluations at the caller's points: point the eval tables at them
+  std::vector<rpca::InstanceArgs> ia(b->count);
+  std::vector<SweepArgs> se(b->count);
+  std::vector<FinishArgs> fe(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    rpca::instance_args(b->ctx[i], X[i], 0, &ia[i]);
+    SweepArgs& sa = ia[i].sa_eval;
+    FinishArgs& fa = ia[i].fa_eval;
+    sa.U[0] = sa.U[1] = U[i];
+    sa.V[0] = sa.V[1] = V[i];
+    sa.gU[0] = sa.gU[1] = gU[i];
+    fa.U[0] = fa.U[1] = U[i];
+    fa.V[0] = fa.V[1] = V[i];
+    fa.gU[0] = fa.gU[1] = gU[i];
+    fa.gV[0] = fa.gV[1] = gV[i];
+    fa.f_out = f[i];
+    se[i] = sa;
+    fe[i] = fa;
+  }
+  if (hipMemcpyAsync(b->d_sa_eval, se.data(), b->count * sizeof(SweepArgs), hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b->d_fa_eval, fe.data(), b->count * sizeof(FinishArgs), hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return RPCA_EHIP;
+  if (batched_objgrad(b, false, precision == RPCA_PREC_BF16) != hipSuccess) return RPCA_EHIP;
+  if (hipEventRecord(b->ev_out, b->stream) != hipSuccess || hipStreamWaitEvent(cs, b->ev_out, 0) != hipSuccess)
+    return RPCA_EHIP;
+  return RPCA_OK;
+}
+
+int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, float* const* V,
+                     const rpca_opts* opts, rpca_info* info, void* stream) {
+  if (!b || !X || !U || !V) return RPCA_EINVAL;
+  for (int i = 0; i < b->count; ++i)
+    if (!X[i] || !U[i] || !V[i]) return RPCA_EINVAL;
+  rpca_opts o;
+  if (opts) o = *opts;
+  else rpca_default_opts(&o);
+  if (!rpca::valid_opts(o)) return RPCA_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t cs = (hipStream_t)stream;
+  hipStream_t s = b->stream;
+  if (hipEventRecord(b->ev_in, cs) != hipSuccess || hipStreamWaitEvent(s, b->ev_in, 0) != hipSuccess)
+    return RPCA_EHIP;
+  rpca::SolvePhase phases[2];
+  const int nph = rpca::solve_phases(o, phases);
+  int rc;
+  for (int i = 0; i < b->count; ++i)
+    if ((rc = rpca::solve_setup(b->ctx[i], X[i], U[i], V[i], o, phases[0].gtol, s))) return rc;
+  std::vector<rpca::InstanceArgs> ia;
+  if (upload_args(b, X, &ia) != hipSuccess) return RPCA_EHIP;
+  const bool use_graph = b->use_graphs;
+  if (batched_objgrad(b, false, phases[0].bf16) != hipSuccess) return RPCA_EHIP;
+  if ((rc = batched_run(b, o, phases[0].bf16, use_graph))) return rc;
+  std::vector<int> iters_bf16(b->count, 0);
+  for (int i = 0; i < b->count; ++i) {
+    if (hipMemcpyAsync(ia[i].state_host, ia[i].state_dev, sizeof(SolverState), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return RPCA_EHIP;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  for (int i = 0; i < b->count; ++i) iters_bf16[i] = phases[0].bf16 ? ia[i].state_host->iter : 0;
+  bool final_bf16 = phases[0].bf16;
+  for (int ph = 1; ph < nph; ++ph) {
+    // the polish phase restarts every instance that did not fail, after a plain
+    // evaluation at each current iterate (an instance that failed stays done;
+    // its re-evaluation in place only refreshes f and g at the same point)
+    std::vector<SweepArgs> se(b->count);
+    std::vector<FinishArgs> fe(b->count);
+    for (int i = 0; i < b->count; ++i) {
+      const SolverState* h = ia[i].state_host;
+      const bool failed = h->stop == STOP_NONFINITE || h->stop == STOP_MAXITER;
+      if (!failed && (rc = rpca::resume_state(b->ctx[i], phases[ph].gtol, o.ftol, s))) return rc;
+      rpca::InstanceArgs a;
+      rpca::instance_args(b->ctx[i], X[i], h->cur, &a);
+      se[i] = a.sa_eval;
+      fe[i] = a.fa_eval;
+    }
+    if (hipMemcpyAsync(b->d_sa_eval, se.data(), b->count * sizeof(SweepArgs), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->d_fa_eval, fe.data(), b->count * sizeof(FinishArgs), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return RPCA_EHIP;
+    if (batched_objgrad(b, false, phases[ph].bf16) != hipSuccess) return RPCA_EHIP;
+    if ((rc = batched_run(b, o, phases[ph].bf16, use_graph))) return rc;
+    final_bf16 = phases[ph].bf16;
+  }
+  int worst = RPCA_OK;
+  for (int i = 0; i < b->count; ++i) {
+    rc = rpca::solve_finish(b->ctx[i], X[i], U[i], V[i], o, final_bf16, phases[nph - 1].gtol, iters_bf16[i], t0,
+                            info ? &info[i] : nullptr, s);
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+  }
+  if (hipEventRecord(b->ev_out, s) != hipSuccess || hipStreamWaitEvent(cs, b->ev_out, 0) != hipSuccess)
+    return RPCA_EHIP;
+  return worst;
+}
+
+int rpca_batch_set_graphs(rpca_batch* b, int32_t on) {
+  if (!b) return RPCA_EINVAL;
+  b->use_graphs = on != 0;
+  return RPCA_OK;
+}
+
+int rpca_batch_info(rpca_batch* b, rpca_batch_layout* out) {
+  if (!b || !out) return RPCA_EINVAL;
+  out->count = b->count;
+  out->sweep_items = b->nitems;
+  out->sweep_grid_fp32 = b->sweep_grid[0];
+  out->sweep_grid_bf16 = b->sweep_grid[1];
+  out->lds_bytes = b->lds_max * 4;
+  out->graphs = (int32_t)b->graphs.size();
+  return RPCA_OK;
+}
+
+void rpca_batch_destroy(rpca_batch* b) {
+  if (b) destroy_batch(b);
+}
+
+}  // extern "C"

@@ -42,10 +42,9 @@ __device__ __forceinline__ double dot4(f4 a, f4 b) {
 // Reduce NV per-thread values over the block (value IMAX, if in range, is a
 // max, the others sums) and write them value-major to part[v*nb + block].
 template <int NV, int IMAX>
-__device__ void block_partials(const double (&acc)[NV], double* part) {
+__device__ void block_partials(const double (&acc)[NV], double* part, int bx, int nb) {
   __shared__ double sh[WAVES][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = gridDim.x;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const double r = (v == IMAX) ? wave_max(acc[v]) : wave_sum(acc[v]);
@@ -55,7 +54,7 @@ __device__ void block_partials(const double (&acc)[NV], double* part) {
   for (int v = threadIdx.x; v < NV; v += THREADS) {
     double r = sh[0][v];
     for (int w = 1; w < WAVES; ++w) r = (v == IMAX) ? fmax(r, sh[w][v]) : r + sh[w][v];
-    part[(int64_t)v * nb + blockIdx.x] = r;
+    part[(int64_t)v * nb + bx] = r;
   }
 }
 
@@ -200,8 +199,9 @@ __device__ void update_small_math(SolverState* st, const double* D) {
   st->phase = (stop == STOP_NONE) ? PH_DIRECTION : PH_DONE;
 }
 
+// Blocks bx of nb of one instance (the single-instance grid or a slice of a batched one).
 template <int MEM>
-__global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
+__device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, int nb) {
   using I = DotIdx<MEM>;
   constexpr int NV = I::NV;
   SolverState* st = a.st;
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * THREADS;
-  for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
+  const int64_t stride = (int64_t)nb * THREADS;
+  for (int64_t e = (int64_t)bx * THREADS + threadIdx.x; e < n4; e += stride) {
     const f4 g1 = gn[e];
     const f4 y = g1 - go[e];
     const f4 s = alpha * dd[e];
@@ -255,13 +255,18 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
     acc[I::GINF] = fmax(acc[I::GINF], m4);
     acc[I::G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
   }
-  block_partials<NV, I::GINF>(acc, a.part);
+  block_partials<NV, I::GINF>(acc, a.part, bx, nb);
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update(LbfgsArgs a) {
+  lbfgs_update_body<MEM>(a, blockIdx.x, gridDim.x);
 }
 
 // One block: combine the update partials and run the small (mem x mem) algebra on
 // an LDS copy of the state (global latency per access would dominate otherwise).
 template <int MEM>
-__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final(LbfgsArgs a, int nb) {
+__device__ __forceinline__ void lbfgs_update_final_body(const LbfgsArgs& a, int nb) {
   using I = DotIdx<MEM>;
   constexpr int NV = I::NV;
   SolverState* st = a.st;
@@ -277,7 +282,12 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_update_final(LbfgsArgs a, int
 }
 
 template <int MEM>
-__global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final(LbfgsArgs a, int nb) {
+  lbfgs_update_final_body<MEM>(a, nb);
+}
+
+template <int MEM>
+__device__ __forceinline__ void lbfgs_direction_body(const LbfgsArgs& a, int bx, int nb) {
   SolverState* st = a.st;
   if (st->phase != PH_DIRECTION) return;
   const int cur = st->cur;
@@ -295,8 +305,8 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     cy[i] = (i < cnt) ? (float)st->coef_y[slot[i]] : 0.f;
   }
   double acc[3] = {0.0, 0.0, 0.0};
-  const int64_t stride = (int64_t)gridDim.x * THREADS;
-  for (int64_t e = (int64_t)blockIdx.x * THREADS + threadIdx.x; e < n4; e += stride) {
+  const int64_t stride = (int64_t)nb * THREADS;
+  for (int64_t e = (int64_t)bx * THREADS + threadIdx.x; e < n4; e += stride) {
     const f4 gv = g[e];
     f4 h = gamma * gv;
 #pragma unroll
@@ -312,11 +322,16 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
     acc[1] += dot4(dv, dv);
     acc[2] += fabs((double)gv[0]) + fabs((double)gv[1]) + fabs((double)gv[2]) + fabs((double)gv[3]);
   }
-  block_partials<3, -1>(acc, a.part);
+  block_partials<3, -1>(acc, a.part, bx, nb);
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction(LbfgsArgs a) {
+  lbfgs_direction_body<MEM>(a, blockIdx.x, gridDim.x);
 }
 
 // One block: g^T d, d^T d, ||g||_1 from the direction partials; first trial step.
-__global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final(LbfgsArgs a, int nb) {
+__device__ __forceinline__ void lbfgs_direction_final_body(const LbfgsArgs& a, int nb) {
   SolverState* st = a.st;
   if (st->phase != PH_DIRECTION) return;
   __shared__ double D[3];
@@ -346,6 +361,47 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final(LbfgsArgs a, 
     st->d_prev = gd;
     st->phase = PH_TRIAL;
   }
+}
+
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final(LbfgsArgs a, int nb) {
+  lbfgs_direction_final_body(a, nb);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: one launch serves every instance of a batch.  off[i] ..
+// off[i+1] are the blocks of instance i (off[count] = grid size); the final
+// kernels run one block per instance.
+__device__ __forceinline__ int batch_instance(const int* off, int count, int b) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int count) {
+  const int i = batch_instance(off, count, blockIdx.x);
+  lbfgs_update_body<MEM>(la[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final_batch(const LbfgsArgs* la, const int* off) {
+  const int i = blockIdx.x;
+  lbfgs_update_final_body<MEM>(la[i], off[i + 1] - off[i]);
+}
+
+template <int MEM>
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count) {
+  const int i = batch_instance(off, count, blockIdx.x);
+  lbfgs_direction_body<MEM>(la[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+__global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final_batch(const LbfgsArgs* la, const int* off) {
+  const int i = blockIdx.x;
+  lbfgs_direction_final_body(la[i], off[i + 1] - off[i]);
 }
 
 }  // namespace
@@ -378,6 +434,42 @@ hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream) 
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
+                                    int mem, hipStream_t stream) {
+  switch (mem) {
+#define CASE(M)                                                                                         \
+  case M:                                                                                               \
+    hipLaunchKernelGGL((k_lbfgs_update_batch<M>), dim3(total_blocks), dim3(THREADS), 0, stream, la, off, \
+                       count);                                                                          \
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                                 \
+    hipLaunchKernelGGL((k_lbfgs_update_final_batch<M>), dim3(count), dim3(THREADS), 0, stream, la, off); \
+    break;
+    RPCA_MEM_CASES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
+                                       int mem, hipStream_t stream) {
+  switch (mem) {
+#define CASE(M)                                                                                            \
+  case M:                                                                                                  \
+    hipLaunchKernelGGL((k_lbfgs_direction_batch<M>), dim3(total_blocks), dim3(THREADS), 0, stream, la, off, \
+                       count);                                                                             \
+    break;
+    RPCA_MEM_CASES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  hipLaunchKernelGGL(k_lbfgs_direction_final_batch, dim3(count), dim3(THREADS), 0, stream, la, off);
   return hipGetLastError();
 }
 

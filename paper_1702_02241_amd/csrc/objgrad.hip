@@ -55,11 +55,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 //     Each block publishes three scalar partials; the last block to arrive
 //     (thread-0 fence + counter over a handful of blocks) forms f and g^T d
 //     and, in solver mode, runs one step of the line search.
-__global__ __launch_bounds__(FIN_THREADS) void k_reduce1(FinishArgs a) {
+__device__ __forceinline__ void reduce1_body(const FinishArgs& a, int bx, int by) {
   const int64_t nk = a.n * a.k;
-  const int64_t o = (int64_t)blockIdx.x * FIN_THREADS + threadIdx.x;
+  const int64_t o = (int64_t)bx * FIN_THREADS + threadIdx.x;
   if (o >= nk) return;
-  const int r0 = blockIdx.y * a.rows_per_seg;
+  const int r0 = by * a.rows_per_seg;
   int r1 = r0 + a.rows_per_seg;
   if (r1 > a.row_groups) r1 = a.row_groups;
   const float* src = a.gvpart + o;
@@ -74,11 +74,14 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce1(FinishArgs a) {
     s += (double)x3;
   }
   for (; r < r1; ++r) s += (double)src[(int64_t)r * nk];
-  a.level2[(int64_t)blockIdx.y * nk + o] = s;
+  a.level2[(int64_t)by * nk + o] = s;
 }
 
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce1(FinishArgs a) { reduce1_body(a, blockIdx.x, blockIdx.y); }
+
+// Block bx of the nblk blocks of one instance.
 template <bool TRIAL>
-__global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
+__device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, const int nblk) {
   __shared__ double sh[FIN_THREADS / 64];
   __shared__ int s_last;
   int outi = 0;
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
   const float lam_l = a.lam_l;
   const float* Vt = a.V[outi];
   const float* Ut = a.U[outi];
-  const int bx = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   double vv = 0.0, gvd = 0.0, gud = 0.0;
   if (bx < a.gv_blocks) {
     const int64_t o = (int64_t)bx * FIN_THREADS + tid;
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
       if (TRIAL) gvd = (double)gvv * (double)a.dV[o];
     }
   } else {
-    const int64_t stride = (int64_t)(gridDim.x - a.gv_blocks) * FIN_THREADS;
+    const int64_t stride = (int64_t)(nblk - a.gv_blocks) * FIN_THREADS;
     for (int64_t o = (int64_t)(bx - a.gv_blocks) * FIN_THREADS + tid; o < mk; o += stride) {
       double s = 0.0;
       for (int cc = 0; cc < a.nchunks; ++cc) s += (double)a.gupart[(int64_t)cc * mk + o];
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
     a.fpart[bx * 3 + 2] = b2;
     __threadfence();
     const unsigned prev = atomicAdd(a.counter, 1u);
-    s_last = (prev == gridDim.x - 1u);
+    s_last = (prev == (unsigned)nblk - 1u);
   }
   __syncthreads();
   if (!s_last) return;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
     gd1 += a.spart[(int64_t)q * RPCA_NSCAL + 2];
     g2 += a.spart[(int64_t)q * RPCA_NSCAL + 3];
   }
-  for (int b = tid; b < (int)gridDim.x; b += FIN_THREADS) {
+  for (int b = tid; b < nblk; b += FIN_THREADS) {
     p0 += a.fpart[b * 3 + 0];
     p1 += a.fpart[b * 3 + 1];
     p2 += a.fpart[b * 3 + 2];
@@ -172,6 +175,41 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
   copy_state_block(st, &sst);
 }
 
+template <bool TRIAL>
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce2(FinishArgs a) {
+  reduce2_body<TRIAL>(a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms (one launch for every instance of a batch).  off1/off2: block
+// offsets of each instance in the reduce1 / reduce2 grids; reduce1 also
+// re-arms the work queue of the batched sweep that preceded it.
+__device__ __forceinline__ int batch_instance(const int* off, int count, int b) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce1_batch(const FinishArgs* fa, const int* off, int count,
+                                                              unsigned* queue_head) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue_head = 0u;
+  const int i = batch_instance(off, count, blockIdx.x);
+  const FinishArgs& a = fa[i];
+  const int gvb = (int)((a.n * a.k + FIN_THREADS - 1) / FIN_THREADS);
+  const int lb = blockIdx.x - off[i];
+  reduce1_body(a, lb % gvb, lb / gvb);
+}
+
+template <bool TRIAL>
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce2_batch(const FinishArgs* fa, const int* off, int count) {
+  const int i = batch_instance(off, count, blockIdx.x);
+  reduce2_body<TRIAL>(fa[i], blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
 }  // namespace
 
 namespace rpca {
@@ -181,19 +219,51 @@ hipError_t launch_sweep_f32_trial(const SweepArgs&, bool, hipStream_t);
 hipError_t launch_sweep_bf16_plain(const SweepArgs&, bool, hipStream_t);
 hipError_t launch_sweep_bf16_trial(const SweepArgs&, bool, hipStream_t);
 
+// Sweep decomposition table, keyed by (k bucket, n bucket): the number of
+// waves the strips are spread over and the divisor of the widest chunk.
+// Defaults are what the cfg-sized measurements favoured; rpca_autotune
+// replaces entries by timing the candidates on the device.
+namespace {
+SweepTune g_tune[TUNE_KB][TUNE_NB];
+bool g_tune_init = false;
+
+void tune_defaults() {
+  if (g_tune_init) return;
+  for (int a = 0; a < TUNE_KB; ++a)
+    for (int b = 0; b < TUNE_NB; ++b) g_tune[a][b] = SweepTune{2048, 1};
+  g_tune_init = true;
+}
+}  // namespace
+
+int tune_k_bucket(int k) { return k <= 8 ? 0 : k <= 16 ? 1 : k <= 24 ? 2 : 3; }
+int tune_n_bucket(int64_t n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4; }
+
+SweepTune tune_get(int k, int64_t n) {
+  tune_defaults();
+  return g_tune[tune_k_bucket(k)][tune_n_bucket(n)];
+}
+
+void tune_set(int kbucket, int nbucket, SweepTune t) {
+  tune_defaults();
+  g_tune[kbucket][nbucket] = t;
+}
+
 // Column chunks (each fitting the sweep's LDS budget) and the wave/workgroup
-// split of the rows.
-int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wave,
-                     int* chunk_w, int* nchunks) {
+// split of the rows, from the tuning table.
+int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wave, int* chunk_w,
+                     int* nchunks) {
+  const SweepTune t = tune_get(k, n);
   const int kb = (k + 15) / 16;
-  const int cmax = rpca_sweep::max_chunk(kb, k);
+  int cmax = rpca_sweep::max_chunk(kb, k);
+  if (t.chunk_div > 1) cmax = ((cmax / t.chunk_div + 15) / 16) * 16;
+  if (cmax < 16) cmax = 16;
   int nch = (int)((n + cmax - 1) / cmax);
   int cw = (int)(((n + nch - 1) / nch + 15) / 16) * 16;
   if (cw > cmax) cw = cmax;
   nch = (int)((n + cw - 1) / cw);
   const int64_t nstrips = (m + 15) / 16;
-  // about eight waves per compute unit over all chunks
-  int64_t target = (2048 + nch - 1) / nch;
+  // the waves of all chunks together make up the table's target
+  int64_t target = (t.target_waves + nch - 1) / nch;
   if (target > nstrips) target = nstrips;
   if (target < 1) target = 1;
   const int64_t spw = (nstrips + target - 1) / target;
@@ -235,6 +305,37 @@ hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream) {
     hipLaunchKernelGGL((k_reduce2<true>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
   else
     hipLaunchKernelGGL((k_reduce2<false>), dim3(blocks), dim3(FIN_THREADS), 0, stream, f2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch_f32(const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool, bool,
+                                  hipStream_t);
+hipError_t launch_sweep_batch_bf16(const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool, bool,
+                                   hipStream_t);
+int sweep_batch_grid_f32(int, bool, bool);
+int sweep_batch_grid_bf16(int, bool, bool);
+
+hipError_t launch_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head, int grid,
+                              int lds_floats, bool masked, bool trial, bool bf16, hipStream_t s) {
+  return bf16 ? launch_sweep_batch_bf16(args, items, nitems, head, grid, lds_floats, masked, trial, s)
+              : launch_sweep_batch_f32(args, items, nitems, head, grid, lds_floats, masked, trial, s);
+}
+
+int sweep_lds_floats(int kb, int k, int cwp) { return rpca_sweep::lds_floats(kb, k, cwp); }
+
+int sweep_batch_grid(int lds_floats, bool masked, bool trial, bool bf16) {
+  return bf16 ? sweep_batch_grid_bf16(lds_floats, masked, trial) : sweep_batch_grid_f32(lds_floats, masked, trial);
+}
+
+hipError_t launch_finish_batch(const FinishArgs* fa, const int* off1, int total1, const int* off2, int total2,
+                               int count, unsigned* queue_head, bool trial, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce1_batch, dim3(total1), dim3(FIN_THREADS), 0, stream, fa, off1, count, queue_head);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (trial)
+    hipLaunchKernelGGL((k_reduce2_batch<true>), dim3(total2), dim3(FIN_THREADS), 0, stream, fa, off2, count);
+  else
+    hipLaunchKernelGGL((k_reduce2_batch<false>), dim3(total2), dim3(FIN_THREADS), 0, stream, fa, off2, count);
   return hipGetLastError();
 }
 

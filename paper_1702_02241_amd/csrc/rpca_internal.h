@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <chrono>
+
 #include "../../include/rpca.h"
 
 #define RPCA_MEMMAX 16      // ring slots for (s, y): up to 15 pairs plus one spare
@@ -102,6 +104,11 @@ struct SweepArgs {
   int32_t row_groups;     // workgroups along the rows (grid.x)
 };
 
+// One work item of the batched sweep: workgroup row rg, column chunk ch of instance inst.
+struct SweepItem {
+  int32_t inst, rg, ch, kb;
+};
+
 // Arguments of the finishing reduction (gV, f, g^T d, line-search step).
 struct FinishArgs {
   int64_t m, n;
@@ -145,6 +152,17 @@ struct LbfgsArgs {
 
 // Host-side launchers (defined in the .hip files).
 namespace rpca {
+// Sweep decomposition per (k bucket, n bucket) (see rpca_autotune).
+constexpr int TUNE_KB = 4;   // k <= 8, 16, 24, 32
+constexpr int TUNE_NB = 5;   // n <= 64, 128, 256, 512, larger
+struct SweepTune {
+  int target_waves;  // waves the strips of one sweep are spread over
+  int chunk_div;     // widest LDS-fitting chunk divided by this
+};
+int tune_k_bucket(int k);
+int tune_n_bucket(int64_t n);
+SweepTune tune_get(int k, int64_t n);
+void tune_set(int kbucket, int nbucket, SweepTune t);
 int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wg,
                      int* chunk_w, int* nchunks);
 hipError_t launch_objgrad(const SweepArgs& sa, const FinishArgs& fa, bool trial, bool bf16,
@@ -154,6 +172,18 @@ hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream);
 hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream);
 hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream);
 int lbfgs_blocks(int64_t N);
+// Batched launches: arrays of per-instance arguments in device memory, block
+// offsets off[0..count] (device) of each instance in the flattened grid.
+hipError_t launch_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head,
+                              int grid, int lds_floats, bool masked, bool trial, bool bf16, hipStream_t s);
+int sweep_batch_grid(int lds_floats, bool masked, bool trial, bool bf16);
+int sweep_lds_floats(int kb, int k, int cwp);
+hipError_t launch_finish_batch(const FinishArgs* fa, const int* off1, int total1, const int* off2, int total2,
+                               int count, unsigned* queue_head, bool trial, hipStream_t s);
+hipError_t launch_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks, int mem,
+                                    hipStream_t s);
+hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
+                                       int mem, hipStream_t s);
 int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks);
 }  // namespace rpca
 
@@ -173,4 +203,31 @@ int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V,
                     double* aux_dev, float* gU, float* gV, hipStream_t s);
 // Device workspace owned by the context, grown on demand; *fresh = 1 when newly allocated.
 void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh);
+
+// Solve steps shared by rpca_solve and the batched solver.
+struct SolvePhase {
+  bool bf16;
+  double gtol;
+};
+struct InstanceArgs {
+  SweepArgs sa_loop, sa_eval;
+  FinishArgs fa_loop, fa_eval;
+  LbfgsArgs lu, ld;
+  int fin1_blocks, fin2_blocks, lb_blocks;
+  int row_groups, nchunks, chunk_w, spw;
+  bool masked;
+  SolverState* state_dev;
+  SolverState* state_host;
+};
+bool valid_opts(const rpca_opts& o);
+int solve_phases(const rpca_opts& o, SolvePhase* ph);
+int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, double gtol0,
+                hipStream_t s);
+int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s);
+int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStream_t s);
+int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s);
+void instance_args(rpca_ctx* c, const float* X, int cur, InstanceArgs* out);
+int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
+                 double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
+                 hipStream_t s);
 }  // namespace rpca

@@ -83,13 +83,13 @@ __host__ __device__ constexpr int max_chunk(int kb, int k) {
   return 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)));
 }
 
+// One work item: the strips of workgroup row `rg` against column chunk `ch`.
 template <int KB, bool MASKED, bool TRIAL, bool BF16>
-__global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, const int ch, float* lds,
+                                           double* sRed) {
   constexpr int KMAX = 16 * KB;
   constexpr int KQ = 4 * KB;
   constexpr int LDV = KMAX + 1;
-  extern __shared__ float lds[];
-  __shared__ double sRed[WAVES];
 
   int cur = 0, outi = 0;
   float alpha = 0.f;
@@ -102,7 +102,6 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
-  const int ch = blockIdx.y;
   const int64_t m = a.m, n = a.n;
   const int k = a.k;
   const float lam_s = a.lam_s, lam_l = a.lam_l;
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
       v = V[o];
       if (TRIAL) {
         v = fmaf(alpha, a.dV[o], v);
-        if (blockIdx.x == 0) a.Vt[outi][o] = v;
+        if (rg == 0) a.Vt[outi][o] = v;
       }
     }
     sVt[jl * LDV + kk] = v;
@@ -139,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
 
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
   const int64_t nstrips = (m + 15) >> 4;
-  const int64_t gw = (int64_t)blockIdx.x * WAVES + w;
+  const int64_t gw = (int64_t)rg * WAVES + w;
   const int64_t s_begin = gw * a.strips_per_wave;
   int64_t s_end = s_begin + a.strips_per_wave;
   if (s_end > nstrips) s_end = nstrips;
@@ -308,14 +307,16 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
       uint32_t ba[PF] = {}, bb[PF] = {};
       load_group(0, xa, ba);
       for (int t0 = 0; t0 < ntiles; t0 += 2 * PF) {
-        // group t0 is in xa; issue group t0+PF into xb, compute xa; then the mirror
-        if (t0 + PF < ntiles) load_group(t0 + PF, xb, bb);
+        // group t0 is in xa; issue group t0+PF into xb, compute xa; then the mirror.
+        // The prefetches are unconditional (past the chunk they re-read its last
+        // column): a conditional load would force a full vmcnt(0) wait at the join.
+        load_group(t0 + PF, xb, bb);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PF; ++u)
           if (t0 + u < ntiles) tile(t0 + u, xa[u], ba[u]);
         if (t0 + PF >= ntiles) break;
-        if (t0 + 2 * PF < ntiles) load_group(t0 + 2 * PF, xa, ba);
+        load_group(t0 + 2 * PF, xa, ba);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PF; ++u)
@@ -354,14 +355,14 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
 
   // Sum the waves' G^T U accumulators in a fixed order and write the partial.
   __syncthreads();
-  float* gvp = a.gvpart + (int64_t)blockIdx.x * n * k;
+  float* gvp = a.gvpart + (int64_t)rg * n * k;
   for (int idx = tid; idx < ncols * k; idx += NT) {
     float acc = 0.f;
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) acc += sGVall[ww * cwp * k + idx];
     gvp[j_begin * k + idx] = acc;
   }
-  double* sp = a.spart + ((int64_t)blockIdx.x * a.nchunks + ch) * RPCA_NSCAL;
+  double* sp = a.spart + ((int64_t)rg * a.nchunks + ch) * RPCA_NSCAL;
   const double v0 = block_sum(f_acc, sRed);
   const double v1 = block_sum(uu_acc, sRed);
   const double v2 = block_sum(gud_acc, sRed);
@@ -372,6 +373,48 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
     sp[2] = v2;
     sp[3] = v3;
   }
+}
+
+template <int KB, bool MASKED, bool TRIAL, bool BF16>
+__global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
+  extern __shared__ float lds[];
+  __shared__ double sRed[WAVES];
+  sweep_item<KB, MASKED, TRIAL, BF16>(a, blockIdx.x, blockIdx.y, lds, sRed);
+}
+
+// Batched sweep: one persistent launch for every instance of a batch.  Each
+// workgroup pulls (instance, workgroup row, chunk) items from a queue (a
+// counter advanced by one atomic per item, re-armed by the reduction that
+// follows) until the list is drained.  The list is sorted by decreasing cost,
+// so the long items start first and the short ones fill the tail.
+template <bool MASKED, bool TRIAL, bool BF16>
+__global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems,
+                                                    unsigned* head) {
+  extern __shared__ float lds[];
+  __shared__ double sRed[WAVES];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const SweepItem b = items[it];
+    if (b.kb == 1)
+      sweep_item<1, MASKED, TRIAL, BF16>(args[b.inst], b.rg, b.ch, lds, sRed);
+    else
+      sweep_item<2, MASKED, TRIAL, BF16>(args[b.inst], b.rg, b.ch, lds, sRed);
+    __syncthreads();
+  }
+}
+
+template <bool MASKED, bool TRIAL, bool BF16>
+hipError_t launch_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head, int grid,
+                        int lds_floats_max, hipStream_t s) {
+  if (lds_floats_max > LDS_LIMIT_FLOATS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_batch<MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), lds_floats_max * sizeof(float),
+                     s, args, items, nitems, head);
+  return hipGetLastError();
 }
 
 template <bool MASKED, bool TRIAL, bool BF16>

@@ -12,6 +12,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpca.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rpca.h")
+HEADER_PATHS = [HEADER_PATH, os.path.join(os.path.dirname(HEADER_PATH), "rpca_warm.h"),
+                os.path.join(os.path.dirname(HEADER_PATH), "rpca_batch.h")]
 
 RPCA_OK, RPCA_ENOTCONV, RPCA_ELINESEARCH, RPCA_ENOTCERT = 0, 1, 2, 3
 RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP, RPCA_ENONFINITE = -1, -2, -3, -4
@@ -68,6 +70,12 @@ class rpca_cert(ctypes.Structure):
     ]
 
 
+class rpca_batch_layout(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("sweep_items", ctypes.c_int32),
+                ("sweep_grid_fp32", ctypes.c_int32), ("sweep_grid_bf16", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+
+
 class rpca_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
@@ -97,6 +105,29 @@ def lib():
             "rpca_status_string": (ctypes.c_char_p, [I32]),
             "rpca_profile_enable": (I32, [P, I32]),
             "rpca_profile_read": (I32, [P, ctypes.POINTER(rpca_profile), I32]),
+            # learned warm start (rpca_warm.h)
+            "rpca_mlp_create": (I32, [I32, I32, I32, I32, I32, I32, U64, ctypes.POINTER(P)]),
+            "rpca_mlp_param": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(I64)]),
+            "rpca_mlp_grad": (I32, [P, I32, ctypes.POINTER(P), ctypes.POINTER(I64)]),
+            "rpca_mlp_forward": (I32, [P, P, I32, P, P]),
+            "rpca_mlp_loss_grad": (I32, [P, P, P, P, I32, P, P]),
+            "rpca_mlp_adam_step": (I32, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, P]),
+            "rpca_mlp_train_step": (I32, [P, P, P, P, I32, ctypes.c_float, P, P]),
+            "rpca_mlp_destroy": (None, [P]),
+            "rpca_window_features": (I32, [P, I64, I64, I32, I32, P, P, P, P]),
+            "rpca_pool_rows": (I32, [P, I64, I64, I32, I32, P, P]),
+            "rpca_upsample_rows": (I32, [P, I64, I64, I32, I32, P, P]),
+            # batched instances (rpca_batch.h)
+            "rpca_batch_create": (I32, [I32, P, P, P, P, P, ctypes.POINTER(P)]),
+            "rpca_batch_objgrad": (I32, [P, P, P, P, P, P, P, I32, P]),
+            "rpca_batch_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), P, P]),
+            "rpca_batch_set_graphs": (I32, [P, I32]),
+            "rpca_batch_info": (I32, [P, ctypes.POINTER(rpca_batch_layout)]),
+            "rpca_batch_destroy": (None, [P]),
+            "rpca_autotune": (I32, [I64, I32, P]),
+            "rpca_tune_get": (I32, [I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+            "rpca_tune_set": (I32, [I32, I64, I32, I32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -167,3 +198,112 @@ def rpca_profile_read(ctx, reset=False):
     prof = rpca_profile()
     rc = lib().rpca_profile_read(ctx, ctypes.byref(prof), 1 if reset else 0)
     return rc, prof
+
+
+RPCA_MLP_W1, RPCA_MLP_B1, RPCA_MLP_W2, RPCA_MLP_B2 = 0, 1, 2, 3
+
+
+def rpca_mlp_create(d_in, d_h, mu, nv, k, max_batch, seed):
+    net = ctypes.c_void_p()
+    rc = lib().rpca_mlp_create(d_in, d_h, mu, nv, k, max_batch, seed, ctypes.byref(net))
+    return rc, net
+
+
+def rpca_mlp_param(net, which):
+    ptr, cnt = ctypes.c_void_p(), ctypes.c_int64()
+    rc = lib().rpca_mlp_param(net, which, ctypes.byref(ptr), ctypes.byref(cnt))
+    return rc, ptr.value, cnt.value
+
+
+def rpca_mlp_grad(net, which):
+    ptr, cnt = ctypes.c_void_p(), ctypes.c_int64()
+    rc = lib().rpca_mlp_grad(net, which, ctypes.byref(ptr), ctypes.byref(cnt))
+    return rc, ptr.value, cnt.value
+
+
+def rpca_mlp_forward(net, x, batch, y, stream=0):
+    return lib().rpca_mlp_forward(net, x, batch, y, stream)
+
+
+def rpca_mlp_loss_grad(net, x, TU, TV, batch, loss, stream=0):
+    return lib().rpca_mlp_loss_grad(net, x, TU, TV, batch, loss, stream)
+
+
+def rpca_mlp_adam_step(net, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=0):
+    return lib().rpca_mlp_adam_step(net, lr, beta1, beta2, eps, stream)
+
+
+def rpca_mlp_train_step(net, x, TU, TV, batch, lr, loss, stream=0):
+    return lib().rpca_mlp_train_step(net, x, TU, TV, batch, lr, loss, stream)
+
+
+def rpca_mlp_destroy(net):
+    lib().rpca_mlp_destroy(net)
+
+
+def rpca_window_features(X, width, height, frames, factor, shift, scale, feat, stream=0):
+    return lib().rpca_window_features(X, width, height, frames, factor, shift, scale, feat, stream)
+
+
+def rpca_pool_rows(A, width, height, factor, c, out, stream=0):
+    return lib().rpca_pool_rows(A, width, height, factor, c, out, stream)
+
+
+def rpca_upsample_rows(A, width, height, factor, c, out, stream=0):
+    return lib().rpca_upsample_rows(A, width, height, factor, c, out, stream)
+
+
+def _ptr_array(ptrs, ctype=ctypes.c_void_p):
+    return (ctype * len(ptrs))(*ptrs)
+
+
+def rpca_batch_create(m, n, k, lam_s, lam_l):
+    """Sequences of per-instance sizes and weights.  Returns (status, batch)."""
+    cnt = len(m)
+    b = ctypes.c_void_p()
+    rc = lib().rpca_batch_create(cnt, (ctypes.c_int64 * cnt)(*m), (ctypes.c_int64 * cnt)(*n),
+                                 (ctypes.c_int32 * cnt)(*k), (ctypes.c_double * cnt)(*lam_s),
+                                 (ctypes.c_double * cnt)(*lam_l), ctypes.byref(b))
+    return rc, b
+
+
+def rpca_batch_objgrad(b, X, U, V, f, gU, gV, precision=0, stream=0):
+    """X, U, V, f, gU, gV: sequences of device pointers (ints)."""
+    return lib().rpca_batch_objgrad(b, _ptr_array(X), _ptr_array(U), _ptr_array(V), _ptr_array(f),
+                                    _ptr_array(gU), _ptr_array(gV), precision, stream)
+
+
+def rpca_batch_solve(b, X, U, V, opts=None, stream=0):
+    cnt = len(X)
+    infos = (rpca_info * cnt)()
+    rc = lib().rpca_batch_solve(b, _ptr_array(X), _ptr_array(U), _ptr_array(V),
+                                ctypes.byref(opts) if opts is not None else None, infos, stream)
+    return rc, list(infos)
+
+
+def rpca_batch_set_graphs(b, on):
+    return lib().rpca_batch_set_graphs(b, 1 if on else 0)
+
+
+def rpca_batch_info(b):
+    out = rpca_batch_layout()
+    rc = lib().rpca_batch_info(b, ctypes.byref(out))
+    return rc, out
+
+
+def rpca_batch_destroy(b):
+    lib().rpca_batch_destroy(b)
+
+
+def rpca_autotune(m_probe=16384, reps=10, stream=0):
+    return lib().rpca_autotune(m_probe, reps, stream)
+
+
+def rpca_tune_get(k, n):
+    w, d = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().rpca_tune_get(k, n, ctypes.byref(w), ctypes.byref(d))
+    return rc, w.value, d.value
+
+
+def rpca_tune_set(k, n, target_waves, chunk_div):
+    return lib().rpca_tune_set(k, n, target_waves, chunk_div)

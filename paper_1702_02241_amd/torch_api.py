@@ -80,3 +80,175 @@ class Context:
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_init_rsvd failed: {R.rpca_status_string(rc)}")
         return U, V
+
+
+class WarmNet:
+    """Owns an rpca_mlp (rpca_warm.h): the 2-layer warm-start network."""
+
+    def __init__(self, d_in, d_h, mu, nv, k, max_batch=64, seed=0):
+        rc, self.net = R.rpca_mlp_create(d_in, d_h, mu, nv, k, max_batch, seed)
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_mlp_create failed: {R.rpca_status_string(rc)}")
+        self.d_in, self.d_h, self.mu, self.nv, self.k = d_in, d_h, mu, nv, k
+        self.d_out = (mu + nv) * k
+        self.max_batch = max_batch
+
+    def close(self):
+        if self.net:
+            R.rpca_mlp_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, W1, b1, W2, b2):
+        """Overwrite the parameters from host arrays (float32 copies)."""
+        for which, arr in enumerate((W1, b1, W2, b2)):
+            rc, ptr, cnt = R.rpca_mlp_param(self.net, which)
+            a = np.ascontiguousarray(np.asarray(arr, np.float32)).reshape(-1)
+            if a.size != cnt:
+                raise ValueError("parameter shape mismatch")
+            _copy_host_to_device(ptr, a)
+
+    def params(self):
+        return [_copy_device_to_host(*R.rpca_mlp_param(self.net, w)[1:]) for w in range(4)]
+
+    def grads(self):
+        return [_copy_device_to_host(*R.rpca_mlp_grad(self.net, w)[1:]) for w in range(4)]
+
+    def forward(self, x):
+        y = torch.empty(x.shape[0], self.d_out, dtype=torch.float32, device=x.device)
+        rc = R.rpca_mlp_forward(self.net, x.data_ptr(), x.shape[0], y.data_ptr(), _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_mlp_forward failed: {R.rpca_status_string(rc)}")
+        return y
+
+    def loss_grad(self, x, TU, TV):
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        rc = R.rpca_mlp_loss_grad(self.net, x.data_ptr(), TU.data_ptr(), TV.data_ptr(), x.shape[0],
+                                  loss.data_ptr(), _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_mlp_loss_grad failed: {R.rpca_status_string(rc)}")
+        return loss
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        rc = R.rpca_mlp_adam_step(self.net, lr, beta1, beta2, eps, _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_mlp_adam_step failed: {R.rpca_status_string(rc)}")
+
+    def train_step(self, x, TU, TV, lr):
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        rc = R.rpca_mlp_train_step(self.net, x.data_ptr(), TU.data_ptr(), TV.data_ptr(), x.shape[0], lr,
+                                   loss.data_ptr(), _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_mlp_train_step failed: {R.rpca_status_string(rc)}")
+        return loss
+
+
+def _hip():
+    """The HIP runtime already loaded by torch and librpca (same soname)."""
+    import ctypes
+    h = ctypes.CDLL("libamdhip64.so.7")
+    h.hipMemcpy.restype = ctypes.c_int
+    h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return h
+
+
+def _copy_host_to_device(ptr, a):
+    """Copy a contiguous float32 host array into library-owned device memory (synchronous)."""
+    torch.cuda.synchronize()
+    if _hip().hipMemcpy(ptr, a.ctypes.data, a.nbytes, 1) != 0:
+        raise RuntimeError("hipMemcpy host->device failed")
+
+
+def _copy_device_to_host(ptr, count):
+    torch.cuda.synchronize()
+    out = np.empty(count, np.float32)
+    if _hip().hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2) != 0:
+        raise RuntimeError("hipMemcpy device->host failed")
+    return out
+
+
+def window_features(Xcm_window, width, height, frames, factor, shift=None, scale=None):
+    """Features of one window: Xcm_window is a (frames, width*height) contiguous
+    device tensor (column-major X of the window).  Returns a d_in device vector."""
+    mu = (width // factor) * (height // factor)
+    feat = torch.empty(2 * mu + frames, dtype=torch.float32, device=Xcm_window.device)
+    rc = R.rpca_window_features(Xcm_window.data_ptr(), width, height, frames, factor,
+                                shift.data_ptr() if shift is not None else None,
+                                scale.data_ptr() if scale is not None else None, feat.data_ptr(), _stream())
+    if rc != R.RPCA_OK:
+        raise RuntimeError(f"rpca_window_features failed: {R.rpca_status_string(rc)}")
+    return feat
+
+
+def pool_rows(A, width, height, factor):
+    c = A.shape[1]
+    out = torch.empty((width // factor) * (height // factor), c, dtype=torch.float32, device=A.device)
+    rc = R.rpca_pool_rows(A.data_ptr(), width, height, factor, c, out.data_ptr(), _stream())
+    if rc != R.RPCA_OK:
+        raise RuntimeError(f"rpca_pool_rows failed: {R.rpca_status_string(rc)}")
+    return out
+
+
+def upsample_rows(A, width, height, factor):
+    c = A.shape[1]
+    out = torch.empty(width * height, c, dtype=torch.float32, device=A.device)
+    rc = R.rpca_upsample_rows(A.data_ptr(), width, height, factor, c, out.data_ptr(), _stream())
+    if rc != R.RPCA_OK:
+        raise RuntimeError(f"rpca_upsample_rows failed: {R.rpca_status_string(rc)}")
+    return out
+
+
+class Batch:
+    """Owns an rpca_batch (rpca_batch.h) for a list of fully observed instances."""
+
+    def __init__(self, shapes, lam_s, lam_l):
+        """shapes: list of (m, n, k); lam_s, lam_l: sequences of per-instance weights."""
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        m, n, k = zip(*self.shapes)
+        rc, self.b = R.rpca_batch_create(m, n, k, list(lam_s), list(lam_l))
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_batch_create failed: {R.rpca_status_string(rc)}")
+
+    def close(self):
+        if self.b:
+            R.rpca_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graphs(self, on):
+        R.rpca_batch_set_graphs(self.b, on)
+
+    def layout(self):
+        return R.rpca_batch_info(self.b)[1]
+
+    def objgrad(self, Xs, Us, Vs, precision=R.RPCA_PREC_FP32):
+        dev = Us[0].device
+        fs = [torch.empty(1, dtype=torch.float64, device=dev) for _ in Us]
+        gUs = [torch.empty_like(U) for U in Us]
+        gVs = [torch.empty_like(V) for V in Vs]
+        rc = R.rpca_batch_objgrad(self.b, [x.data_ptr() for x in Xs], [u.data_ptr() for u in Us],
+                                  [v.data_ptr() for v in Vs], [f.data_ptr() for f in fs],
+                                  [g.data_ptr() for g in gUs], [g.data_ptr() for g in gVs], precision, _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_batch_objgrad failed: {R.rpca_status_string(rc)}")
+        return fs, gUs, gVs
+
+    def solve(self, Xs, Us, Vs, **opts):
+        o = R.default_opts()
+        for key, val in opts.items():
+            setattr(o, key, val)
+        rc, infos = R.rpca_batch_solve(self.b, [x.data_ptr() for x in Xs], [u.data_ptr() for u in Us],
+                                       [v.data_ptr() for v in Vs], o, _stream())
+        if rc < 0:
+            raise RuntimeError(f"rpca_batch_solve failed: {R.rpca_status_string(rc)}")
+        return rc, infos

@@ -10,17 +10,21 @@ from paper_1702_02241_amd import rpca as R
 
 
 def _declared_symbols():
-    text = open(R.HEADER_PATH).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rpca_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for path in R.HEADER_PATHS:
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(rpca_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     L = R.lib()
     names = _declared_symbols()
     assert "rpca_create" in names and "rpca_solve" in names and "rpca_certificate" in names
+    assert "rpca_mlp_train_step" in names and "rpca_window_features" in names
     for name in names:
-        assert hasattr(L, name), f"{name} declared in rpca.h but not exported"
+        assert hasattr(L, name), f"{name} declared in a header but not exported"
 
 
 def test_default_opts():
@@ -67,3 +71,48 @@ def test_struct_layouts_match_header_order():
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"(\w+)(?:\[\d+\])?\s*[;,]", body)
         assert [f for f, _ in cls._fields_] == fields
+
+
+def test_warm_start_entry_points_reject_bad_arguments_before_hip():
+    P = ctypes.c_void_p
+    net = P()
+    L = R.lib()
+    assert L.rpca_mlp_create(0, 8, 4, 4, 2, 4, 0, ctypes.byref(net)) == R.RPCA_EINVAL
+    assert L.rpca_mlp_create(8, 8, 4, 4, 33, 4, 0, ctypes.byref(net)) == R.RPCA_EINVAL   # k > 32
+    assert L.rpca_mlp_create(8, 8, 4, 4, 2, 0, 0, ctypes.byref(net)) == R.RPCA_EINVAL    # batch bound
+    assert L.rpca_mlp_create(8, 8, 4, 4, 2, 4097, 0, ctypes.byref(net)) == R.RPCA_EINVAL
+    assert not net.value
+    assert R.rpca_mlp_forward(None, 1, 1, 1) == R.RPCA_EINVAL
+    assert R.rpca_mlp_loss_grad(None, 1, 1, 1, 1, 1) == R.RPCA_EINVAL
+    assert R.rpca_mlp_adam_step(None, 1e-3) == R.RPCA_EINVAL
+    assert R.rpca_mlp_param(None, 0)[0] == R.RPCA_EINVAL
+    # factor must divide the frame; shift and scale come together
+    assert R.rpca_window_features(1, 10, 8, 3, 3, None, None, 1) == R.RPCA_EINVAL
+    assert R.rpca_window_features(1, 12, 8, 3, 4, 1, None, 1) == R.RPCA_EINVAL
+    assert R.rpca_pool_rows(1, 10, 8, 4, 2, 1) == R.RPCA_EINVAL
+    assert R.rpca_upsample_rows(1, 12, 8, 4, 0, 1) == R.RPCA_EINVAL
+    R.rpca_mlp_destroy(None)
+
+
+def test_tune_table_round_trip_and_bounds():
+    rc, w, d = R.rpca_tune_get(10, 200)
+    assert rc == R.RPCA_OK and w >= 64 and d >= 1
+    assert R.rpca_tune_set(10, 200, 4096, 2) == R.RPCA_OK
+    assert R.rpca_tune_get(12, 250)[1:] == (4096, 2)      # same (k, n) bucket
+    assert R.rpca_tune_get(10, 600)[1:] == (w, d)         # other bucket untouched
+    assert R.rpca_tune_set(10, 200, w, d) == R.RPCA_OK
+    assert R.rpca_tune_set(33, 200, 2048, 1) == R.RPCA_EINVAL
+    assert R.rpca_tune_set(10, 200, 8, 1) == R.RPCA_EINVAL
+    assert R.rpca_autotune(8, 10) == R.RPCA_EINVAL
+
+
+def test_batch_entry_points_reject_bad_arguments_before_hip():
+    rc, b = R.rpca_batch_create([100, 50], [20, 10], [5, 11], [0.1, 0.1], [1.0, 1.0])   # k > n
+    assert rc == R.RPCA_EINVAL and not b.value
+    rc, b = R.rpca_batch_create([100], [20], [5], [0.0], [1.0])
+    assert rc == R.RPCA_EINVAL
+    assert R.rpca_batch_objgrad(None, [1], [1], [1], [1], [1], [1]) == R.RPCA_EINVAL
+    rc, _ = R.rpca_batch_solve(None, [1], [1], [1])
+    assert rc == R.RPCA_EINVAL
+    assert R.rpca_batch_set_graphs(None, 1) == R.RPCA_EINVAL
+    R.rpca_batch_destroy(None)

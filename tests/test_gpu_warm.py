@@ -1,0 +1,141 @@
+"""GPU parity of the warm-start kernels (rpca_warm.h) against the FP64 oracle
+(oracle/mlp.py): window statistics, row pooling and upsampling, the MLP
+forward pass, the loss and all four gradients, and Adam.
+
+Bars: FP32 MFMA GEMMs with FP32 accumulation over K up to ~10^4, so the
+relative Frobenius error of forward outputs and gradients is held to 1e-5
+(typical measured values are printed); pooling and upsampling are exact up to
+FP32 rounding of a mean (1e-6); Adam is elementwise FP32 (1e-6 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as om
+from paper_1702_02241_amd import synth
+from paper_1702_02241_amd import torch_api as T
+
+from gpu_common import device, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _net_case(B, din, dh, mu, nv, k, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(B, din)).astype(np.float32)
+    W1 = (rng.normal(size=(din, dh)) * np.sqrt(2.0 / din)).astype(np.float32)
+    b1 = (rng.normal(size=dh) * 0.1).astype(np.float32)
+    W2 = (rng.normal(size=(dh, (mu + nv) * k)) * np.sqrt(2.0 / dh)).astype(np.float32)
+    b2 = (rng.normal(size=(mu + nv) * k) * 0.1).astype(np.float32)
+    TU = rng.normal(size=(B, mu, k)).astype(np.float32)
+    TV = rng.normal(size=(B, nv, k)).astype(np.float32)
+    return x, W1, b1, W2, b2, TU, TV
+
+
+@pytest.mark.parametrize("B,din,dh,mu,nv,k", [
+    (4, 37, 19, 11, 7, 3),         # everything ragged, below one tile
+    (16, 300, 96, 120, 40, 10),    # several tiles
+    (64, 2500, 512, 300, 100, 10), # hidden layer of the full network, split-K paths
+    (3, 70, 130, 50, 9, 32),       # largest k
+])
+def test_mlp_forward_and_gradients_match_oracle(B, din, dh, mu, nv, k):
+    dev = device()
+    x, W1, b1, W2, b2, TU, TV = _net_case(B, din, dh, mu, nv, k, seed=B + din)
+    net = T.WarmNet(din, dh, mu, nv, k, max_batch=max(B, 8), seed=1)
+    net.set_params(W1, b1, W2, b2)
+    xd = torch.from_numpy(x).to(dev)
+    y = net.forward(xd)
+    torch.cuda.synchronize()
+    _, _, yr = om.forward(x.astype(np.float64), W1.astype(np.float64), b1.astype(np.float64),
+                          W2.astype(np.float64), b2.astype(np.float64))
+    ey = rel(y.cpu().numpy(), yr)
+    TUd, TVd = torch.from_numpy(TU).to(dev), torch.from_numpy(TV).to(dev)
+    loss = net.loss_grad(xd, TUd, TVd)
+    torch.cuda.synchronize()
+    T_dense = np.einsum("bik,bjk->bij", TU.astype(np.float64), TV.astype(np.float64))
+    lr_, dW1, db1, dW2, db2 = om.loss_grad(x.astype(np.float64), T_dense, W1.astype(np.float64),
+                                           b1.astype(np.float64), W2.astype(np.float64),
+                                           b2.astype(np.float64), mu, nv, k)
+    el = abs(float(loss.item()) - lr_) / abs(lr_)
+    g = net.grads()
+    errs = [rel(g[0].reshape(din, dh), dW1), rel(g[1], db1), rel(g[2].reshape(dh, -1), dW2), rel(g[3], db2)]
+    print(f"[mlp B={B} din={din} dh={dh} mu={mu} nv={nv} k={k}] y rel {ey:.2e} loss rel {el:.2e} "
+          f"dW1 {errs[0]:.2e} db1 {errs[1]:.2e} dW2 {errs[2]:.2e} db2 {errs[3]:.2e}")
+    assert ey <= 1e-5
+    assert el <= 1e-5
+    assert max(errs) <= 1e-5
+    net.close()
+
+
+def test_mlp_gradients_bitwise_deterministic():
+    dev = device()
+    x, W1, b1, W2, b2, TU, TV = _net_case(32, 1200, 256, 200, 50, 10, seed=3)
+    net = T.WarmNet(1200, 256, 200, 50, 10, max_batch=32, seed=1)
+    net.set_params(W1, b1, W2, b2)
+    xd, TUd, TVd = (torch.from_numpy(a).to(dev) for a in (x, TU, TV))
+    l1 = net.loss_grad(xd, TUd, TVd).item()
+    g1 = net.grads()
+    l2 = net.loss_grad(xd, TUd, TVd).item()
+    g2 = net.grads()
+    assert l1 == l2
+    assert all(np.array_equal(a, b) for a, b in zip(g1, g2))
+    net.close()
+
+
+def test_adam_steps_match_oracle():
+    dev = device()
+    B, din, dh, mu, nv, k = 8, 50, 32, 20, 6, 4
+    x, W1, b1, W2, b2, TU, TV = _net_case(B, din, dh, mu, nv, k, seed=9)
+    net = T.WarmNet(din, dh, mu, nv, k, max_batch=B, seed=1)
+    net.set_params(W1, b1, W2, b2)
+    xd, TUd, TVd = (torch.from_numpy(a).to(dev) for a in (x, TU, TV))
+    P = [a.astype(np.float64).reshape(-1) for a in (W1, b1, W2, b2)]
+    M = [np.zeros_like(p) for p in P]
+    Vm = [np.zeros_like(p) for p in P]
+    for t in range(1, 4):
+        net.loss_grad(xd, TUd, TVd)
+        G = [g.astype(np.float64) for g in net.grads()]   # the GPU's gradients at the GPU's iterate
+        Pg = net.params()
+        net.adam_step(1e-2)
+        after = net.params()
+        for i in range(4):
+            # one oracle step from the GPU's own parameters and moments path
+            p_new, M[i], Vm[i] = om.adam_step(Pg[i].astype(np.float64), G[i], M[i], Vm[i], t, lr=1e-2)
+            e = rel(after[i], p_new)
+            assert e <= 1e-6, (t, i, e)
+    print("[adam] three steps match")
+    net.close()
+
+
+@pytest.mark.parametrize("W,H,f,frames", [(320, 240, 4, 100), (40, 24, 4, 7), (30, 18, 3, 5)])
+def test_window_features_match_oracle(W, H, f, frames):
+    dev = device()
+    X, _, _ = synth.video_frames(n_frames=frames, width=W, height=H, seed=11)
+    Xcm = torch.from_numpy(np.ascontiguousarray(X.T.astype(np.float32))).to(dev)
+    feat = T.window_features(Xcm, W, H, frames, f)
+    ref = om.window_features(X.astype(np.float32).astype(np.float64), W, H, f)
+    e = rel(feat.cpu().numpy(), ref)
+    em = float(np.max(np.abs(feat.cpu().numpy() - ref)))
+    print(f"[features {W}x{H}/{f} frames={frames}] rel {e:.2e} max abs {em:.2e}")
+    assert e <= 1e-6 and em <= 1e-6
+    # with a normalisation
+    rng = np.random.default_rng(0)
+    shift = rng.normal(size=ref.size).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, size=ref.size).astype(np.float32)
+    feat2 = T.window_features(Xcm, W, H, frames, f, torch.from_numpy(shift).to(dev),
+                              torch.from_numpy(scale).to(dev))
+    ref2 = (ref - shift) * scale
+    assert rel(feat2.cpu().numpy(), ref2) <= 1e-6
+
+
+@pytest.mark.parametrize("W,H,f,c", [(320, 240, 4, 10), (12, 8, 2, 3), (9, 6, 3, 1)])
+def test_pool_and_upsample_match_oracle(W, H, f, c):
+    dev = device()
+    rng = np.random.default_rng(W + c)
+    A = rng.normal(size=(W * H, c)).astype(np.float32)
+    P = T.pool_rows(torch.from_numpy(A).to(dev), W, H, f)
+    Pr = om.downsample_rows(A.astype(np.float64), W, H, f)
+    assert rel(P.cpu().numpy(), Pr) <= 1e-6
+    Up = T.upsample_rows(torch.from_numpy(Pr.astype(np.float32)).to(dev), W, H, f)
+    Ur = om.upsample_rows(Pr.astype(np.float32).astype(np.float64), W, H, f)
+    assert np.array_equal(Up.cpu().numpy(), Ur.astype(np.float32))
