@@ -69,16 +69,24 @@ typedef struct rpca_opts {
   int32_t max_iter;         /* L-BFGS iterations, default 5000 */
   int32_t init;             /* rpca_init, default RPCA_INIT_GIVEN */
   double gtol;              /* stop: ||g||_inf <= gtol * max(1,|f|), default 1e-6 */
-  double ftol;              /* stop: relative f decrease over 5 iterations < ftol, default 1e-9 */
+  double ftol;              /* stop: relative f decrease over 5 iterations < ftol, default 1e-9;
+                               0 switches the test off (certification rounds always do) */
   double bf16_gtol;         /* BF16 phase tolerance before the FP32 polish, default 1e-3 */
   double c1, c2;            /* strong-Wolfe constants, default 1e-4, 0.9 */
-  int32_t certify;          /* 1: run the certificate at the end and tighten gtol until
-                               rel_gap <= cert_tol (at most 4 rounds); default 1 */
+  int32_t certify;          /* 1 (default): run the certificate at the end; while rel_gap > cert_tol
+                               continue from the point reached (one more preconditioner cycle
+                               with the stopping tests off, or a tenfold tighter gtol in plain
+                               variables) and certify again, at most 8 certificates */
   double cert_tol;          /* certified threshold on gap/F, default 1e-3 */
   int32_t rsvd_oversample;  /* p, default 10 */
   int32_t rsvd_power;       /* q, default 2 */
   uint64_t seed;            /* seed of the counter-based generator (rSVD sketch, power start) */
   int32_t slots_per_sync;   /* line-search trials per host poll, default 16 */
+  int32_t precond;          /* 1 (default): iterate on A = U P_U^{-1}, B = V P_V^{-1} with
+                               P_U = (V^T V + lam_L I)^{-1/2}, P_V = (U^T U + lam_L I)^{-1/2},
+                               refreshed every precond_cycle iterations (same minimisers;
+                               far fewer iterations for ill-conditioned factors); 0: plain */
+  int32_t precond_cycle;    /* iterations per preconditioner refresh, default 50 */
 } rpca_opts;
 
 typedef struct rpca_info {

@@ -5,10 +5,11 @@
  * Each instance is the problem of rpca.h (f(U,V) = phi(U V^T) +
  * lam_L/2 (||U||^2 + ||V||^2), Sec. 1 eq. PhiDef and eq. smoothNC; L-BFGS with
  * memory `mem`, Sec. 5.1; certificate of Sec. 3.4), fully observed.  The
- * batch runs every solver step as ONE launch for all instances: a persistent
- * sweep kernel pulls (instance, row group, column chunk) items from a queue
- * sorted by decreasing cost, and the reductions and L-BFGS passes cover all
- * instances in one grid each.  Instances that have converged skip every
+ * batch runs every solver step as one launch for all instances: the
+ * reductions and L-BFGS passes cover all instances in one grid each, and the
+ * sweep is one persistent kernel per tile class (k <= 16 or <= 32, tiles per
+ * column chunk) present in the batch, pulling (instance, row group, column
+ * chunk) items from a queue sorted by decreasing cost.  Instances that have converged skip every
  * kernel.  Groups of solver slots are captured once in a hipGraph and
  * replayed until all instances are done; certificates then run per instance.
  *
@@ -35,10 +36,11 @@ typedef struct rpca_batch rpca_batch;
 typedef struct rpca_batch_layout {
   int32_t count;            /* instances */
   int32_t sweep_items;      /* (instance, row group, chunk) items of one sweep */
-  int32_t sweep_grid_fp32;  /* persistent workgroups of the FP32 sweep */
-  int32_t sweep_grid_bf16;  /* persistent workgroups of the BF16 sweep */
-  int32_t lds_bytes;        /* dynamic LDS per workgroup of the sweep */
+  int32_t sweep_grid_fp32;  /* persistent workgroups of the FP32 sweeps (all classes) */
+  int32_t sweep_grid_bf16;  /* persistent workgroups of the BF16 sweeps (all classes) */
+  int32_t lds_bytes;        /* largest dynamic LDS per workgroup of a sweep */
   int32_t graphs;           /* captured slot groups so far */
+  int32_t sweep_classes;    /* persistent sweep launches per pass (one per tile class) */
 } rpca_batch_layout;
 
 /* Create a batch of `count` (1..65536) instances; m, n, k, lam_s, lam_l are

@@ -9,49 +9,10 @@
 #include <new>
 #include <vector>
 
+#include "ctx.h"
 #include "rpca_internal.h"
 #include "smalllinalg.h"
 
-struct rpca_ctx {
-  int64_t m = 0, n = 0;
-  int k = 0;
-  double lam_s = 0, lam_l = 0;
-  uint32_t* mask = nullptr;  // device bitmask or null
-  int mw = 0;
-  // sweep configuration
-  int row_groups = 0, spw = 0, chunk_w = 0, nchunks = 0, sweep_wgs = 0, segs = 0, rps = 16;
-  float* gvpart = nullptr;
-  float* gupart = nullptr;
-  double* spart = nullptr;
-  double* fpart = nullptr;
-  double* level2 = nullptr;
-  unsigned int* counters = nullptr;  // [0] finish, [1] update, [2] direction, [3..] spare
-  // solver workspace
-  int64_t N = 0;  // (m + n) k padded to a multiple of 256
-  float* x[2] = {nullptr, nullptr};
-  float* g[2] = {nullptr, nullptr};
-  float* d = nullptr;
-  float* S = nullptr;
-  float* Y = nullptr;
-  double* lpart = nullptr;
-  SolverState* st = nullptr;       // device
-  SolverState* st_host = nullptr;  // pinned host mirror
-  double* dscratch = nullptr;      // device doubles for small results
-  double best_F = INFINITY;        // best convex objective seen by certificates
-  // certificate / rSVD workspace (allocated on first use)
-  void* cert_ws = nullptr;
-  size_t cert_ws_bytes = 0;
-  // optional per-launch timing
-  struct Pending {
-    int cls;
-    hipEvent_t a, b;
-  };
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev_free;
-  std::vector<Pending> pending;
-  int64_t prof_launches[RPCA_K_NCLASS] = {0};
-  double prof_ms[RPCA_K_NCLASS] = {0};
-};
 
 namespace {
 
@@ -86,7 +47,8 @@ SweepArgs make_sweep_args(const rpca_ctx* c, const float* X) {
   a.mw = c->mw;
   a.lam_s = (float)c->lam_s;
   a.lam_l = (float)c->lam_l;
-  a.xvec = (c->m % 4 == 0) && (((uintptr_t)X & 15u) == 0);
+  // vector (buffer) loads: 16-byte aligned columns, lane offsets within 32 bits
+  a.xvec = (c->m % 4 == 0) && (((uintptr_t)X & 15u) == 0) && c->m < ((int64_t)1 << 26);
   a.gupart = c->gupart;
   a.gvpart = c->gvpart;
   a.spart = c->spart;
@@ -134,6 +96,8 @@ void solver_views(const rpca_ctx* c, SweepArgs* sa, FinishArgs* fa, LbfgsArgs* l
   sa->dU = c->d;
   sa->dV = c->d + mk;
   sa->st = c->st;
+  sa->pc = c->pc_on ? c->pc_dev : nullptr;
+  fa->pc = sa->pc;
   fa->dU = c->d;
   fa->dV = c->d + mk;
   fa->st = c->st;
@@ -229,6 +193,8 @@ void rpca_default_opts(rpca_opts* o) {
   o->precision = RPCA_PREC_FP32;
   o->mem = 10;
   o->max_iter = 5000;
+  o->precond = 1;
+  o->precond_cycle = 50;
   o->init = RPCA_INIT_GIVEN;
   o->gtol = 1e-6;
   o->ftol = 1e-9;
@@ -276,6 +242,8 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->lpart);
   dfree(c->st);
   dfree(c->dscratch);
+  dfree(c->pc_dev);
+  dfree(c->pc_gram);
   dfree(c->cert_ws);
   if (c->st_host) (void)hipHostFree(c->st_host);
   prof_collect(c);
@@ -345,6 +313,8 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, con
   TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 1024));
   TRY(dalloc(&c->st, 1));
   TRY(dalloc(&c->dscratch, 64));
+  TRY(dalloc(&c->pc_dev, (size_t)7 * k * k));
+  TRY(dalloc(&c->pc_gram, (size_t)rpca::PC_GRAM_BLOCKS * k * k));
   void* hp = nullptr;
   if (hipHostMalloc(&hp, sizeof(SolverState), hipHostMallocDefault) != hipSuccess) {
     rpca_destroy(c);
@@ -426,6 +396,8 @@ int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V,
   return RPCA_OK;
 }
 
+SolverState* ctx_state_host(rpca_ctx* c) { return c->st_host; }
+
 void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
   *fresh = 0;
   if (c->cert_ws && c->cert_ws_bytes >= bytes) return c->cert_ws;
@@ -482,6 +454,8 @@ int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s)
   fa.gU[0] = fa.gU[1] = c->g[cur];
   fa.gV[0] = fa.gV[1] = c->g[cur] + mk;
   fa.f_out = &c->st->f;
+  sa.pc = c->pc_on ? c->pc_dev : nullptr;
+  fa.pc = sa.pc;
   HIPCHK(objgrad_launch(c, sa, fa, false, bf16, s));
   return RPCA_OK;
 }
@@ -489,6 +463,12 @@ int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s)
 // Restart the device loop from the current iterate after a phase change:
 // keep the L-BFGS memory, clear the stop flag and the f history.
 int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
+  return restart_state(c, gtol, ftol, -1, false, s);
+}
+
+// Restart with an iteration cap (max_iter < 0: keep it) and optionally an empty
+// memory (after a change of variables the stored pairs no longer apply).
+int restart_state(rpca_ctx* c, double gtol, double ftol, int max_iter, bool reset_memory, hipStream_t s) {
   SolverState* h = c->st_host;
   HIPCHK(hipMemcpyAsync(h, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -497,9 +477,43 @@ int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s) {
   h->gtol = gtol;
   h->ftol = ftol;
   h->restarted = 0;
+  if (max_iter >= 0) h->max_iter = max_iter;
+  if (reset_memory) {
+    // the first step after a restart is 1 (first_iter stays as it was: only the
+    // very first iteration of a solve scales its step by 1/||g||_1)
+    h->count = 0;
+    h->newest = -1;
+    h->spare = 0;
+  }
   for (int i = 0; i < 8; ++i) h->fhist[i] = INFINITY;
   HIPCHK(hipMemcpyAsync(c->st, h, sizeof(SolverState), hipMemcpyHostToDevice, s));
   return RPCA_OK;
+}
+
+// One solver phase from the plain iterate in x[cur]: in preconditioned
+// variables, cycles of o.precond_cycle iterations, each with a preconditioner
+// refreshed from the current point and an empty memory; plain, one cycle that
+// keeps the memory.  Ends with x[cur] plain again.
+int run_cycles(rpca_ctx* c, const float* X, const rpca_opts& o, bool bf16, double gtol, double ftol,
+               bool keep_memory, int budget, hipStream_t s) {
+  int rc;
+  const int it0 = c->st_host->iter;
+  const int limit = (budget > 0 && o.max_iter - it0 > budget) ? it0 + budget : o.max_iter;
+  for (;;) {
+    const int cur = c->st_host->cur;
+    int cap = limit;
+    if (o.precond) {
+      if ((rc = precond_refresh(c, cur, s))) return rc;
+      const int it = c->st_host->iter;
+      cap = (limit - it > o.precond_cycle) ? it + o.precond_cycle : limit;
+    }
+    if ((rc = restart_state(c, gtol, ftol, cap, o.precond || !keep_memory, s))) return rc;
+    if ((rc = eval_current(c, X, cur, bf16, s))) return rc;
+    if ((rc = run_lbfgs(c, X, &o, bf16, s))) return rc;
+    const SolverState* h = c->st_host;
+    if (!(o.precond && h->stop == STOP_MAXITER && h->iter < limit)) break;
+  }
+  return precond_to_plain(c, c->st_host->cur, s);
 }
 
 // Everything a batched launch needs to run this context's solver slots:
@@ -527,11 +541,13 @@ void instance_args(rpca_ctx* c, const float* X, int cur, InstanceArgs* out) {
   fa.gU[0] = fa.gU[1] = c->g[cur];
   fa.gV[0] = fa.gV[1] = c->g[cur] + mk;
   fa.f_out = &c->st->f;
+  sa.pc = c->pc_on ? c->pc_dev : nullptr;
+  fa.pc = sa.pc;
   int gvb = 0;
   out->fin2_blocks = finish_blocks(c->m, c->n, c->k, c->nchunks, &gvb);
   out->fa_loop.gv_blocks = gvb;
   out->fa_eval.gv_blocks = gvb;
-  out->fin1_blocks = gvb * c->segs;
+  out->fin1_blocks = (int)((c->n * c->k + 255) / 256) * c->segs;  // reduce1: 256 elements per block
   out->lb_blocks = lbfgs_blocks(c->N);
   out->row_groups = c->row_groups;
   out->nchunks = c->nchunks;
@@ -549,7 +565,8 @@ namespace rpca {
 bool valid_opts(const rpca_opts& o) {
   return !(o.mem < 1 || o.mem > RPCA_MEMMAX - 1 || o.max_iter < 0 || !(o.c1 > 0) || !(o.c2 > o.c1) ||
            !(o.c2 < 1) || !(o.gtol >= 0) || !(o.ftol >= 0) || o.precision < 0 || o.precision > 2 ||
-           !(o.bf16_gtol >= 0) || !(o.cert_tol > 0));
+           !(o.bf16_gtol >= 0) || !(o.cert_tol > 0) || o.precond < 0 || o.precond > 1 ||
+           (o.precond && o.precond_cycle < 1));
 }
 
 int solve_phases(const rpca_opts& o, SolvePhase* ph) {
@@ -619,12 +636,22 @@ int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opt
     ++rounds;
     rel_gap = cert.rel_gap;
     certified = rel_gap <= o.cert_tol;
-    if (certified || stop == STOP_MAXITER || rounds >= 5) break;
-    // not certified yet: tighten the stopping tests and continue from here
-    gtol *= 0.1;
-    ftol *= 0.01;
-    if ((rc = resume_state(c, gtol, ftol, s))) return rc;
-    if ((rc = run_lbfgs(c, X, &o, final_bf16, s))) return rc;
+    if (certified || stop == STOP_MAXITER || rounds >= 8) break;
+    // Not certified yet: continue from here.  Near the optimum f changes by less
+    // than its FP32 evaluation noise per iteration while the gradient still
+    // carries the structure the certificate measures, so the round runs with
+    // the stopping tests off, for one preconditioner cycle (plain variables: a
+    // tenfold tighter gradient test), and ends at the cycle's cap or when the
+    // line search can no longer make progress.
+    if (o.precond) {
+      gtol = 0.0;
+      ftol = 0.0;
+    } else {
+      gtol *= 0.1;
+      ftol = 0.0;
+    }
+    if ((rc = run_cycles(c, X, o, final_bf16, gtol, ftol, true, o.precond ? o.precond_cycle : 0, s))) return rc;
+    if (c->st_host->stop == STOP_MAXITER && c->st_host->iter < o.max_iter) c->st_host->stop = STOP_GTOL;
   }
   HIPCHK(hipStreamSynchronize(s));
   const SolverState fin = *c->st_host;
@@ -671,15 +698,12 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   const int nph = rpca::solve_phases(o, phases);
   int rc = rpca::solve_setup(c, X, U, V, o, phases[0].gtol, s);
   if (rc) return rc;
-  if ((rc = rpca::eval_current(c, X, 0, phases[0].bf16, s))) return rc;
-  if ((rc = rpca::run_lbfgs(c, X, &o, phases[0].bf16, s))) return rc;
+  if ((rc = rpca::run_cycles(c, X, o, phases[0].bf16, phases[0].gtol, o.ftol, true, 0, s))) return rc;
   int iters_bf16 = phases[0].bf16 ? c->st_host->iter : 0;
   bool final_bf16 = phases[0].bf16;
   for (int ph = 1; ph < nph; ++ph) {
     if (c->st_host->stop == STOP_NONFINITE || c->st_host->stop == STOP_MAXITER) break;
-    if ((rc = rpca::resume_state(c, phases[ph].gtol, o.ftol, s))) return rc;
-    if ((rc = rpca::eval_current(c, X, c->st_host->cur, phases[ph].bf16, s))) return rc;
-    if ((rc = rpca::run_lbfgs(c, X, &o, phases[ph].bf16, s))) return rc;
+    if ((rc = rpca::run_cycles(c, X, o, phases[ph].bf16, phases[ph].gtol, o.ftol, true, 0, s))) return rc;
     final_bf16 = phases[ph].bf16;
   }
   return rpca::solve_finish(c, X, U, V, o, final_bf16, phases[nph - 1].gtol, iters_bf16, t0, info, s);

@@ -1,9 +1,8 @@
 // Batched solver: many independent Split-SPCP instances of uneven shape
-// solved together.  Every step of an L-BFGS slot is ONE launch for the whole
-// batch:
+// solved together.  Every step of an L-BFGS slot covers the whole batch:
 //   direction  (blocks of all instances in one grid, then one block per instance)
-//   sweep      (one persistent kernel pulling (instance, row group, chunk) items
-//               from a queue; items sorted by decreasing cost)
+//   sweep      (one persistent kernel per tile class, each pulling (instance,
+//               row group, chunk) items from its queue; decreasing cost first)
 //   finish     (two batched reductions with the line-search step per instance)
 //   update     (batched history pass, then one block per instance)
 // Per-instance solver states live in device memory and every kernel skips the
@@ -46,7 +45,14 @@ struct rpca_batch {
   int count = 0;
   std::vector<rpca_ctx*> ctx;
   bool masked = false;
-  // decomposition (fixed by the shapes)
+  // decomposition (fixed by the shapes): sweep items grouped by tile class
+  struct SweepClass {
+    int kb, tmax;
+    int begin, count;  // range in d_items
+    int lds;           // dynamic LDS floats (largest instance of the class)
+    int grid[2];       // persistent workgroups, FP32 / BF16
+  };
+  std::vector<SweepClass> classes;
   int nitems = 0, lds_max = 0;
   int tot_fin1 = 0, tot_fin2 = 0, tot_lb = 0;
   std::vector<int> off_fin1, off_fin2, off_lb;
@@ -105,22 +111,11 @@ void destroy_batch(rpca_batch* b) {
   delete b;
 }
 
-// Upload the argument tables for the arrays of X pointers (evaluation at x[0]).
-hipError_t upload_args(rpca_batch* b, const float* const* X, std::vector<rpca::InstanceArgs>* ia) {
+// Upload the argument tables (synchronous: the host vectors are the caller's temporaries).
+hipError_t upload_tables(rpca_batch* b, const std::vector<SweepArgs>& sl, const std::vector<SweepArgs>& se,
+                         const std::vector<FinishArgs>& fl, const std::vector<FinishArgs>& fe,
+                         const std::vector<LbfgsArgs>& lu, const std::vector<LbfgsArgs>& ld) {
   const int n = b->count;
-  ia->resize(n);
-  std::vector<SweepArgs> sl(n), se(n);
-  std::vector<FinishArgs> fl(n), fe(n);
-  std::vector<LbfgsArgs> lu(n), ld(n);
-  for (int i = 0; i < n; ++i) {
-    rpca::instance_args(b->ctx[i], X[i], 0, &(*ia)[i]);
-    sl[i] = (*ia)[i].sa_loop;
-    se[i] = (*ia)[i].sa_eval;
-    fl[i] = (*ia)[i].fa_loop;
-    fe[i] = (*ia)[i].fa_eval;
-    lu[i] = (*ia)[i].lu;
-    ld[i] = (*ia)[i].ld;
-  }
   hipStream_t s = b->stream;
   hipError_t e;
   if ((e = hipMemcpyAsync(b->d_sa_loop, sl.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return e;
@@ -129,18 +124,24 @@ hipError_t upload_args(rpca_batch* b, const float* const* X, std::vector<rpca::I
   if ((e = hipMemcpyAsync(b->d_fa_eval, fe.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return e;
   if ((e = hipMemcpyAsync(b->d_lu, lu.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
   if ((e = hipMemcpyAsync(b->d_ld, ld.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
-  // the host vectors die with this frame: finish the copies first
   return hipStreamSynchronize(s);
 }
 
-// One batched objective/gradient pass (plain: at x[0] into st->f and g[0]; trial: solver slot).
+// One batched objective/gradient pass (plain: at x[0] into st->f and g[0]; trial:
+// solver slot): one persistent sweep per tile class, then the batched reductions.
 hipError_t batched_objgrad(rpca_batch* b, bool trial, bool bf16) {
   hipStream_t s = b->stream;
-  hipError_t e = rpca::launch_sweep_batch(trial ? b->d_sa_loop : b->d_sa_eval, b->d_items, b->nitems, b->d_head,
-                                          b->sweep_grid[bf16 ? 1 : 0], b->lds_max, b->masked, trial, bf16, s);
-  if (e != hipSuccess) return e;
+  const SweepArgs* args = trial ? b->d_sa_loop : b->d_sa_eval;
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    const auto& cl = b->classes[c];
+    const hipError_t e = rpca::launch_sweep_batch(cl.kb, cl.tmax, args, b->d_items + cl.begin, cl.count,
+                                                  b->d_head + c, cl.grid[bf16 ? 1 : 0], cl.lds, b->masked, trial,
+                                                  bf16, s);
+    if (e != hipSuccess) return e;
+  }
   return rpca::launch_finish_batch(trial ? b->d_fa_loop : b->d_fa_eval, b->d_off_fin1, b->tot_fin1,
-                                   b->d_off_fin2, b->tot_fin2, b->count, b->d_head, trial, s);
+                                   b->d_off_fin2, b->tot_fin2, b->count, b->d_head, (int)b->classes.size(), trial,
+                                   s);
 }
 
 hipError_t batched_slot(rpca_batch* b, int mem, bool bf16) {
@@ -236,26 +237,39 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
     rpca::instance_args(b->ctx[i], nullptr, 0, &ia[i]);
     const int kb = (k[i] + 15) / 16;
     const int64_t nstrips = (m[i] + 15) / 16;
+    const int tmax = rpca::sweep_tmax_class(kb, (int)((std::min<int64_t>(n[i], ia[i].chunk_w) + 15) / 16));
     for (int rg = 0; rg < ia[i].row_groups; ++rg)
       for (int ch = 0; ch < ia[i].nchunks; ++ch) {
-        items.push_back({i, rg, ch, kb});
+        items.push_back({i, rg, ch, kb, tmax});
         int64_t s0 = (int64_t)rg * 4 * ia[i].spw, s1 = s0 + 4 * (int64_t)ia[i].spw;
         if (s1 > nstrips) s1 = nstrips;
         const int64_t c0 = (int64_t)ch * ia[i].chunk_w;
         const int64_t cols = std::min<int64_t>(ia[i].chunk_w, n[i] - c0);
         cost.push_back((double)std::max<int64_t>(s1 - s0, 0) * (double)cols * (1.0 + 0.6 * (kb - 1)));
       }
-    const int cwp = (int)((std::min<int64_t>(n[i], ia[i].chunk_w) + 15) / 16) * 16;
-    b->lds_max = std::max(b->lds_max, rpca::sweep_lds_floats(kb, k[i], cwp));
     b->off_fin1[i + 1] = b->off_fin1[i] + ia[i].fin1_blocks;
     b->off_fin2[i + 1] = b->off_fin2[i] + ia[i].fin2_blocks;
     b->off_lb[i + 1] = b->off_lb[i] + ia[i].lb_blocks;
   }
+  // group by tile class, then decreasing cost within a class
+  auto cls = [](const SweepItem& it) { return it.kb * 64 + it.tmax; };
   std::vector<int> ord(items.size());
   std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    if (cls(items[x]) != cls(items[y])) return cls(items[x]) < cls(items[y]);
+    return cost[x] > cost[y];
+  });
   std::vector<SweepItem> sorted(items.size());
   for (size_t j = 0; j < ord.size(); ++j) sorted[j] = items[ord[j]];
+  for (size_t j = 0; j < sorted.size(); ++j) {
+    if (b->classes.empty() || b->classes.back().kb != sorted[j].kb || b->classes.back().tmax != sorted[j].tmax)
+      b->classes.push_back({sorted[j].kb, sorted[j].tmax, (int)j, 0, 0, {0, 0}});
+    auto& cl = b->classes.back();
+    cl.count += 1;
+    const int i = sorted[j].inst;
+    const int cwp = (int)((std::min<int64_t>(n[i], ia[i].chunk_w) + 15) / 16) * 16;
+    cl.lds = std::max(cl.lds, rpca::sweep_lds_floats(sorted[j].kb, k[i], cwp));
+  }
   b->nitems = (int)sorted.size();
   b->tot_fin1 = b->off_fin1[count];
   b->tot_fin2 = b->off_fin2[count];
@@ -263,7 +277,7 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
   std::vector<SolverState*> states(count);
   for (int i = 0; i < count; ++i) states[i] = ia[i].state_dev;
   bool ok = dalloc(&b->d_items, sorted.size()) && dalloc(&b->d_off_fin1, count + 1) &&
-            dalloc(&b->d_off_fin2, count + 1) && dalloc(&b->d_off_lb, count + 1) && dalloc(&b->d_head, 1) &&
+            dalloc(&b->d_off_fin2, count + 1) && dalloc(&b->d_off_lb, count + 1) && dalloc(&b->d_head, b->classes.size()) &&
             dalloc(&b->d_sa_loop, count) && dalloc(&b->d_sa_eval, count) && dalloc(&b->d_fa_loop, count) &&
             dalloc(&b->d_fa_eval, count) && dalloc(&b->d_lu, count) && dalloc(&b->d_ld, count) &&
             dalloc(&b->d_states, count) && dalloc(&b->d_phase, count) &&
@@ -281,7 +295,7 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
        hipMemcpy(b->d_off_lb, b->off_lb.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(b->d_states, states.data(), count * sizeof(SolverState*), hipMemcpyHostToDevice) ==
            hipSuccess &&
-       hipMemset(b->d_head, 0, sizeof(unsigned)) == hipSuccess &&
+       hipMemset(b->d_head, 0, b->classes.size() * sizeof(unsigned)) == hipSuccess &&
        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
@@ -289,8 +303,13 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
     destroy_batch(b);
     return RPCA_EHIP;
   }
-  b->sweep_grid[0] = std::min(b->nitems, rpca::sweep_batch_grid(b->lds_max, false, true, false));
-  b->sweep_grid[1] = std::min(b->nitems, rpca::sweep_batch_grid(b->lds_max, false, true, true));
+  for (auto& cl : b->classes) {
+    cl.grid[0] = std::min(cl.count, rpca::sweep_batch_grid(cl.kb, cl.tmax, cl.lds, false, true, false));
+    cl.grid[1] = std::min(cl.count, rpca::sweep_batch_grid(cl.kb, cl.tmax, cl.lds, false, true, true));
+    b->sweep_grid[0] += cl.grid[0];
+    b->sweep_grid[1] += cl.grid[1];
+    b->lds_max = std::max(b->lds_max, cl.lds);
+  }
   *out = b;
   return RPCA_OK;
 }
@@ -354,43 +373,64 @@ int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, floa
   int rc;
   for (int i = 0; i < b->count; ++i)
     if ((rc = rpca::solve_setup(b->ctx[i], X[i], U[i], V[i], o, phases[0].gtol, s))) return rc;
-  std::vector<rpca::InstanceArgs> ia;
-  if (upload_args(b, X, &ia) != hipSuccess) return RPCA_EHIP;
   const bool use_graph = b->use_graphs;
-  if (batched_objgrad(b, false, phases[0].bf16) != hipSuccess) return RPCA_EHIP;
-  if ((rc = batched_run(b, o, phases[0].bf16, use_graph))) return rc;
+  std::vector<rpca::InstanceArgs> ia(b->count);
   std::vector<int> iters_bf16(b->count, 0);
-  for (int i = 0; i < b->count; ++i) {
-    if (hipMemcpyAsync(ia[i].state_host, ia[i].state_dev, sizeof(SolverState), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return RPCA_EHIP;
-  }
-  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
-  for (int i = 0; i < b->count; ++i) iters_bf16[i] = phases[0].bf16 ? ia[i].state_host->iter : 0;
+  std::vector<char> failed(b->count, 0);
   bool final_bf16 = phases[0].bf16;
-  for (int ph = 1; ph < nph; ++ph) {
-    // the polish phase restarts every instance that did not fail, after a plain
-    // evaluation at each current iterate (an instance that failed stays done;
-    // its re-evaluation in place only refreshes f and g at the same point)
-    std::vector<SweepArgs> se(b->count);
-    std::vector<FinishArgs> fe(b->count);
-    for (int i = 0; i < b->count; ++i) {
-      const SolverState* h = ia[i].state_host;
-      const bool failed = h->stop == STOP_NONFINITE || h->stop == STOP_MAXITER;
-      if (!failed && (rc = rpca::resume_state(b->ctx[i], phases[ph].gtol, o.ftol, s))) return rc;
-      rpca::InstanceArgs a;
-      rpca::instance_args(b->ctx[i], X[i], h->cur, &a);
-      se[i] = a.sa_eval;
-      fe[i] = a.fa_eval;
+  for (int ph = 0; ph < nph; ++ph) {
+    // cycles: every instance that starts a cycle gets a fresh preconditioner (if
+    // enabled), an iteration cap and an empty memory; the others stay done
+    for (int cyc = 0;; ++cyc) {
+      std::vector<char> active(b->count, 0);
+      int nact = 0;
+      for (int i = 0; i < b->count; ++i) {
+        const SolverState* h = rpca::ctx_state_host(b->ctx[i]);
+        if (cyc == 0) active[i] = !failed[i];
+        else active[i] = o.precond && h->stop == STOP_MAXITER && h->iter < o.max_iter;
+        nact += active[i];
+      }
+      if (!nact) break;
+      for (int i = 0; i < b->count; ++i) {
+        if (!active[i]) continue;
+        rpca_ctx* c = b->ctx[i];
+        const SolverState* h = rpca::ctx_state_host(c);
+        int cap = o.max_iter;
+        if (o.precond) {
+          if ((rc = rpca::precond_refresh(c, h->cur, s))) return rc;
+          cap = (o.max_iter - h->iter > o.precond_cycle) ? h->iter + o.precond_cycle : o.max_iter;
+        }
+        if ((rc = rpca::restart_state(c, phases[ph].gtol, o.ftol, cap, o.precond != 0, s))) return rc;
+      }
+      // argument tables at each instance's current iterate and variables
+      std::vector<SweepArgs> sl(b->count), se(b->count);
+      std::vector<FinishArgs> fl(b->count), fe(b->count);
+      std::vector<LbfgsArgs> lu(b->count), ld(b->count);
+      for (int i = 0; i < b->count; ++i) {
+        rpca::instance_args(b->ctx[i], X[i], rpca::ctx_state_host(b->ctx[i])->cur, &ia[i]);
+        sl[i] = ia[i].sa_loop;
+        se[i] = ia[i].sa_eval;
+        fl[i] = ia[i].fa_loop;
+        fe[i] = ia[i].fa_eval;
+        lu[i] = ia[i].lu;
+        ld[i] = ia[i].ld;
+      }
+      if (upload_tables(b, sl, se, fl, fe, lu, ld) != hipSuccess) return RPCA_EHIP;
+      if (batched_objgrad(b, false, phases[ph].bf16) != hipSuccess) return RPCA_EHIP;
+      if ((rc = batched_run(b, o, phases[ph].bf16, use_graph))) return rc;
+      for (int i = 0; i < b->count; ++i)
+        if (hipMemcpyAsync(ia[i].state_host, ia[i].state_dev, sizeof(SolverState), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+          return RPCA_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
     }
-    if (hipMemcpyAsync(b->d_sa_eval, se.data(), b->count * sizeof(SweepArgs), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(b->d_fa_eval, fe.data(), b->count * sizeof(FinishArgs), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return RPCA_EHIP;
-    if (batched_objgrad(b, false, phases[ph].bf16) != hipSuccess) return RPCA_EHIP;
-    if ((rc = batched_run(b, o, phases[ph].bf16, use_graph))) return rc;
+    for (int i = 0; i < b->count; ++i) {
+      rpca_ctx* c = b->ctx[i];
+      if ((rc = rpca::precond_to_plain(c, rpca::ctx_state_host(c)->cur, s))) return rc;
+      const SolverState* h = rpca::ctx_state_host(c);
+      if (ph == 0 && phases[0].bf16) iters_bf16[i] = h->iter;
+      if (h->stop == STOP_NONFINITE || h->stop == STOP_MAXITER) failed[i] = 1;
+    }
     final_bf16 = phases[ph].bf16;
   }
   int worst = RPCA_OK;
@@ -419,6 +459,7 @@ int rpca_batch_info(rpca_batch* b, rpca_batch_layout* out) {
   out->sweep_grid_bf16 = b->sweep_grid[1];
   out->lds_bytes = b->lds_max * 4;
   out->graphs = (int32_t)b->graphs.size();
+  out->sweep_classes = (int32_t)b->classes.size();
   return RPCA_OK;
 }
 

@@ -16,6 +16,7 @@
 #include "rpca_internal.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 namespace {
 
@@ -193,7 +194,8 @@ __device__ void update_small_math(SolverState* st, const double* D) {
   int stop = STOP_NONE;
   if (!isfinite(f) || !isfinite(D[I::GG])) stop = STOP_NONFINITE;
   else if (D[I::GINF] <= st->gtol * fmax(1.0, fabs(f))) stop = STOP_GTOL;
-  else if (st->iter >= 5 && (st->fhist[2] - f) <= st->ftol * fmax(1.0, fabs(f))) stop = STOP_FTOL;
+  else if (st->ftol > 0.0 && st->iter >= 5 && (st->fhist[2] - f) <= st->ftol * fmax(1.0, fabs(f)))
+    stop = STOP_FTOL;
   else if (st->iter >= st->max_iter) stop = STOP_MAXITER;
   st->stop = stop;
   st->phase = (stop == STOP_NONE) ? PH_DIRECTION : PH_DONE;
@@ -409,10 +411,14 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final_batch(const L
 namespace rpca {
 
 int lbfgs_blocks(int64_t N) {
-  // about one float4 per thread, at most 1024 blocks
+  // about one float4 per thread, at most cap blocks
+  static int cap = [] {
+    const char* e = getenv("RPCA_LBFGS_BLOCKS_EXPT");
+    return e ? atoi(e) : 1024;
+  }();
   int64_t b = (N / 4 + THREADS - 1) / THREADS;
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > cap) b = cap;
   return (int)b;
 }
 

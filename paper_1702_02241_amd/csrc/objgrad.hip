@@ -50,7 +50,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Finishing reduction, two launches (no grid-wide fence in the wide one):
 //   k_reduce1: grid (ceil(nk/256), segs); thread o of block (bx, by) sums the
 //     G^T U partials of workgroup rows [by*rps, (by+1)*rps) -> level2[by][o].
-//   k_reduce2: blocks < gv_blocks: gV = sum_by level2 + lam_l V_t (fixed order);
+//   k_reduce2: blocks < gv_blocks (whole rows of V each): gV = sum_by level2 +
+//     lam_l V_t (fixed order), or its preconditioned form;
 //     further blocks (several chunks only): gU = sum over chunks + lam_l U_t.
 //     Each block publishes three scalar partials; the last block to arrive
 //     (thread-0 fence + counter over a handful of blocks) forms f and g^T d
@@ -96,23 +97,58 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
   const float* Ut = a.U[outi];
   const int tid = threadIdx.x;
   double vv = 0.0, gvd = 0.0, gud = 0.0;
+  const int k = a.k;
   if (bx < a.gv_blocks) {
-    const int64_t o = (int64_t)bx * FIN_THREADS + tid;
-    if (o < nk) {
-      double s = 0.0;
+    // whole rows per block: thread (jr, c) of row j = bx * rpb + jr
+    const int rpb = FIN_THREADS / k;
+    const int jr = tid / k, c = tid % k;
+    const int64_t j = (int64_t)bx * rpb + jr;
+    const bool ok = jr < rpb && j < a.n;
+    const int64_t o = j * k + c;
+    double s = 0.0;
+    if (ok)
       for (int q = 0; q < a.segs; ++q) s += a.level2[(int64_t)q * nk + o];
-      const float v = Vt[o];
-      const float gvv = (float)(s + (double)lam_l * (double)v);
-      a.gV[outi][o] = gvv;
-      vv = (double)v * (double)v;
-      if (TRIAL) gvd = (double)gvv * (double)a.dV[o];
+    if (!a.pc) {
+      if (ok) {
+        const float v = Vt[o];
+        const float gvv = (float)(s + (double)lam_l * (double)v);
+        a.gV[outi][o] = gvv;
+        vv = (double)v * (double)v;
+        if (TRIAL) gvd = (double)gvv * (double)a.dV[o];
+      }
+    } else {
+      // preconditioned variables: grad_B = (G^T A) W + lam_l B M_V, ||V||^2 = sum B M_V B^T
+      __shared__ double sS[FIN_THREADS];
+      sS[tid] = s;
+      __syncthreads();
+      if (ok) {
+        const float* W = a.pc;
+        const float* MV = a.pc + 2 * k * k;
+        double t1 = 0.0, t2 = 0.0;
+        for (int t = 0; t < k; ++t) {
+          t1 += sS[jr * k + t] * (double)W[t * k + c];
+          t2 += (double)Vt[j * k + t] * (double)MV[t * k + c];
+        }
+        const float gvv = (float)(t1 + (double)lam_l * t2);
+        a.gV[outi][o] = gvv;
+        vv = (double)Vt[o] * t2;
+        if (TRIAL) gvd = (double)gvv * (double)a.dV[o];
+      }
     }
   } else {
+    const float* MU = a.pc ? a.pc + k * k : nullptr;
     const int64_t stride = (int64_t)(nblk - a.gv_blocks) * FIN_THREADS;
     for (int64_t o = (int64_t)(bx - a.gv_blocks) * FIN_THREADS + tid; o < mk; o += stride) {
       double s = 0.0;
       for (int cc = 0; cc < a.nchunks; ++cc) s += (double)a.gupart[(int64_t)cc * mk + o];
-      const float gu = (float)(s + (double)lam_l * (double)Ut[o]);
+      double reg = Ut[o];
+      if (MU) {  // A M_U
+        const int64_t i = o / k;
+        const int c = (int)(o % k);
+        reg = 0.0;
+        for (int t = 0; t < k; ++t) reg += (double)Ut[i * k + t] * (double)MU[t * k + c];
+      }
+      const float gu = (float)(s + (double)lam_l * reg);
       a.gU[outi][o] = gu;
       if (TRIAL) gud += (double)gu * (double)a.dU[o];
     }
@@ -195,8 +231,8 @@ __device__ __forceinline__ int batch_instance(const int* off, int count, int b) 
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_reduce1_batch(const FinishArgs* fa, const int* off, int count,
-                                                              unsigned* queue_head) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *queue_head = 0u;
+                                                              unsigned* queue_heads, int nheads) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < nheads) queue_heads[threadIdx.x] = 0u;
   const int i = batch_instance(off, count, blockIdx.x);
   const FinishArgs& a = fa[i];
   const int gvb = (int)((a.n * a.k + FIN_THREADS - 1) / FIN_THREADS);
@@ -284,7 +320,8 @@ hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t 
 }
 
 int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks) {
-  const int gvb = (int)((n * k + FIN_THREADS - 1) / FIN_THREADS);
+  const int rpb = FIN_THREADS / k;  // whole rows of V per block
+  const int gvb = (int)((n + rpb - 1) / rpb);
   int gub = 0;
   if (nchunks > 1) {
     gub = (int)((m * k + FIN_THREADS * 8 - 1) / (FIN_THREADS * 8));
@@ -308,28 +345,33 @@ hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_batch_f32(const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool, bool,
+hipError_t launch_sweep_batch_f32(int, int, const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool, bool,
                                   hipStream_t);
-hipError_t launch_sweep_batch_bf16(const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool, bool,
-                                   hipStream_t);
-int sweep_batch_grid_f32(int, bool, bool);
-int sweep_batch_grid_bf16(int, bool, bool);
+hipError_t launch_sweep_batch_bf16(int, int, const SweepArgs*, const SweepItem*, int, unsigned*, int, int, bool,
+                                   bool, hipStream_t);
+int sweep_batch_grid_f32(int, int, int, bool, bool);
+int sweep_batch_grid_bf16(int, int, int, bool, bool);
 
-hipError_t launch_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head, int grid,
-                              int lds_floats, bool masked, bool trial, bool bf16, hipStream_t s) {
-  return bf16 ? launch_sweep_batch_bf16(args, items, nitems, head, grid, lds_floats, masked, trial, s)
-              : launch_sweep_batch_f32(args, items, nitems, head, grid, lds_floats, masked, trial, s);
+hipError_t launch_sweep_batch(int kb, int tmax, const SweepArgs* args, const SweepItem* items, int nitems,
+                              unsigned* head, int grid, int lds_floats, bool masked, bool trial, bool bf16,
+                              hipStream_t s) {
+  return bf16 ? launch_sweep_batch_bf16(kb, tmax, args, items, nitems, head, grid, lds_floats, masked, trial, s)
+              : launch_sweep_batch_f32(kb, tmax, args, items, nitems, head, grid, lds_floats, masked, trial, s);
+}
+
+int sweep_batch_grid(int kb, int tmax, int lds_floats, bool masked, bool trial, bool bf16) {
+  return bf16 ? sweep_batch_grid_bf16(kb, tmax, lds_floats, masked, trial)
+              : sweep_batch_grid_f32(kb, tmax, lds_floats, masked, trial);
 }
 
 int sweep_lds_floats(int kb, int k, int cwp) { return rpca_sweep::lds_floats(kb, k, cwp); }
-
-int sweep_batch_grid(int lds_floats, bool masked, bool trial, bool bf16) {
-  return bf16 ? sweep_batch_grid_bf16(lds_floats, masked, trial) : sweep_batch_grid_f32(lds_floats, masked, trial);
-}
+int sweep_tmax_class(int kb, int ntiles) { return rpca_sweep::tmax_class(kb, ntiles); }
 
 hipError_t launch_finish_batch(const FinishArgs* fa, const int* off1, int total1, const int* off2, int total2,
-                               int count, unsigned* queue_head, bool trial, hipStream_t stream) {
-  hipLaunchKernelGGL(k_reduce1_batch, dim3(total1), dim3(FIN_THREADS), 0, stream, fa, off1, count, queue_head);
+                               int count, unsigned* queue_heads, int nheads, bool trial, hipStream_t stream) {
+  if (nheads > FIN_THREADS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce1_batch, dim3(total1), dim3(FIN_THREADS), 0, stream, fa, off1, count, queue_heads,
+                     nheads);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (trial)

@@ -98,6 +98,7 @@ struct SweepArgs {
   float* gupart;          // [chunks][m*k] partial G V when n spans several chunks
   float* gvpart;          // [row_groups][n*k] partial G^T U (one per workgroup row)
   double* spart;          // [row_groups*chunks][RPCA_NSCAL] scalar partials
+  const float* pc;        // preconditioner [W | M_U | M_V] (k x k each) or null (plain variables)
   int32_t strips_per_wave;  // 16-row strips per wave (contiguous)
   int32_t chunk_w;        // columns per chunk (multiple of 16)
   int32_t nchunks;
@@ -106,7 +107,7 @@ struct SweepArgs {
 
 // One work item of the batched sweep: workgroup row rg, column chunk ch of instance inst.
 struct SweepItem {
-  int32_t inst, rg, ch, kb;
+  int32_t inst, rg, ch, kb, tmax;
 };
 
 // Arguments of the finishing reduction (gV, f, g^T d, line-search step).
@@ -132,6 +133,7 @@ struct FinishArgs {
   int32_t nchunks, row_groups, sweep_wgs;
   int32_t segs, rows_per_seg;  // workgroup rows are summed in segs segments
   int32_t gv_blocks;      // set by the launcher
+  const float* pc;        // preconditioner [W | M_U | M_V] or null (see SweepArgs)
 };
 
 // Flat N-vector kernels of L-BFGS.  x, g, d, S, Y all hold N = (m+n)k floats,
@@ -174,12 +176,14 @@ hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t strea
 int lbfgs_blocks(int64_t N);
 // Batched launches: arrays of per-instance arguments in device memory, block
 // offsets off[0..count] (device) of each instance in the flattened grid.
-hipError_t launch_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head,
-                              int grid, int lds_floats, bool masked, bool trial, bool bf16, hipStream_t s);
-int sweep_batch_grid(int lds_floats, bool masked, bool trial, bool bf16);
+hipError_t launch_sweep_batch(int kb, int tmax, const SweepArgs* args, const SweepItem* items, int nitems,
+                              unsigned* head, int grid, int lds_floats, bool masked, bool trial, bool bf16,
+                              hipStream_t s);
+int sweep_batch_grid(int kb, int tmax, int lds_floats, bool masked, bool trial, bool bf16);
 int sweep_lds_floats(int kb, int k, int cwp);
+int sweep_tmax_class(int kb, int ntiles);
 hipError_t launch_finish_batch(const FinishArgs* fa, const int* off1, int total1, const int* off2, int total2,
-                               int count, unsigned* queue_head, bool trial, hipStream_t s);
+                               int count, unsigned* queue_heads, int nheads, bool trial, hipStream_t s);
 hipError_t launch_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks, int mem,
                                     hipStream_t s);
 hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
@@ -226,7 +230,15 @@ int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts
 int eval_current(rpca_ctx* c, const float* X, int cur, bool bf16, hipStream_t s);
 int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStream_t s);
 int resume_state(rpca_ctx* c, double gtol, double ftol, hipStream_t s);
+int restart_state(rpca_ctx* c, double gtol, double ftol, int max_iter, bool reset_memory, hipStream_t s);
+int run_cycles(rpca_ctx* c, const float* X, const rpca_opts& o, bool bf16, double gtol, double ftol,
+               bool keep_memory, int budget, hipStream_t s);
 void instance_args(rpca_ctx* c, const float* X, int cur, InstanceArgs* out);
+// Preconditioned variables (precond.hip).
+constexpr int PC_GRAM_BLOCKS = 256;
+int precond_refresh(rpca_ctx* c, int cur, hipStream_t s);
+int precond_to_plain(rpca_ctx* c, int cur, hipStream_t s);
+SolverState* ctx_state_host(rpca_ctx* c);
 int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
                  double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
                  hipStream_t s);

@@ -6,22 +6,26 @@
 //   G^T U and G V                 (the two gradient products, chain rule on eq. smoothNC)
 // so neither R nor G is ever written to memory.
 //
-// Work split.  The columns are cut into chunks (grid.y) small enough for the
-// LDS budget below; every wave owns a contiguous run of 16-row strips and, for
-// each strip, walks the chunk's 16-column tiles in groups of four.  The X loads
-// of the next group are issued before the current group is computed and pinned
-// there with a scheduling barrier, so about eight tiles per wave are in flight
-// while registers stay independent of the chunk width.  Per 16x16 tile:
+// Work split.  The columns are cut into chunks (grid.y) of at most TMAX
+// 16-column tiles that fit the LDS budget below; V of the chunk is staged in
+// LDS.  Every wave owns a contiguous run of 16-row strips and walks the
+// chunk's tiles of each strip in groups of PF.  While a group is computed the
+// next one is in flight; the last group of a strip prefetches the next
+// strip's operands and first group, so the load stream never drains between
+// strips.  X is read with buffer loads: the tile's column base is scalar,
+// the lane offset one VGPR, and columns past the chunk fall outside the
+// resource's range and read as zero.  Per 16x16 tile:
 //   * R on MFMA with the accumulator seeded by -X.  In the MFMA output layout
 //     (column j = lane%16, rows 4*(lane/16)+r) G is already the A operand of
-//     G^T U with the K index running over rows.  The tile's G^T U is added into
-//     the wave's private LDS accumulator (one writer per address, so no
-//     atomics); the waves' accumulators are summed in a fixed order at the end.
+//     G^T U with K running over rows, so the tile's G^T U goes straight into
+//     that tile's accumulator, kept in (accumulation) registers across all
+//     strips of the wave.  The waves' accumulators meet in LDS once, at the
+//     end, and are summed in a fixed order.
 //   * G V contracts over columns: G goes through a 16x17 per-wave LDS tile to
 //     the transposed layout and into MFMA; the strip's G V accumulates in
 //     registers over the chunk and is complete when the strip ends (one chunk)
 //     or written as a per-chunk partial.
-// FP32 mode uses v_mfma_f32_16x16x4_f32; BF16 mode rounds U, V and G to bf16 and
+// FP32 mode uses v_mfma_f32_16x16x4f32; BF16 mode rounds U, V and G to bf16 and
 // uses v_mfma_f32_16x16x16_bf16 (FP32 accumulation, FP32 residual).  Every
 // cross-wave and cross-workgroup sum runs in a fixed order: bitwise reproducible.
 #pragma once
@@ -40,8 +44,10 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 constexpr int WAVES = 4;
 constexpr int NT = 64 * WAVES;
 constexpr int LDT = 17;   // padded row of the per-wave transpose tile
-constexpr int PF = 4;     // tiles per load group
 constexpr int LDS_LIMIT_FLOATS = 16384;  // 64 KB per workgroup
+constexpr int TMAX_KB1 = 16;  // most tiles per chunk (register accumulators), k <= 16
+constexpr int TMAX_KB2 = 8;   // k in 17..32
+constexpr uint32_t BUF_DWORD3 = 0x00020000;  // raw buffer resource word 3 on gfx9 (32-bit data format)
 
 __device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -73,23 +79,50 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Dynamic LDS (floats): sVt[cwp][KMAX+1] | sGV[WAVES][cwp][k] | sT[WAVES][16*LDT]
+// Dynamic LDS (floats): sVt[cwp][16 kb + 1] | sGV[WAVES][cwp][k] | sT[WAVES][16*LDT]
 __host__ __device__ constexpr int lds_floats(int kb, int k, int cwp) {
   return cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * 16 * LDT;
 }
 
-// Widest chunk (multiple of 16 columns) whose staging fits the LDS budget.
+// Widest chunk (multiple of 16 columns) that fits the LDS budget and the
+// register accumulators.
 __host__ __device__ constexpr int max_chunk(int kb, int k) {
-  return 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)));
+  return 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k))) <
+                 16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2)
+             ? 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)))
+             : 16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2);
 }
 
-// One work item: the strips of workgroup row `rg` against column chunk `ch`.
-template <int KB, bool MASKED, bool TRIAL, bool BF16>
+// Tile-count class of a chunk: the instantiated TMAX that covers ntiles.
+__host__ __device__ constexpr int tmax_class(int kb, int ntiles) {
+  return ntiles <= 4 ? 4 : (ntiles <= 8 || kb == 2) ? 8 : 16;
+}
+
+// Loads in flight per wave: PF tiles per group, an even number of groups per strip
+// (the two group buffers line up at every strip start).
+template <int TMAX>
+struct Pipe {
+  static constexpr int PF = TMAX <= 4 ? 2 : 4;
+  static constexpr int NG0 = (TMAX + PF - 1) / PF;
+  static constexpr int NG = NG0 + (NG0 & 1);
+};
+
+template <int KB>
+struct StripOps {
+  float ua[4 * KB];   // R: A operand (layout per precision, see load_ops)
+  float ub[4][KB];    // G^T U:  B[row 4g + r][kk = 16 kb + c]
+  float dub[4][KB];   // dU at the ub positions (trial)
+};
+
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
 __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, const int ch, float* lds,
-                                           double* sRed) {
+                                            double* sRed) {
   constexpr int KMAX = 16 * KB;
   constexpr int KQ = 4 * KB;
   constexpr int LDV = KMAX + 1;
+  using P = Pipe<TMAX>;
+  constexpr int PF = P::PF;
+  constexpr int NG = P::NG;
 
   int cur = 0, outi = 0;
   float alpha = 0.f;
@@ -112,29 +145,62 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
 
   const int64_t j_begin = (int64_t)ch * a.chunk_w;
   const int ncols = (int)((n - j_begin) < a.chunk_w ? (n - j_begin) : a.chunk_w);
-  const int ntiles = (ncols + 15) >> 4;
+  const int ntiles = (ncols + 15) >> 4;  // <= TMAX (the launcher picks TMAX)
   const int cwp = ntiles * 16;
   float* sVt = lds;
   float* sGVall = lds + cwp * LDV;
-  float* sGV = sGVall + w * cwp * k;
   float* myT = sGVall + WAVES * cwp * k + w * 16 * LDT;
 
-  // Stage the (trial) V rows of this chunk (zero padded); clear the G^T U accumulators.
-  for (int idx = tid; idx < cwp * KMAX; idx += NT) {
-    const int jl = idx / KMAX, kk = idx % KMAX;
-    float v = 0.f;
-    if (jl < ncols && kk < k) {
-      const int64_t o = (j_begin + jl) * k + kk;
-      v = V[o];
-      if (TRIAL) {
-        v = fmaf(alpha, a.dV[o], v);
-        if (rg == 0) a.Vt[outi][o] = v;
+  // Preconditioned variables (the solver's A, B with U = A P_U, V = B P_V): the
+  // product U V^T = A (B W^T)^T with W = P_U P_V, so the staged rows are B W^T
+  // and everything else in the tile loop is unchanged.  pc = [W | M_U | M_V],
+  // k x k each, row-major (M_U = P_U^2, M_V = P_V^2).
+  const float* __restrict__ pc = a.pc;
+  if (pc) {
+    float* raw = sGVall;  // [cwp][k], free until the end of the item
+    for (int idx = tid; idx < cwp * k; idx += NT) {
+      const int jl = idx / k;
+      float v = 0.f;
+      if (jl < ncols) {
+        const int64_t o = j_begin * k + idx;
+        v = V[o];
+        if (TRIAL) {
+          v = fmaf(alpha, a.dV[o], v);
+          if (rg == 0) a.Vt[outi][o] = v;
+        }
       }
+      raw[idx] = v;
     }
-    sVt[jl * LDV + kk] = v;
+    __syncthreads();
+    for (int idx = tid; idx < cwp * KMAX; idx += NT) {
+      const int jl = idx / KMAX, kk = idx % KMAX;
+      float v = 0.f;
+      if (kk < k)
+        for (int t = 0; t < k; ++t) v = fmaf(raw[jl * k + t], pc[kk * k + t], v);
+      sVt[jl * LDV + kk] = v;
+    }
+  } else {
+    for (int idx = tid; idx < cwp * KMAX; idx += NT) {
+      const int jl = idx / KMAX, kk = idx % KMAX;
+      float v = 0.f;
+      if (jl < ncols && kk < k) {
+        const int64_t o = (j_begin + jl) * k + kk;
+        v = V[o];
+        if (TRIAL) {
+          v = fmaf(alpha, a.dV[o], v);
+          if (rg == 0) a.Vt[outi][o] = v;
+        }
+      }
+      sVt[jl * LDV + kk] = v;
+    }
   }
-  for (int idx = tid; idx < WAVES * cwp * k; idx += NT) sGVall[idx] = 0.f;
   __syncthreads();
+
+  f4 gva[TMAX][KB];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) gva[t][kb] = f4{0.f, 0.f, 0.f, 0.f};
 
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
   const int64_t nstrips = (m + 15) >> 4;
@@ -143,24 +209,24 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
   int64_t s_end = s_begin + a.strips_per_wave;
   if (s_end > nstrips) s_end = nstrips;
   const bool vec = a.xvec != 0;
-  const int64_t tile_stride = 16 * m;  // floats between the same lane's columns in consecutive tiles
+  // strips whose 16 rows are all inside X take the pipelined vector path
+  int64_t s_pipe_end = vec ? (m >> 4) : 0;
+  if (s_pipe_end > s_end) s_pipe_end = s_end;
+  if (s_pipe_end < s_begin) s_pipe_end = s_begin;
+  const int64_t tile_stride = 16 * m;
 
-  for (int64_t s = s_begin; s < s_end; ++s) {
+  auto load_ops = [&](int64_t s, StripOps<KB>& o) {
     const int64_t i0 = s * 16;
-    const bool full = vec && (i0 + 16 <= m);
-    // U_t operands of the strip (clamped addresses + selects: no branches).
     const int64_t i_c = (i0 + c < m) ? i0 + c : m - 1;
     const bool row_c_ok = i0 + c < m;
-    float ua[KQ];      // R:      A[i = c][kk = 4q + g]
-    float ub[4][KB];   // G^T U:  B[row 4g + r][kk = 16 kb + c]
-    float dub[4][KB];  // dU at the ub positions (trial)
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
-      const int kk = 4 * q + g;
+      // FP32: A[i = c][kk = 4q + g] per K-step q; BF16: lane holds kk = 16 kb + 4 g + e, q = 4 kb + e
+      const int kk = BF16 ? 16 * (q >> 2) + 4 * g + (q & 3) : 4 * q + g;
       const int kkc = kk < k ? kk : k - 1;
       float v = U[i_c * k + kkc];
       if (TRIAL) v = fmaf(alpha, dU[i_c * k + kkc], v);
-      ua[q] = (kk < k && row_c_ok) ? v : 0.f;
+      o.ua[q] = (kk < k && row_c_ok) ? v : 0.f;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -176,159 +242,132 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
           dv = dU[ic * k + kkc];
           v = fmaf(alpha, dv, v);
         }
-        ub[r][kb] = ok ? v : 0.f;
-        dub[r][kb] = ok ? dv : 0.f;
+        o.ub[r][kb] = ok ? v : 0.f;
+        o.dub[r][kb] = ok ? dv : 0.f;
       }
     }
-    // BF16 A operand of R: lane (c, g) holds U_t[i0 + c][16 kb + 4 g + e], e = 0..3
-    s4 uab[KB], ubb[KB];
-    if (BF16) {
+  };
+
+  // vector loads of tiles [gi*PF, gi*PF + PF) of strip s (rows inside X).  Buffer
+  // loads: the tile's column base is scalar, the lane offset one VGPR, and
+  // columns past the chunk fall outside the resource's range and read zero.
+  const uint32_t lane_off = (uint32_t)(c * m * 4 + 16 * g);
+  auto load_group = [&](int64_t s, int gi, f4(&xr)[PF], uint32_t(&br)[PF]) {
+    const uint32_t voff = lane_off + (uint32_t)(s * 64);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int t = gi * PF + u;
+      if (t < TMAX) {
+        int valid = ncols - 16 * t;
+        valid = valid < 0 ? 0 : (valid > 16 ? 16 : valid);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(X + (j_begin + 16 * t) * m), (short)0, (int)(valid * m * 4), BUF_DWORD3);
+        xr[u] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
+        if (MASKED) {
+          const int jl = 16 * t + c;
+          const int64_t j = j_begin + ((jl < ncols) ? jl : ncols - 1);
+          const int64_t i0 = s * 16;
+          br[u] = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
+        }
+      }
+    }
+  };
+
+  auto tile = [&](int t, const StripOps<KB>& o, f4 xraw, uint32_t braw, float& ftile, float& gtile,
+                  f4(&gu)[KB]) {
+    const int jl = 16 * t + c;
+    const bool jok = jl < ncols;
+    const f4 xv = jok ? xraw : f4{0.f, 0.f, 0.f, 0.f};
+    const uint32_t bits = MASKED ? (jok ? braw : 0u) : 0xFu;
+    f4 acc = -xv;
+    if (!BF16) {
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) acc = mfma_f32(o.ua[q], sVt[jl * LDV + 4 * q + g], acc);
+    } else {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        float t4[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int kk = 16 * kb + 4 * g + e;
-          const int kkc = kk < k ? kk : k - 1;
-          float v = U[i_c * k + kkc];
-          if (TRIAL) v = fmaf(alpha, dU[i_c * k + kkc], v);
-          t4[e] = (kk < k && row_c_ok) ? v : 0.f;
-        }
-        uab[kb] = pack_bf16(t4[0], t4[1], t4[2], t4[3]);
-        ubb[kb] = pack_bf16(ub[0][kb], ub[1][kb], ub[2][kb], ub[3][kb]);
+        const float* vr = sVt + jl * LDV + 16 * kb + 4 * g;
+        const s4 ua4 = pack_bf16(o.ua[4 * kb + 0], o.ua[4 * kb + 1], o.ua[4 * kb + 2], o.ua[4 * kb + 3]);
+        acc = mfma_bf16(ua4, pack_bf16(vr[0], vr[1], vr[2], vr[3]), acc);
       }
     }
-    f4 gu[KB];
+    float G[4];
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) gu[kb] = f4{0.f, 0.f, 0.f, 0.f};
-    float ftile = 0.f, gtile = 0.f;
-    // lane's column base (column c of tile 0 of the chunk, rows i0 + 4g .. +3)
-    const float* xbase = X + (j_begin + c) * m + i0 + 4 * g;
-
-    auto strip = [&](auto full_tag) {
-      constexpr bool FULL = decltype(full_tag)::value;
-      auto load_group = [&](int t0, f4(&xr)[PF], uint32_t(&br)[PF]) {
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          const int jl = 16 * (t0 + u) + c;
-          // columns past the chunk re-read its last column (valid address; zeroed at use)
-          const int64_t off = (jl < ncols) ? (int64_t)(t0 + u) * tile_stride
-                                           : (int64_t)(ncols - 1 - c) * m;
-          if (FULL) {
-            xr[u] = *reinterpret_cast<const f4*>(xbase + off);
-          } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int64_t i = i0 + 4 * g + r;
-              const float xv_r = xbase[off + ((i < m) ? r : (m - 1 - i0 - 4 * g))];
-              xr[u][r] = (i < m) ? xv_r : 0.f;
-            }
-          }
-          if (MASKED) {
-            const int64_t j = j_begin + ((jl < ncols) ? jl : ncols - 1);
-            br[u] = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
-          }
-        }
-      };
-      auto tile = [&](int t, f4 xraw, uint32_t braw) {
-        const int jl = 16 * t + c;
-        const bool jok = jl < ncols;
-        const f4 xv = jok ? xraw : f4{0.f, 0.f, 0.f, 0.f};
-        const uint32_t bits = MASKED ? (jok ? braw : 0u) : 0xFu;
-        f4 acc = -xv;
-        if (!BF16) {
-#pragma unroll
-          for (int q = 0; q < KQ; ++q) acc = mfma_f32(ua[q], sVt[jl * LDV + 4 * q + g], acc);
-        } else {
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const float* vr = sVt + jl * LDV + 16 * kb + 4 * g;
-            acc = mfma_bf16(uab[kb], pack_bf16(vr[0], vr[1], vr[2], vr[3]), acc);
-          }
-        }
-        float G[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float R = acc[r];
-          const float ar = fabsf(R);
-          float rho = (ar <= lam_s) ? 0.5f * R * R : lam_s * (ar - 0.5f * lam_s);
-          float gr = fminf(fmaxf(R, -lam_s), lam_s);
-          if (MASKED && !((bits >> r) & 1u)) {
-            rho = 0.f;
-            gr = 0.f;
-          }
-          ftile += rho;
-          gtile = fmaf(gr, gr, gtile);
-          G[r] = gr;
-          myT[(4 * g + r) * LDT + c] = gr;
-        }
-        // G^T U of the tile (K = the strip's 16 rows) into the wave's LDS accumulator
-        f4 gvt[KB];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) gvt[kb] = f4{0.f, 0.f, 0.f, 0.f};
-        if (!BF16) {
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) gvt[kb] = mfma_f32(G[r], ub[r][kb], gvt[kb]);
-        } else {
-          const s4 gb = pack_bf16(G[0], G[1], G[2], G[3]);
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) gvt[kb] = mfma_bf16(gb, ubb[kb], gvt[kb]);
-        }
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-          const int kk = 16 * kb + c;
-          if (kk < k) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sGV[(16 * t + 4 * g + r) * k + kk] += gvt[kb][r];
-          }
-        }
-        // G V of the tile (K = the tile's 16 columns) from the transposed G
-        if (!BF16) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float gt = myT[c * LDT + 4 * q + g];
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-              gu[kb] = mfma_f32(gt, sVt[(16 * t + 4 * q + g) * LDV + 16 * kb + c], gu[kb]);
-          }
-        } else {
-          const float* tr = myT + c * LDT + 4 * g;
-          const s4 gtb = pack_bf16(tr[0], tr[1], tr[2], tr[3]);
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
-            gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
-          }
-        }
-      };
-      f4 xa[PF], xb[PF];
-      uint32_t ba[PF] = {}, bb[PF] = {};
-      load_group(0, xa, ba);
-      for (int t0 = 0; t0 < ntiles; t0 += 2 * PF) {
-        // group t0 is in xa; issue group t0+PF into xb, compute xa; then the mirror.
-        // The prefetches are unconditional (past the chunk they re-read its last
-        // column): a conditional load would force a full vmcnt(0) wait at the join.
-        load_group(t0 + PF, xb, bb);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < PF; ++u)
-          if (t0 + u < ntiles) tile(t0 + u, xa[u], ba[u]);
-        if (t0 + PF >= ntiles) break;
-        load_group(t0 + 2 * PF, xa, ba);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < PF; ++u)
-          if (t0 + PF + u < ntiles) tile(t0 + PF + u, xb[u], bb[u]);
+    for (int r = 0; r < 4; ++r) {
+      const float R = acc[r];
+      const float ar = fabsf(R);
+      float rho = (ar <= lam_s) ? 0.5f * R * R : lam_s * (ar - 0.5f * lam_s);
+      float gr = fminf(fmaxf(R, -lam_s), lam_s);
+      if (MASKED && !((bits >> r) & 1u)) {
+        rho = 0.f;
+        gr = 0.f;
       }
-    };
-    if (full) strip(std::true_type{});
-    else strip(std::false_type{});
+      ftile += rho;
+      gtile = fmaf(gr, gr, gtile);
+      G[r] = gr;
+      myT[(4 * g + r) * LDT + c] = gr;
+    }
+    if (!BF16) {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gva[t][kb] = mfma_f32(G[r], o.ub[r][kb], gva[t][kb]);
+    } else {
+      const s4 gb = pack_bf16(G[0], G[1], G[2], G[3]);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        gva[t][kb] = mfma_bf16(gb, pack_bf16(o.ub[0][kb], o.ub[1][kb], o.ub[2][kb], o.ub[3][kb]), gva[t][kb]);
+    }
+    if (!BF16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float gt = myT[c * LDT + 4 * q + g];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) gu[kb] = mfma_f32(gt, sVt[(16 * t + 4 * q + g) * LDV + 16 * kb + c], gu[kb]);
+      }
+    } else {
+      const float* tr = myT + c * LDT + 4 * g;
+      const s4 gtb = pack_bf16(tr[0], tr[1], tr[2], tr[3]);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
+        gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
+      }
+    }
+  };
 
+  auto strip_end = [&](int64_t s, const StripOps<KB>& o, const f4(&gu)[KB], float ftile, float gtile) {
+    const int64_t i0 = s * 16;
     f_acc += (double)ftile;
     gg_acc += (double)gtile;
-    // Finish the strip's rows: lane (g, c) holds G V for rows i0+4g+r, column 16 kb + c.
+    // the regulariser's row term: U itself, or A M_U in preconditioned variables
+    // (the strip's rows go through the wave's transpose tile, one 16-column block at a time)
+    float reg[4][KB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) reg[r][kb] = o.ub[r][kb];
+    if (pc) {
+      const float* __restrict__ MU = pc + k * k;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) reg[r][kb] = 0.f;
+#pragma unroll
+      for (int kbi = 0; kbi < KB; ++kbi) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) myT[(4 * g + r) * LDT + c] = o.ub[r][kbi];
+        for (int t = 0; t < 16 && 16 * kbi + t < k; ++t) {
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const int kk = 16 * kb + c;
+            const float mv = (kk < k) ? MU[(16 * kbi + t) * k + kk] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) reg[r][kb] = fmaf(myT[(4 * g + r) * LDT + t], mv, reg[r][kb]);
+          }
+        }
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t i = i0 + 4 * g + r;
@@ -336,24 +375,108 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
       for (int kb = 0; kb < KB; ++kb) {
         const int kk = 16 * kb + c;
         if (kk < k && i < m) {
-          const int64_t o = i * k + kk;
+          const int64_t oo = i * k + kk;
           if (a.nchunks == 1) {
-            const float gval = fmaf(lam_l, ub[r][kb], gu[kb][r]);
-            a.gU[outi][o] = gval;
-            if (TRIAL) gud_acc += (double)gval * (double)dub[r][kb];
+            const float gval = fmaf(lam_l, reg[r][kb], gu[kb][r]);
+            a.gU[outi][oo] = gval;
+            if (TRIAL) gud_acc += (double)gval * (double)o.dub[r][kb];
           } else {
-            a.gupart[(int64_t)ch * m * k + o] = gu[kb][r];
+            a.gupart[(int64_t)ch * m * k + oo] = gu[kb][r];
           }
           if (ch == 0) {
-            uu_acc += (double)ub[r][kb] * (double)ub[r][kb];
-            if (TRIAL) a.Ut[outi][o] = ub[r][kb];
+            uu_acc += (double)o.ub[r][kb] * (double)reg[r][kb];
+            if (TRIAL) a.Ut[outi][oo] = o.ub[r][kb];
           }
         }
       }
     }
+  };
+
+  // ---- pipelined strips: group gi+1 (or the next strip's group 0 and operands) is in flight
+  //      while group gi is computed
+  if (s_begin < s_pipe_end) {
+    StripOps<KB> ops;
+    load_ops(s_begin, ops);
+    f4 xbuf[2][PF];
+    uint32_t bbuf[2][PF] = {};
+    load_group(s_begin, 0, xbuf[0], bbuf[0]);
+    for (int64_t s = s_begin; s < s_pipe_end; ++s) {
+      const int64_t sn = (s + 1 < s_pipe_end) ? s + 1 : s;
+      StripOps<KB> nops;
+      f4 gu[KB];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) gu[kb] = f4{0.f, 0.f, 0.f, 0.f};
+      float ftile = 0.f, gtile = 0.f;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) {
+        const int cb = gi & 1, nb = cb ^ 1;
+        if (gi + 1 < NG) {
+          load_group(s, gi + 1, xbuf[nb], bbuf[nb]);
+        } else {
+          load_ops(sn, nops);
+          load_group(sn, 0, xbuf[nb], bbuf[nb]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int t = gi * PF + u;
+          if (t < TMAX) {
+            if (t < ntiles) tile(t, ops, xbuf[cb][u], bbuf[cb][u], ftile, gtile, gu);
+          }
+        }
+      }
+      strip_end(s, ops, gu, ftile, gtile);
+      ops = nops;
+    }
+  }
+  // ---- remaining strips (ragged last strip, or X without vector alignment): scalar loads
+  for (int64_t s = s_pipe_end; s < s_end; ++s) {
+    StripOps<KB> ops;
+    load_ops(s, ops);
+    f4 gu[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) gu[kb] = f4{0.f, 0.f, 0.f, 0.f};
+    float ftile = 0.f, gtile = 0.f;
+    const int64_t i0 = s * 16;
+    const float* xbase = X + (j_begin + c) * m + i0 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < TMAX; ++t) {
+      if (t < ntiles) {
+        const int jl = 16 * t + c;
+        const int64_t off = (jl < ncols) ? (int64_t)t * tile_stride : (int64_t)(ncols - 1 - c) * m;
+        f4 xr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i0 + 4 * g + r;
+          const float xv_r = xbase[off + ((i < m) ? r : (m - 1 - i0 - 4 * g))];
+          xr[r] = (i < m) ? xv_r : 0.f;
+        }
+        uint32_t br = 0;
+        if (MASKED) {
+          const int64_t j = j_begin + ((jl < ncols) ? jl : ncols - 1);
+          br = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
+        }
+        tile(t, ops, xr, br, ftile, gtile, gu);
+      }
+    }
+    strip_end(s, ops, gu, ftile, gtile);
   }
 
-  // Sum the waves' G^T U accumulators in a fixed order and write the partial.
+  // ---- the waves' G^T U accumulators: through LDS, summed in a fixed order
+  float* sGV = sGVall + w * cwp * k;
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    if (t < ntiles) {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int kk = 16 * kb + c;
+        if (kk < k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sGV[(16 * t + 4 * g + r) * k + kk] = gva[t][kb][r];
+        }
+      }
+    }
+  }
   __syncthreads();
   float* gvp = a.gvpart + (int64_t)rg * n * k;
   for (int idx = tid; idx < ncols * k; idx += NT) {
@@ -375,20 +498,23 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
   }
 }
 
-template <int KB, bool MASKED, bool TRIAL, bool BF16>
+
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
 __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   extern __shared__ float lds[];
   __shared__ double sRed[WAVES];
-  sweep_item<KB, MASKED, TRIAL, BF16>(a, blockIdx.x, blockIdx.y, lds, sRed);
+  sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(a, blockIdx.x, blockIdx.y, lds, sRed);
 }
 
-// Batched sweep: one persistent launch for every instance of a batch.  Each
-// workgroup pulls (instance, workgroup row, chunk) items from a queue (a
-// counter advanced by one atomic per item, re-armed by the reduction that
-// follows) until the list is drained.  The list is sorted by decreasing cost,
-// so the long items start first and the short ones fill the tail.
-template <bool MASKED, bool TRIAL, bool BF16>
-__global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* args, const SweepItem* items, int nitems,
+// Batched sweep: one persistent launch per tile class (k block, tiles per
+// chunk) for every instance of a batch in that class.  Each workgroup pulls
+// (instance, workgroup row, chunk) items from the class's queue (a counter
+// advanced by one atomic per item, re-armed by the reduction that follows)
+// until the list is drained.  Lists are sorted by decreasing cost, so the long
+// items start first and the short ones fill the tail.
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
+__global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* __restrict__ args,
+                                                    const SweepItem* __restrict__ items, int nitems,
                                                     unsigned* head) {
   extern __shared__ float lds[];
   __shared__ double sRed[WAVES];
@@ -396,25 +522,61 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* args, const
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
     __syncthreads();
-    const int it = s_item;
+    // the item index is uniform: keep it (and what it addresses) in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= nitems) break;
-    const SweepItem b = items[it];
-    if (b.kb == 1)
-      sweep_item<1, MASKED, TRIAL, BF16>(args[b.inst], b.rg, b.ch, lds, sRed);
-    else
-      sweep_item<2, MASKED, TRIAL, BF16>(args[b.inst], b.rg, b.ch, lds, sRed);
+    const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
+    const int rg = __builtin_amdgcn_readfirstlane(items[it].rg);
+    const int ch = __builtin_amdgcn_readfirstlane(items[it].ch);
+    const SweepArgs a = args[inst];
+    sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(a, rg, ch, lds, sRed);
     __syncthreads();
   }
 }
 
 template <bool MASKED, bool TRIAL, bool BF16>
-hipError_t launch_batch(const SweepArgs* args, const SweepItem* items, int nitems, unsigned* head, int grid,
-                        int lds_floats_max, hipStream_t s) {
+hipError_t launch_batch(int kb, int tmax, const SweepArgs* args, const SweepItem* items, int nitems,
+                        unsigned* head, int grid, int lds_floats_max, hipStream_t s) {
   if (lds_floats_max > LDS_LIMIT_FLOATS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep_batch<MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), lds_floats_max * sizeof(float),
-                     s, args, items, nitems, head);
+  const size_t bytes = lds_floats_max * sizeof(float);
+  if (kb == 1 && tmax == 4)
+    hipLaunchKernelGGL((k_sweep_batch<1, 4, MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), bytes, s, args, items, nitems, head);
+  else if (kb == 1 && tmax == 8)
+    hipLaunchKernelGGL((k_sweep_batch<1, 8, MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), bytes, s, args, items, nitems, head);
+  else if (kb == 1 && tmax == 16)
+    hipLaunchKernelGGL((k_sweep_batch<1, 16, MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), bytes, s, args, items, nitems, head);
+  else if (kb == 2 && tmax == 4)
+    hipLaunchKernelGGL((k_sweep_batch<2, 4, MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), bytes, s, args, items, nitems, head);
+  else if (kb == 2 && tmax == 8)
+    hipLaunchKernelGGL((k_sweep_batch<2, 8, MASKED, TRIAL, BF16>), dim3(grid), dim3(NT), bytes, s, args, items, nitems, head);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// Resident workgroups of one class's batched sweep (per CU x CUs).
+template <bool MASKED, bool TRIAL, bool BF16>
+int batch_grid(int kb, int tmax, int lds_floats_max) {
+  int per_cu = 0;
+  const size_t bytes = lds_floats_max * sizeof(float);
+  hipError_t e = hipErrorInvalidValue;
+  if (kb == 1 && tmax == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_batch<1, 4, MASKED, TRIAL, BF16>, NT, bytes);
+  else if (kb == 1 && tmax == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_batch<1, 8, MASKED, TRIAL, BF16>, NT, bytes);
+  else if (kb == 1 && tmax == 16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_batch<1, 16, MASKED, TRIAL, BF16>, NT, bytes);
+  else if (kb == 2 && tmax == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_batch<2, 4, MASKED, TRIAL, BF16>, NT, bytes);
+  else if (kb == 2 && tmax == 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_batch<2, 8, MASKED, TRIAL, BF16>, NT, bytes);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  return per_cu * cus;
 }
 
 template <bool MASKED, bool TRIAL, bool BF16>
@@ -422,14 +584,18 @@ hipError_t launch_kb(const SweepArgs& sa, hipStream_t s) {
   const int kb = (sa.k + 15) / 16;
   const int cwp = (int)(((sa.n < sa.chunk_w ? sa.n : sa.chunk_w) + 15) / 16) * 16;
   const int lds = lds_floats(kb, sa.k, cwp);
-  if (lds > LDS_LIMIT_FLOATS || sa.chunk_w > max_chunk(kb, sa.k)) return hipErrorInvalidValue;
+  if (kb < 1 || kb > 2 || lds > LDS_LIMIT_FLOATS || sa.chunk_w > max_chunk(kb, sa.k)) return hipErrorInvalidValue;
+  const int tm = tmax_class(kb, cwp / 16);
   const dim3 grid(sa.row_groups, sa.nchunks), block(NT);
-  if (kb == 1)
-    hipLaunchKernelGGL((k_sweep<1, MASKED, TRIAL, BF16>), grid, block, lds * sizeof(float), s, sa);
-  else if (kb == 2)
-    hipLaunchKernelGGL((k_sweep<2, MASKED, TRIAL, BF16>), grid, block, lds * sizeof(float), s, sa);
-  else
-    return hipErrorInvalidValue;
+  const size_t bytes = lds * sizeof(float);
+  if (kb == 1) {
+    if (tm == 4) hipLaunchKernelGGL((k_sweep<1, 4, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+    else if (tm == 8) hipLaunchKernelGGL((k_sweep<1, 8, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+    else hipLaunchKernelGGL((k_sweep<1, 16, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+  } else {
+    if (tm == 4) hipLaunchKernelGGL((k_sweep<2, 4, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+    else hipLaunchKernelGGL((k_sweep<2, 8, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+  }
   return hipGetLastError();
 }
 

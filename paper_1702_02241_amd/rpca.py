@@ -38,6 +38,8 @@ class rpca_opts(ctypes.Structure):
         ("rsvd_power", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("slots_per_sync", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("precond_cycle", ctypes.c_int32),
     ]
 
 
@@ -73,7 +75,8 @@ class rpca_cert(ctypes.Structure):
 class rpca_batch_layout(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("sweep_items", ctypes.c_int32),
                 ("sweep_grid_fp32", ctypes.c_int32), ("sweep_grid_bf16", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("sweep_classes", ctypes.c_int32)]
 
 
 class rpca_profile(ctypes.Structure):

@@ -107,7 +107,7 @@ def test_adam_steps_match_oracle():
     net.close()
 
 
-@pytest.mark.parametrize("W,H,f,frames", [(320, 240, 4, 100), (40, 24, 4, 7), (30, 18, 3, 5)])
+@pytest.mark.parametrize("W,H,f,frames", [(320, 240, 4, 100), (64, 48, 4, 7), (60, 45, 3, 5)])
 def test_window_features_match_oracle(W, H, f, frames):
     dev = device()
     X, _, _ = synth.video_frames(n_frames=frames, width=W, height=H, seed=11)
