@@ -9,10 +9,17 @@ timed region starts.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16_polish]
 
 Prints one JSON line.  ``value`` is objective+gradient evaluations per second
-over the timed solves (every line-search trial counts); ``ms_per_step`` is the
-time to a certified solution.  ``roofline`` describes the objective/gradient
-sweep kernel timed with HIP events on its own stream; ``cpu_baseline`` times
-the FP64 NumPy oracle's objective/gradient on the host on a bounded sample.
+over the timed solves (every line-search trial counts, and the time includes
+the start, the certificates and the host); ``ms_per_step`` is the time to a
+certified solution.  ``roofline`` describes the dominant kernel, the
+objective/gradient sweep, timed with the library's HIP events on its launch
+stream over back-to-back evaluations; its ``traffic`` comes from the committed
+rocprofv3 counter summary under profiles/ (null once the sweep source
+differs from the one measured).  ``solve_kernel_ms_per_step`` is the device
+time per kernel class, from a second pass over the same solves with the
+events on.  ``objgrad_evals_per_s`` is the rate of the
+objective+gradient alone; ``cpu_baseline`` times the FP64 NumPy oracle's
+objective+gradient on the host on a bounded sample.
 """
 import argparse
 import json
@@ -37,7 +44,66 @@ def parse():
     ap.add_argument("--objgrad-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--probe", choices=["objgrad", "solve", "copy"], default=None,
+                    help="profiling aid: run --reps objective/gradient evaluations (or device copies of X, "
+                         "the calibration of the HBM byte counters) at the workload's shape and exit")
+    ap.add_argument("--reps", type=int, default=20)
     return ap.parse_args()
+
+
+def probe(args):
+    """Short fixed workloads for rocprofv3 counter runs (no JSON line)."""
+    import torch
+
+    from paper_1702_02241_amd import synth
+    from paper_1702_02241_amd import torch_api as T
+    dev = torch.device("cuda:0")
+    p = synth.video()
+    Xcm = T.to_device_X(p.X, dev)
+    if args.probe == "copy":
+        # one elementwise kernel: reads X once, writes a same-size buffer once
+        Y = torch.empty_like(Xcm)
+        for _ in range(args.reps):
+            torch.mul(Xcm, 1.0, out=Y)
+        torch.cuda.synchronize()
+        print(f"probe copy: {args.reps} x (read {Xcm.numel() * 4} B + write {Y.numel() * 4} B)")
+        return
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    U, V = ctx.init_rsvd(Xcm)
+    if args.probe == "solve":
+        # line-search trial sweeps: --reps L-BFGS iterations from the cold start, no certificate
+        ctx.solve(Xcm, U, V, certify=0, max_iter=args.reps)
+        torch.cuda.synchronize()
+        print(f"probe solve: {args.reps} iterations at {p.m}x{p.n}, k={p.k}")
+    else:
+        for _ in range(args.reps):
+            ctx.objgrad(Xcm, U, V)
+        torch.cuda.synchronize()
+        print(f"probe objgrad: {args.reps} evaluations at {p.m}x{p.n}, k={p.k}")
+    ctx.close()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_video76800x200_hbm_traffic.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_1702_02241_amd", "csrc", "sweep_kernel.h")
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when the sweep source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
+                                                                           "sweep_kernel_h_sha256:")))
+    if vals.get("sweep_kernel_h_sha256", "").strip() != src:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(p, U, V, budget_s):
@@ -68,6 +134,9 @@ def cpu_baseline(p, U, V, budget_s):
 
 def main():
     args = parse()
+    if args.probe:
+        probe(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is the single-GPU kernel; "
               "multi-GPU sharding is described in DESIGN.md and not built", file=sys.stderr)
@@ -93,6 +162,7 @@ def main():
     for _ in range(args.warmup):
         ctx.solve(Xcm, U, V, **opts)
     torch.cuda.synchronize()
+    # Timed region: the certified solves.
     infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -104,13 +174,24 @@ def main():
     ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
     last_rc, last = infos[-1]
 
-    # Per-class device time of one more solve (HIP events on the launch stream).
+    # The same solves again with the library's per-launch HIP events (recorded on the
+    # stream each kernel is launched on): device time per kernel class and step.
     R.rpca_profile_enable(ctx.ctx, True)
     R.rpca_profile_read(ctx.ctx, reset=True)
-    ctx.solve(Xcm, U, V, **opts)
+    for _ in range(args.steps):
+        ctx.solve(Xcm, U, V, **opts)
     torch.cuda.synchronize()
     _, prof_solve = R.rpca_profile_read(ctx.ctx, reset=True)
-    # The dominant kernel: the objective/gradient sweep, timed alone over repeated launches.
+    classes = {"sweep": R.RPCA_K_SWEEP, "trial_sweep": R.RPCA_K_TRIAL, "finish": R.RPCA_K_FINISH,
+               "update": R.RPCA_K_UPDATE, "direction": R.RPCA_K_DIRECTION}
+    solve_breakdown = {c: dict(launches=int(prof_solve.launches[i]) // max(args.steps, 1),
+                               ms=round(prof_solve.ms[i] / max(args.steps, 1), 3))
+                       for c, i in classes.items()}
+
+    # The dominant kernel, the objective/gradient sweep, timed with HIP events over
+    # back-to-back evaluations (the trial-point sweeps inside the solves are the same
+    # kernel reading U + alpha dU as well; launches that find the solve finished
+    # exit at once and would bias an average over the solves).
     for _ in range(args.objgrad_reps):
         ctx.objgrad(Xcm, U, V)
     torch.cuda.synchronize()
@@ -118,17 +199,21 @@ def main():
     R.rpca_profile_enable(ctx.ctx, False)
     sweep_ms = prof.ms[R.RPCA_K_SWEEP] / max(prof.launches[R.RPCA_K_SWEEP], 1)
     finish_ms = prof.ms[R.RPCA_K_FINISH] / max(prof.launches[R.RPCA_K_FINISH], 1)
-    # algorithmic bytes of one sweep: read X, U, V once, write G V + lam U (gU)
-    alg_bytes = 4 * (m * n + m * k + n * k + m * k)
+    # algorithmic bytes of one evaluation: read X, U, V once, write gU = G V + lam_L U
+    alg_bytes = 4 * (m * n + 2 * m * k + n * k)
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="k_objgrad_sweep (plain evaluation)",
-                    kernel_ms=round(sweep_ms, 5), finish_ms=round(finish_ms, 5),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                    kernel="k_sweep (objective/gradient evaluation)", kernel_ms=round(sweep_ms, 5),
+                    launches=int(prof.launches[R.RPCA_K_SWEEP]), finish_ms=round(finish_ms, 5),
                     alg_bytes_per_launch=alg_bytes)
-    classes = ["sweep", "finish", "update", "direction"]
-    solve_breakdown = {c: dict(launches=int(prof_solve.launches[i]), ms=round(prof_solve.ms[i], 3))
-                       for i, c in enumerate(classes)}
+    # objective+gradient rate without the events
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.objgrad_reps):
+        ctx.objgrad(Xcm, U, V)
+    torch.cuda.synchronize()
+    og_rate = args.objgrad_reps / (time.perf_counter() - t1)
 
     cpu = None
     if not args.no_cpu:
@@ -159,7 +244,8 @@ def main():
         "certified": int(all(i.certified for _, i in infos)),
         "rel_gap": last.rel_gap,
         "status": last_rc,
-        "solve_kernel_ms": solve_breakdown,
+        "solve_kernel_ms_per_step": solve_breakdown,
+        "objgrad_evals_per_s": round(og_rate, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

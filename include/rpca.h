@@ -172,10 +172,11 @@ int rpca_init_rsvd(rpca_ctx* ctx, const float* X, const float* Omega_s, int32_t 
 
 /* Kernel classes reported by the profiler. */
 enum rpca_kernel_class {
-  RPCA_K_SWEEP = 0,       /* fused objective/gradient sweep over X */
+  RPCA_K_SWEEP = 0,       /* fused objective/gradient sweep over X (plain evaluations) */
   RPCA_K_FINISH = 1,      /* finishing reduction + line-search step */
   RPCA_K_UPDATE = 2,      /* L-BFGS history update (FP64 dots) */
   RPCA_K_DIRECTION = 3,   /* L-BFGS direction */
+  RPCA_K_TRIAL = 4,       /* the same sweep at line-search trial points */
   RPCA_K_NCLASS = 8
 };
 

@@ -158,7 +158,7 @@ hipError_t timed(rpca_ctx* c, int cls, hipStream_t s, F&& launch) {
 
 hipError_t objgrad_launch(rpca_ctx* c, const SweepArgs& sa, const FinishArgs& fa, bool trial,
                           bool bf16, hipStream_t s) {
-  hipError_t e = timed(c, RPCA_K_SWEEP, s, [&] { return rpca::launch_sweep(sa, trial, bf16, s); });
+  hipError_t e = timed(c, trial ? RPCA_K_TRIAL : RPCA_K_SWEEP, s, [&] { return rpca::launch_sweep(sa, trial, bf16, s); });
   if (e != hipSuccess) return e;
   return timed(c, RPCA_K_FINISH, s, [&] { return rpca::launch_finish(fa, trial, s); });
 }
@@ -376,6 +376,8 @@ CtxView ctx_view(rpca_ctx* c) {
   v.mask = c->mask;
   v.mw = c->mw;
   v.best_F = &c->best_F;
+  v.phi0 = &c->phi0;
+  v.phi0_X = &c->phi0_X;
   return v;
 }
 
@@ -591,6 +593,8 @@ int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts
   }
   HIPCHK(hipMemcpyAsync(c->x[0], U, mk * 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(c->x[0] + mk, V, nk * 4, hipMemcpyDeviceToDevice, s));
+  c->phi0 = NAN;  // X may have changed since the last solve
+  c->phi0_X = nullptr;
   SolverState* h = c->st_host;
   memset(h, 0, sizeof(*h));
   h->phase = PH_DIRECTION;
@@ -631,7 +635,7 @@ int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opt
     const int stop = c->st_host->stop;
     if (!o.certify || stop == STOP_NONFINITE) break;
     rpca_cert cert;
-    const int crc = rpca_certificate(c, X, U, V, &cert, s);
+    const int crc = certificate_impl(c, X, U, V, &cert, o.cert_tol, s);
     if (crc < 0) return crc;
     ++rounds;
     rel_gap = cert.rel_gap;
@@ -640,7 +644,7 @@ int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opt
     // Not certified yet: continue from here.  Near the optimum f changes by less
     // than its FP32 evaluation noise per iteration while the gradient still
     // carries the structure the certificate measures, so the round runs with
-    // the stopping tests off, for one preconditioner cycle (plain variables: a
+    // the stopping tests off, for half a preconditioner cycle (plain variables: a
     // tenfold tighter gradient test), and ends at the cycle's cap or when the
     // line search can no longer make progress.
     if (o.precond) {
@@ -650,7 +654,8 @@ int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opt
       gtol *= 0.1;
       ftol = 0.0;
     }
-    if ((rc = run_cycles(c, X, o, final_bf16, gtol, ftol, true, o.precond ? o.precond_cycle : 0, s))) return rc;
+    const int round_budget = o.precond ? (o.precond_cycle > 1 ? o.precond_cycle / 2 : 1) : 0;
+    if ((rc = run_cycles(c, X, o, final_bf16, gtol, ftol, true, round_budget, s))) return rc;
     if (c->st_host->stop == STOP_MAXITER && c->st_host->iter < o.max_iter) c->st_host->stop = STOP_GTOL;
   }
   HIPCHK(hipStreamSynchronize(s));

@@ -236,15 +236,26 @@ __global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
     out[(j_begin + idx / BP) * BP + idx % BP] = sZ[idx];
 }
 
-__global__ void k_right_reduce(const double* part, int row_groups, int64_t n, double* Z, int ldz,
-                               int col0, int bw) {
-  const int64_t o = (int64_t)blockIdx.x * THREADS + threadIdx.x;
-  if (o >= n * BP) return;
-  const int p = (int)(o % BP);
-  if (p >= bw) return;
+// Z[:, col0 + p] = sum over row groups of the partials.  Block = RR_OUT outputs x
+// RR_SUB row-group subsets (subset q sums groups q, q + RR_SUB, ...); the subsets
+// are then added in a fixed order.
+constexpr int RR_OUT = 32, RR_SUB = THREADS / RR_OUT;
+__global__ __launch_bounds__(THREADS) void k_right_reduce(const double* part, int row_groups, int64_t n, double* Z,
+                                                          int ldz, int col0, int bw) {
+  __shared__ double sh[RR_SUB][RR_OUT];
+  const int lo = threadIdx.x % RR_OUT, q = threadIdx.x / RR_OUT;
+  const int64_t o = (int64_t)blockIdx.x * RR_OUT + lo;
   double s = 0.0;
-  for (int r = 0; r < row_groups; ++r) s += part[(int64_t)r * n * BP + o];
-  Z[(o / BP) * ldz + col0 + p] = s;
+  if (o < n * BP)
+    for (int r = q; r < row_groups; r += RR_SUB) s += part[(int64_t)r * n * BP + o];
+  sh[q][lo] = s;
+  __syncthreads();
+  if (q == 0 && o < n * BP) {
+    double t = sh[0][lo];
+    for (int u = 1; u < RR_SUB; ++u) t += sh[u][lo];
+    const int p = (int)(o % BP);
+    if (p < bw) Z[(o / BP) * ldz + col0 + p] = t;
+  }
 }
 
 // Gram matrices of thin row sets, FP64.  mode 0: row i = [A_i, B_i - lam A_i]
@@ -410,8 +421,8 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t outs = cv.n * BP;
-    hipLaunchKernelGGL(k_right_reduce, dim3((unsigned)((outs + THREADS - 1) / THREADS)), dim3(THREADS),
-                       0, s, (const double*)w.part, w.rg_right, cv.n, Z, ldz, col0, a.bw);
+    hipLaunchKernelGGL(k_right_reduce, dim3((unsigned)((outs + RR_OUT - 1) / RR_OUT)), dim3(THREADS), 0, s,
+                       (const double*)w.part, w.rg_right, cv.n, Z, ldz, col0, a.bw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -540,10 +551,14 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
 
 }  // namespace
 
-extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, const float* V,
-                                rpca_cert* out, void* stream) {
-  if (!c || !X || !U || !V || !out) return RPCA_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+namespace rpca {
+
+// The certificate of (U, V).  quick_tol > 0 (the solver's own rounds): phi(0) is
+// taken from the solve's cache when known, and when the terms that need no power
+// iteration already put rel_gap above quick_tol the power iteration is skipped
+// (T4 = 0 then, rel_gap is the lower bound it gives, certified = 0).
+int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V, rpca_cert* out,
+                     double quick_tol, hipStream_t s) {
   const rpca::CtxView cv = rpca::ctx_view(c);
   const int64_t m = cv.m, n = cv.n;
   const int k = cv.k;
@@ -552,16 +567,24 @@ extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, con
   int rc = get_workspace(c, &ws, s);
   if (rc) return rc;
   memset(out, 0, sizeof(*out));
-  // 1. phi(0) from a sweep at U = V = 0, then one sweep at (U, V): G V, G^T U,
-  //    phi(L), ||U||^2, ||V||^2, ||G||^2
-  rc = rpca::ctx_objgrad_aux(c, X, ws.zU, ws.zV, ws.scal + 8, ws.scal + 9, ws.gU, ws.gV, s);
-  if (rc) return rc;
+  // 1. phi(0) from a sweep at U = V = 0 (or the solve's cache), then one sweep at
+  //    (U, V): G V, G^T U, phi(L), ||U||^2, ||V||^2, ||G||^2
+  const bool cached = quick_tol > 0 && cv.phi0_X && *cv.phi0_X == (const void*)X && isfinite(*cv.phi0);
+  if (!cached) {
+    rc = rpca::ctx_objgrad_aux(c, X, ws.zU, ws.zV, ws.scal + 8, ws.scal + 9, ws.gU, ws.gV, s);
+    if (rc) return rc;
+  }
   rc = rpca::ctx_objgrad_aux(c, X, U, V, ws.scal, ws.scal + 1, ws.gU, ws.gV, s);
   if (rc) return rc;
   double scal[16];
   if (hipMemcpyAsync(scal, ws.scal, sizeof(scal), hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
-  const double phiL = scal[1], g2 = scal[4], phi0 = scal[9];
+  const double phiL = scal[1], g2 = scal[4];
+  const double phi0 = cached ? *cv.phi0 : scal[9];
+  if (cv.phi0_X) {
+    *cv.phi0 = phi0;
+    *cv.phi0_X = (const void*)X;
+  }
   // 2. Gram matrices [U, G V] (m rows) and [V, G^T U] (n rows), 2k x 2k
   std::vector<double> GU, GV;
   GramArgs ga;
@@ -671,6 +694,43 @@ extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, con
   }
   const double nD2 = g2 / (lam_l * lam_l);
   const double normM2 = std::max(nD2 - nDtU1 - nDV1 + nC, 0.0);
+  // Quick rejection: T4 >= 0, so the other terms alone bound rel_gap from below.
+  if (quick_tol > 0) {
+    double nuc = 0.0, normL2 = 0.0, trunc2 = 0.0;
+    for (int i = 0; i < k; ++i) {
+      nuc += sig[i];
+      normL2 += sig[i] * sig[i];
+      if (i >= r) trunc2 += sig[i] * sig[i];
+    }
+    const double E_lo = sqrt(std::max(T1 + T2 + T3, 0.0)) + sqrt(trunc2) / lam_l;
+    const double F = lam_l * nuc + phiL;
+    double* best = cv.best_F;
+    if (F < *best) *best = F;
+    const double Fb = std::min(std::min(F, phi0), *best);
+    const double gap_lo = E_lo * (lam_l * sqrt(normL2) + Fb);
+    const double rel_lo = F > 0 ? gap_lo / F : INFINITY;
+    if (rel_lo > quick_tol) {
+      out->T1 = T1;
+      out->T2 = T2;
+      out->T3 = T3;
+      out->T4 = 0.0;
+      out->E = E_lo;
+      out->F = F;
+      out->phi = phiL;
+      out->phi0 = phi0;
+      out->F_bound = Fb;
+      out->normL = sqrt(normL2);
+      out->gap = gap_lo;
+      out->rel_gap = rel_lo;
+      out->normM2 = normM2;
+      for (int i = 0; i < k && i < 64; ++i) out->sigma[i] = sig[i];
+      out->r = r;
+      out->power_iters = 0;
+      out->block = 0;
+      out->certified = 0;
+      return RPCA_OK;
+    }
+  }
   // 5. T4 by block power iteration on M^T M (host-side projections, n x b).  The
   //    block grows (8 -> 16 -> 32) while its smallest Ritz value is still above 1,
   //    so that every singular value above 1 is captured when there are at most 31.
@@ -767,7 +827,7 @@ extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, con
       Xb = Zb;
       orth_host(Xb, b);
       const bool all_conv = dmax <= 1e-8 * std::max(ritz[0], 1e-300);
-      const bool below_one = ritz[0] < 0.98 * 0.98 && d0 <= 1e-7 * ritz[0];
+      const bool below_one = ritz[0] < 0.98 * 0.98 && d0 <= 1e-5 * ritz[0];
       if (it > 2 && (all_conv || below_one)) break;
     }
     if (sqrt(ritz[b - 1]) > 1.0 && b < bmax) {
@@ -837,6 +897,14 @@ extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, con
   out->block = b;
   out->certified = out->rel_gap <= 1e-3;
   return RPCA_OK;
+}
+
+}  // namespace rpca
+
+extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, const float* V,
+                                rpca_cert* out, void* stream) {
+  if (!c || !X || !U || !V || !out) return RPCA_EINVAL;
+  return rpca::certificate_impl(c, X, U, V, out, 0.0, (hipStream_t)stream);
 }
 
 extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s, int32_t oversample,

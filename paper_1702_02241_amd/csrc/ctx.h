@@ -34,6 +34,8 @@ struct rpca_ctx {
   SolverState* st_host = nullptr;  // pinned host mirror
   double* dscratch = nullptr;      // device doubles for small results
   double best_F = INFINITY;        // best convex objective seen by certificates
+  double phi0 = NAN;               // phi(0) cached for the certificates of one solve
+  const void* phi0_X = nullptr;    // ... and the X it was computed from
   // preconditioned variables A = U P_U^{-1}, B = V P_V^{-1} (see precond.hip)
   bool pc_on = false;
   float* pc_dev = nullptr;         // [W | M_U | M_V | P_U | P_V | P_U^{-1} | P_V^{-1}], k x k each

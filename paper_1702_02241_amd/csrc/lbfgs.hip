@@ -11,12 +11,11 @@
 // where R is the upper triangle of S^T Y and Dg its diagonal.  One pass over
 // the history ("update") computes every inner product the small matrices need
 // in FP64; a second pass ("direction") forms d = -H g.  Both passes end in a
-// last-block reduction that runs the small (mem x mem) algebra on one
-// thread, so the whole iteration stays on the device.
+// one-block kernel that combines the block partials and runs the small
+// (mem x mem) algebra (one wave), so the whole iteration stays on the device.
 #include "rpca_internal.h"
 
 #include <math.h>
-#include <stdlib.h>
 
 namespace {
 
@@ -59,14 +58,17 @@ __device__ void block_partials(const double (&acc)[NV], double* part, int bx, in
   }
 }
 
-// One block: combine the nb block partials of NV values in a fixed order into out[] (LDS).
+// One block: combine the nb block partials of NV values in a fixed order into out[]
+// (LDS).  Thread t sums partials t, t + THREADS, ... of every value (all loads
+// independent, so they are in flight together), then wave reductions and the
+// waves in a fixed order.
 template <int NV, int IMAX>
 __device__ void combine_partials(const double* part, int nb, double* out) {
   __shared__ double sh[WAVES][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double r[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) r[v] = 0.0;
+  for (int v = 0; v < NV; ++v) r[v] = 0.0;  // the max value (|g|) is >= 0: 0 is its identity too
   for (int b = threadIdx.x; b < nb; b += THREADS) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -103,41 +105,11 @@ struct DotIdx {
   static constexpr int NV = SY + 8;
 };
 
-// Compact-form coefficients from the ordered small matrices (one thread).
-__device__ void compact_coefficients(SolverState* st, const double* a_ord, const double* b_ord) {
-  const int h = st->count;
-  double u[RPCA_MEMMAX], w[RPCA_MEMMAX], p[RPCA_MEMMAX];
-  const double gamma = st->gamma;
-  // u = R^{-1} a  (R upper triangular, R_ij = s_i^T y_j for i <= j)
-  for (int i = h - 1; i >= 0; --i) {
-    double s = a_ord[i];
-    for (int j = i + 1; j < h; ++j) s -= st->SY[st->order[i]][st->order[j]] * u[j];
-    u[i] = s / st->SY[st->order[i]][st->order[i]];
-  }
-  // w = Dg u + gamma Y^T Y u - gamma b
-  for (int i = 0; i < h; ++i) {
-    double s = st->SY[st->order[i]][st->order[i]] * u[i] - gamma * b_ord[i];
-    for (int j = 0; j < h; ++j) s += gamma * st->YY[st->order[i]][st->order[j]] * u[j];
-    w[i] = s;
-  }
-  // p = R^{-T} w  (forward substitution with R^T lower triangular)
-  for (int i = 0; i < h; ++i) {
-    double s = w[i];
-    for (int j = 0; j < i; ++j) s -= st->SY[st->order[j]][st->order[i]] * p[j];
-    p[i] = s / st->SY[st->order[i]][st->order[i]];
-  }
-  for (int i = 0; i < RPCA_MEMMAX; ++i) {
-    st->coef_s[i] = 0.0;
-    st->coef_y[i] = 0.0;
-  }
-  for (int i = 0; i < h; ++i) {
-    st->coef_s[st->order[i]] = p[i];
-    st->coef_y[st->order[i]] = -gamma * u[i];
-  }
-}
-
+// Pair bookkeeping of the update (one thread): norms, the keep test, the new
+// pair's inner products into the slot matrices, the ring order, gamma.  The
+// ordered a = S^T g and b = Y^T g go to a_ord / b_ord.
 template <int MEM>
-__device__ void update_small_math(SolverState* st, const double* D) {
+__device__ void update_pairs(SolverState* st, const double* D, double* a_ord, double* b_ord) {
   using I = DotIdx<MEM>;
   const int cnt = st->count;
   const double sy = D[I::SY], yy = D[I::YY], ss = D[I::SS];
@@ -145,7 +117,6 @@ __device__ void update_small_math(SolverState* st, const double* D) {
   st->gnorm_inf = D[I::GINF];
   st->gnorm1 = D[I::G1];
   st->gg = D[I::GG];
-  double a_ord[RPCA_MEMMAX], b_ord[RPCA_MEMMAX];
   for (int i = 0; i < cnt; ++i) {
     a_ord[i] = D[4 * i + 0];
     b_ord[i] = D[4 * i + 1];
@@ -185,8 +156,51 @@ __device__ void update_small_math(SolverState* st, const double* D) {
     st->newest = sn;
     st->gamma = sy / yy;
   }
-  if (st->count > 0) compact_coefficients(st, a_ord, b_ord);
-  // stopping tests
+}
+
+// Compact-form coefficients from dense, ordered copies R[i][j] = s_i^T y_j and
+// Q[i][j] = y_i^T y_j, by one wave: lane j holds entry j of the sums, the
+// triangular solves step through i with a wave reduction each (h <= 15 steps).
+// u, w, p live in LDS (us, ps) so every lane sees them.
+__device__ void compact_wave(SolverState* st, const double (*R)[RPCA_MEMMAX], const double (*Q)[RPCA_MEMMAX],
+                             const double* a_ord, const double* b_ord, double* us, double* ps) {
+  const int lane = threadIdx.x & 63;
+  const int h = st->count;
+  const double gamma = st->gamma;
+  // u = R^{-1} a  (R upper triangular): u_i = (a_i - sum_{j>i} R_ij u_j) / R_ii
+  for (int i = h - 1; i >= 0; --i) {
+    double t = (lane > i && lane < h) ? R[i][lane] * us[lane] : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) us[i] = (a_ord[i] - t) / R[i][i];
+  }
+  // w_i = R_ii u_i - gamma b_i + gamma sum_j Q_ij u_j  (lane i)
+  double wv = 0.0;
+  if (lane < h) {
+    double acc = R[lane][lane] * us[lane] - gamma * b_ord[lane];
+    for (int j2 = 0; j2 < h; ++j2) acc += gamma * Q[lane][j2] * us[j2];
+    wv = acc;
+  }
+  // p = R^{-T} w: p_i = (w_i - sum_{j<i} R_ji p_j) / R_ii
+  for (int i = 0; i < h; ++i) {
+    double t = (lane < i) ? R[lane][i] * ps[lane] : 0.0;
+    t = wave_sum(t);
+    const double wi = __shfl(wv, i, 64);
+    if (lane == 0) ps[i] = (wi - t) / R[i][i];
+  }
+  if (lane < RPCA_MEMMAX) {
+    st->coef_s[lane] = 0.0;
+    st->coef_y[lane] = 0.0;
+  }
+  if (lane < h) {
+    st->coef_s[st->order[lane]] = ps[lane];
+    st->coef_y[st->order[lane]] = -gamma * us[lane];
+  }
+}
+
+// Stopping tests after an update (one thread).
+template <int MEM>
+__device__ void update_stops(SolverState* st, const double* D) {
+  using I = DotIdx<MEM>;
   const double f = st->f;
   for (int i = 0; i < 7; ++i) st->fhist[i] = st->fhist[i + 1];
   st->fhist[7] = f;
@@ -201,7 +215,6 @@ __device__ void update_small_math(SolverState* st, const double* D) {
   st->phase = (stop == STOP_NONE) ? PH_DIRECTION : PH_DONE;
 }
 
-// Blocks bx of nb of one instance (the single-instance grid or a slice of a batched one).
 template <int MEM>
 __device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, int nb) {
   using I = DotIdx<MEM>;
@@ -276,9 +289,26 @@ __device__ __forceinline__ void lbfgs_update_final_body(const LbfgsArgs& a, int 
   __shared__ double D[NV];
   combine_partials<NV, I::GINF>(a.part, nb, D);
   __shared__ SolverState sst;
+  __shared__ double a_ord[RPCA_MEMMAX], b_ord[RPCA_MEMMAX];
+  __shared__ double R[RPCA_MEMMAX][RPCA_MEMMAX], Q[RPCA_MEMMAX][RPCA_MEMMAX];
   copy_state_block(&sst, st);
   __syncthreads();
-  if (threadIdx.x == 0) update_small_math<MEM>(&sst, D);
+  if (threadIdx.x == 0) update_pairs<MEM>(&sst, D, a_ord, b_ord);
+  __syncthreads();
+  {
+    // dense ordered copies of the pair matrices (one entry per thread)
+    const int h = sst.count;
+    const int i = threadIdx.x / RPCA_MEMMAX, j = threadIdx.x % RPCA_MEMMAX;
+    if (i < h && j < h) {
+      R[i][j] = sst.SY[sst.order[i]][sst.order[j]];
+      Q[i][j] = sst.YY[sst.order[i]][sst.order[j]];
+    }
+  }
+  __syncthreads();
+  __shared__ double us[RPCA_MEMMAX], ps[RPCA_MEMMAX];
+  if (threadIdx.x < 64 && sst.count > 0) compact_wave(&sst, R, Q, a_ord, b_ord, us, ps);
+  __syncthreads();
+  if (threadIdx.x == 0) update_stops<MEM>(&sst, D);
   __syncthreads();
   copy_state_block(st, &sst);
 }
@@ -411,14 +441,11 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final_batch(const L
 namespace rpca {
 
 int lbfgs_blocks(int64_t N) {
-  // about one float4 per thread, at most cap blocks
-  static int cap = [] {
-    const char* e = getenv("RPCA_LBFGS_BLOCKS_EXPT");
-    return e ? atoi(e) : 1024;
-  }();
+  // about one float4 per thread, at most 512 blocks (two per CU): fewer blocks
+  // mean fewer partials for the one-block combine that follows
   int64_t b = (N / 4 + THREADS - 1) / THREADS;
   if (b < 1) b = 1;
-  if (b > cap) b = cap;
+  if (b > 512) b = 512;
   return (int)b;
 }
 

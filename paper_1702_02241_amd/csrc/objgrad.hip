@@ -179,13 +179,32 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
     p1 += a.fpart[b * 3 + 1];
     p2 += a.fpart[b * 3 + 2];
   }
-  fd = block_sum<FIN_THREADS>(fd, sh);
-  uu = block_sum<FIN_THREADS>(uu, sh);
-  gd1 = block_sum<FIN_THREADS>(gd1, sh);
-  g2 = block_sum<FIN_THREADS>(g2, sh);
-  p0 = block_sum<FIN_THREADS>(p0, sh);
-  p1 = block_sum<FIN_THREADS>(p1, sh);
-  p2 = block_sum<FIN_THREADS>(p2, sh);
+  {
+    // the seven sums in one pass: wave reductions, then the waves in a fixed order
+    __shared__ double sh7[FIN_THREADS / 64][7];
+    double v[7] = {fd, uu, gd1, g2, p0, p1, p2};
+#pragma unroll
+    for (int e = 0; e < 7; ++e)
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v[e] += __shfl_xor(v[e], o, 64);
+    if ((tid & 63) == 0)
+#pragma unroll
+      for (int e = 0; e < 7; ++e) sh7[tid >> 6][e] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+      double r = 0.0;
+      for (int w = 0; w < FIN_THREADS / 64; ++w) r += sh7[w][e];
+      v[e] = r;
+    }
+    fd = v[0];
+    uu = v[1];
+    gd1 = v[2];
+    g2 = v[3];
+    p0 = v[4];
+    p1 = v[5];
+    p2 = v[6];
+  }
   if (!TRIAL) {
     if (tid == 0) {
       *a.f_out = fd + 0.5 * (double)lam_l * (uu + p0);
@@ -199,16 +218,16 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
     }
     return;
   }
-  // line-search step on an LDS copy of the state (one thread), written back by the block
+  // line-search step on an LDS copy of the state head (one thread), written back by the block
   __shared__ SolverState sst;
-  copy_state_block(&sst, st);
+  copy_state_head(&sst, st);
   __syncthreads();
   if (tid == 0) {
     rpca_ls::line_search_step(&sst, fd + 0.5 * (double)lam_l * (uu + p0), gd1 + p1 + p2);
     *a.counter = 0u;
   }
   __syncthreads();
-  copy_state_block(st, &sst);
+  copy_state_head(st, &sst);
 }
 
 template <bool TRIAL>

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <chrono>
@@ -61,12 +62,13 @@ struct SolverState {
   double f_t, dphi_t;   // last trial
   double dd;            // d^T d
   double gamma;
+  double fhist[8];
+  double best_f;
+  // --- everything above is the state head (what the line search reads and writes) ---
   double SY[RPCA_MEMMAX][RPCA_MEMMAX];  // s_i^T y_j by slot
   double YY[RPCA_MEMMAX][RPCA_MEMMAX];  // y_i^T y_j by slot
   double coef_s[RPCA_MEMMAX];           // d = -(gamma g + sum coef_s[slot] s_slot + sum coef_y[slot] y_slot)
   double coef_y[RPCA_MEMMAX];
-  double fhist[8];
-  double best_f;
 };
 
 // Block-cooperative copy of the solver state in 8-byte words (used to stage the
@@ -76,6 +78,14 @@ __device__ __forceinline__ void copy_state_block(SolverState* dst, const SolverS
   const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
   unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
   for (int i = threadIdx.x; i < (int)(sizeof(SolverState) / 8); i += blockDim.x) d[i] = s[i];
+}
+
+// The same for the state head only (the fields before the (s, y) Gram matrices).
+__device__ __forceinline__ void copy_state_head(SolverState* dst, const SolverState* src) {
+  static_assert(offsetof(SolverState, SY) % 8 == 0, "state head size");
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int i = threadIdx.x; i < (int)(offsetof(SolverState, SY) / 8); i += blockDim.x) d[i] = s[i];
 }
 
 // Arguments of the fused objective/gradient sweep.
@@ -201,8 +211,12 @@ struct CtxView {
   const uint32_t* mask;
   int mw;
   double* best_F;
+  double* phi0;          // phi(0) of the current solve (NaN: unknown)
+  const void** phi0_X;   // the X it belongs to
 };
 CtxView ctx_view(rpca_ctx* c);
+int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V, rpca_cert* out,
+                     double quick_tol, hipStream_t s);
 int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V, double* f_dev,
                     double* aux_dev, float* gU, float* gV, hipStream_t s);
 // Device workspace owned by the context, grown on demand; *fresh = 1 when newly allocated.

@@ -8,7 +8,8 @@
 //
 // Work split.  The columns are cut into chunks (grid.y) of at most TMAX
 // 16-column tiles that fit the LDS budget below; V of the chunk is staged in
-// LDS.  Every wave owns a contiguous run of 16-row strips and walks the
+// LDS.  Every wave owns every fourth 16-row strip of its workgroup's rows (the
+// neighbouring waves read the other halves of the same cache lines) and walks the
 // chunk's tiles of each strip in groups of PF.  While a group is computed the
 // next one is in flight; the last group of a strip prefetches the next
 // strip's operands and first group, so the load stream never drains between
@@ -203,16 +204,26 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     for (int kb = 0; kb < KB; ++kb) gva[t][kb] = f4{0.f, 0.f, 0.f, 0.f};
 
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
+  // The workgroup owns strips [rg * WAVES * spw, (rg + 1) * WAVES * spw); wave w
+  // takes every WAVES-th of them starting at w.  A 16-row strip reads half of
+  // each 128-byte line of a column; the neighbouring wave reads the other half
+  // at about the same time, so each line comes from HBM once.
   const int64_t nstrips = (m + 15) >> 4;
-  const int64_t gw = (int64_t)rg * WAVES + w;
-  const int64_t s_begin = gw * a.strips_per_wave;
-  int64_t s_end = s_begin + a.strips_per_wave;
-  if (s_end > nstrips) s_end = nstrips;
+  const int64_t s_first = (int64_t)rg * WAVES * a.strips_per_wave + w;
+  int64_t n_all = 0;  // strips of this wave: s_first + WAVES * j, j < n_all
+  if (s_first < nstrips) {
+    n_all = (nstrips - s_first + WAVES - 1) / WAVES;
+    if (n_all > a.strips_per_wave) n_all = a.strips_per_wave;
+  }
   const bool vec = a.xvec != 0;
-  // strips whose 16 rows are all inside X take the pipelined vector path
-  int64_t s_pipe_end = vec ? (m >> 4) : 0;
-  if (s_pipe_end > s_end) s_pipe_end = s_end;
-  if (s_pipe_end < s_begin) s_pipe_end = s_begin;
+  // strips whose 16 rows are all inside X (a prefix of the wave's list) take the
+  // pipelined vector path
+  const int64_t full_lim = vec ? (m >> 4) : 0;
+  int64_t n_pipe = 0;
+  if (s_first < full_lim) {
+    n_pipe = (full_lim - s_first + WAVES - 1) / WAVES;
+    if (n_pipe > n_all) n_pipe = n_all;
+  }
   const int64_t tile_stride = 16 * m;
 
   auto load_ops = [&](int64_t s, StripOps<KB>& o) {
@@ -394,14 +405,15 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
 
   // ---- pipelined strips: group gi+1 (or the next strip's group 0 and operands) is in flight
   //      while group gi is computed
-  if (s_begin < s_pipe_end) {
+  if (n_pipe > 0) {
     StripOps<KB> ops;
-    load_ops(s_begin, ops);
+    load_ops(s_first, ops);
     f4 xbuf[2][PF];
     uint32_t bbuf[2][PF] = {};
-    load_group(s_begin, 0, xbuf[0], bbuf[0]);
-    for (int64_t s = s_begin; s < s_pipe_end; ++s) {
-      const int64_t sn = (s + 1 < s_pipe_end) ? s + 1 : s;
+    load_group(s_first, 0, xbuf[0], bbuf[0]);
+    for (int64_t j = 0; j < n_pipe; ++j) {
+      const int64_t s = s_first + WAVES * j;
+      const int64_t sn = (j + 1 < n_pipe) ? s + WAVES : s;
       StripOps<KB> nops;
       f4 gu[KB];
 #pragma unroll
@@ -430,7 +442,8 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     }
   }
   // ---- remaining strips (ragged last strip, or X without vector alignment): scalar loads
-  for (int64_t s = s_pipe_end; s < s_end; ++s) {
+  for (int64_t j = n_pipe; j < n_all; ++j) {
+    const int64_t s = s_first + WAVES * j;
     StripOps<KB> ops;
     load_ops(s, ops);
     f4 gu[KB];

@@ -83,7 +83,7 @@ class rpca_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
 
-RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION = 0, 1, 2, 3
+RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION, RPCA_K_TRIAL = 0, 1, 2, 3, 4
 
 _lib = None
 
