@@ -134,6 +134,15 @@ void rpca_default_opts(rpca_opts* opts);
 int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
                 const uint8_t* mask, rpca_ctx** out);
 
+/* rpca_create with the sweep's decomposition fixed by a wave count:
+ * target_waves (0..2^20) is the number of wavefronts the row strips of one
+ * sweep are spread over (0: the tuning table's value for this k and n).  A
+ * context that shares the GPU with others (or that must reproduce an
+ * instance of a batch bit for bit, see rpca_batch_instance_waves) uses it.
+ * Same errors as rpca_create; target_waves out of range is RPCA_EINVAL. */
+int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
+                      const uint8_t* mask, int32_t target_waves, rpca_ctx** out);
+
 /* Objective and gradient at (U, V) (Sec. 1 eq. PhiDef/eq. smoothNC, Sec. 3.2 eq. diff).
  * X, U, V, gU, gV: device.  f: device pointer to one double receiving f(U,V).
  * Deterministic: the same inputs give bitwise identical outputs. */

@@ -73,6 +73,14 @@ int rpca_batch_set_graphs(rpca_batch* b, int32_t on);
 /* Decomposition of the batch (for reports and tests). */
 int rpca_batch_info(rpca_batch* b, rpca_batch_layout* out);
 
+/* Wave target of instance i's sweep decomposition.  A batch shares one
+ * chip's worth of waves (16 per compute unit) over its instances in
+ * proportion to m n (k > 16 weighs 1.6 times), at least 4 each, so its items
+ * stay long enough to stream; a context made by rpca_create_waves with this
+ * value computes instance i's objective and gradient bit for bit as the
+ * batch does.  RPCA_EINVAL for a bad index or null pointer. */
+int rpca_batch_instance_waves(rpca_batch* b, int32_t i, int32_t* waves);
+
 void rpca_batch_destroy(rpca_batch* b);
 
 /* Sweep decomposition table (process-wide), keyed by (k bucket: k <= 8, 16,

@@ -165,6 +165,95 @@ hipError_t objgrad_launch(rpca_ctx* c, const SweepArgs& sa, const FinishArgs& fa
 
 }  // namespace
 
+int rpca::create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
+                     int target_waves, rpca_ctx** out) {
+  if (!out) return RPCA_EINVAL;
+  if (m < 1 || n < 1 || k < 1 || k > 32 || k > m || k > n) return RPCA_EINVAL;
+  if (!(lam_s > 0) || !(lam_l > 0) || !isfinite(lam_s) || !isfinite(lam_l)) return RPCA_EINVAL;
+  if (m > (int64_t)1 << 31 || n > (int64_t)1 << 24) return RPCA_EINVAL;
+  rpca_ctx* c = new (std::nothrow) rpca_ctx();
+  if (!c) return RPCA_ENOMEM;
+  c->m = m;
+  c->n = n;
+  c->k = k;
+  c->lam_s = lam_s;
+  c->lam_l = lam_l;
+  int rc = RPCA_OK;
+#define TRY(expr)                   \
+  do {                              \
+    rc = (expr);                    \
+    if (rc != RPCA_OK) {            \
+      rpca_destroy(c);              \
+      return rc;                    \
+    }                               \
+  } while (0)
+  if (mask) {
+    c->mw = (int)((m + 31) / 32);
+    std::vector<uint32_t> bits((size_t)c->mw * (size_t)n, 0u);
+    for (int64_t j = 0; j < n; ++j) {
+      const uint8_t* col = mask + j * m;
+      uint32_t* w = bits.data() + j * c->mw;
+      for (int64_t i = 0; i < m; ++i)
+        if (col[i]) w[i >> 5] |= 1u << (i & 31);
+    }
+    TRY(dalloc(&c->mask, bits.size()));
+    if (hipMemcpy(c->mask, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      rpca_destroy(c);
+      return RPCA_EHIP;
+    }
+  }
+  c->sweep_wgs =
+      rpca::sweep_blocks_for(m, n, k, &c->row_groups, &c->spw, &c->chunk_w, &c->nchunks, target_waves);
+  TRY(dalloc(&c->gvpart, (size_t)c->row_groups * n * k));
+  if (c->nchunks > 1) TRY(dalloc(&c->gupart, (size_t)c->nchunks * m * k));
+  TRY(dalloc(&c->spart, (size_t)c->sweep_wgs * RPCA_NSCAL));
+  TRY(dalloc(&c->fpart, (size_t)rpca::finish_blocks(m, n, k, c->nchunks, nullptr) * 3 + 16));
+  c->rps = 16;
+  c->segs = (c->row_groups + c->rps - 1) / c->rps;
+  TRY(dalloc(&c->level2, (size_t)c->segs * n * k));
+  TRY(dalloc(&c->counters, 16));
+  if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess) {
+    rpca_destroy(c);
+    return RPCA_EHIP;
+  }
+  const int64_t raw = (m + n) * k;
+  c->N = ((raw + 255) / 256) * 256;
+  for (int i = 0; i < 2; ++i) {
+    TRY(dalloc(&c->x[i], c->N));
+    TRY(dalloc(&c->g[i], c->N));
+  }
+  TRY(dalloc(&c->d, c->N));
+  TRY(dalloc(&c->S, (size_t)RPCA_MEMMAX * c->N));
+  TRY(dalloc(&c->Y, (size_t)RPCA_MEMMAX * c->N));
+  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 1024));
+  TRY(dalloc(&c->st, 1));
+  TRY(dalloc(&c->dscratch, 64));
+  TRY(dalloc(&c->pc_dev, (size_t)7 * k * k));
+  TRY(dalloc(&c->pc_gram, (size_t)rpca::PC_GRAM_BLOCKS * k * k));
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, sizeof(SolverState), hipHostMallocDefault) != hipSuccess) {
+    rpca_destroy(c);
+    return RPCA_ENOMEM;
+  }
+  c->st_host = static_cast<SolverState*>(hp);
+  // zero the padded tails once; kernels never write past (m+n)k
+  for (int i = 0; i < 2; ++i) {
+    if (hipMemset(c->x[i], 0, c->N * 4) != hipSuccess || hipMemset(c->g[i], 0, c->N * 4) != hipSuccess) {
+      rpca_destroy(c);
+      return RPCA_EHIP;
+    }
+  }
+  if (hipMemset(c->d, 0, c->N * 4) != hipSuccess ||
+      hipMemset(c->S, 0, (size_t)RPCA_MEMMAX * c->N * 4) != hipSuccess ||
+      hipMemset(c->Y, 0, (size_t)RPCA_MEMMAX * c->N * 4) != hipSuccess) {
+    rpca_destroy(c);
+    return RPCA_EHIP;
+  }
+#undef TRY
+  *out = c;
+  return RPCA_OK;
+}
+
 extern "C" {
 
 int rpca_profile_enable(rpca_ctx* c, int32_t on) {
@@ -253,91 +342,15 @@ void rpca_destroy(rpca_ctx* c) {
 
 int rpca_create(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
                 rpca_ctx** out) {
-  if (!out) return RPCA_EINVAL;
-  if (m < 1 || n < 1 || k < 1 || k > 32 || k > m || k > n) return RPCA_EINVAL;
-  if (!(lam_s > 0) || !(lam_l > 0) || !isfinite(lam_s) || !isfinite(lam_l)) return RPCA_EINVAL;
-  if (m > (int64_t)1 << 31 || n > (int64_t)1 << 24) return RPCA_EINVAL;
-  rpca_ctx* c = new (std::nothrow) rpca_ctx();
-  if (!c) return RPCA_ENOMEM;
-  c->m = m;
-  c->n = n;
-  c->k = k;
-  c->lam_s = lam_s;
-  c->lam_l = lam_l;
-  int rc = RPCA_OK;
-#define TRY(expr)                   \
-  do {                              \
-    rc = (expr);                    \
-    if (rc != RPCA_OK) {            \
-      rpca_destroy(c);              \
-      return rc;                    \
-    }                               \
-  } while (0)
-  if (mask) {
-    c->mw = (int)((m + 31) / 32);
-    std::vector<uint32_t> bits((size_t)c->mw * (size_t)n, 0u);
-    for (int64_t j = 0; j < n; ++j) {
-      const uint8_t* col = mask + j * m;
-      uint32_t* w = bits.data() + j * c->mw;
-      for (int64_t i = 0; i < m; ++i)
-        if (col[i]) w[i >> 5] |= 1u << (i & 31);
-    }
-    TRY(dalloc(&c->mask, bits.size()));
-    if (hipMemcpy(c->mask, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-      rpca_destroy(c);
-      return RPCA_EHIP;
-    }
-  }
-  c->sweep_wgs = rpca::sweep_blocks_for(m, n, k, &c->row_groups, &c->spw, &c->chunk_w, &c->nchunks);
-  TRY(dalloc(&c->gvpart, (size_t)c->row_groups * n * k));
-  if (c->nchunks > 1) TRY(dalloc(&c->gupart, (size_t)c->nchunks * m * k));
-  TRY(dalloc(&c->spart, (size_t)c->sweep_wgs * RPCA_NSCAL));
-  TRY(dalloc(&c->fpart, (size_t)rpca::finish_blocks(m, n, k, c->nchunks, nullptr) * 3 + 16));
-  c->rps = 16;
-  c->segs = (c->row_groups + c->rps - 1) / c->rps;
-  TRY(dalloc(&c->level2, (size_t)c->segs * n * k));
-  TRY(dalloc(&c->counters, 16));
-  if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess) {
-    rpca_destroy(c);
-    return RPCA_EHIP;
-  }
-  const int64_t raw = (m + n) * k;
-  c->N = ((raw + 255) / 256) * 256;
-  for (int i = 0; i < 2; ++i) {
-    TRY(dalloc(&c->x[i], c->N));
-    TRY(dalloc(&c->g[i], c->N));
-  }
-  TRY(dalloc(&c->d, c->N));
-  TRY(dalloc(&c->S, (size_t)RPCA_MEMMAX * c->N));
-  TRY(dalloc(&c->Y, (size_t)RPCA_MEMMAX * c->N));
-  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 1024));
-  TRY(dalloc(&c->st, 1));
-  TRY(dalloc(&c->dscratch, 64));
-  TRY(dalloc(&c->pc_dev, (size_t)7 * k * k));
-  TRY(dalloc(&c->pc_gram, (size_t)rpca::PC_GRAM_BLOCKS * k * k));
-  void* hp = nullptr;
-  if (hipHostMalloc(&hp, sizeof(SolverState), hipHostMallocDefault) != hipSuccess) {
-    rpca_destroy(c);
-    return RPCA_ENOMEM;
-  }
-  c->st_host = static_cast<SolverState*>(hp);
-  // zero the padded tails once; kernels never write past (m+n)k
-  for (int i = 0; i < 2; ++i) {
-    if (hipMemset(c->x[i], 0, c->N * 4) != hipSuccess || hipMemset(c->g[i], 0, c->N * 4) != hipSuccess) {
-      rpca_destroy(c);
-      return RPCA_EHIP;
-    }
-  }
-  if (hipMemset(c->d, 0, c->N * 4) != hipSuccess ||
-      hipMemset(c->S, 0, (size_t)RPCA_MEMMAX * c->N * 4) != hipSuccess ||
-      hipMemset(c->Y, 0, (size_t)RPCA_MEMMAX * c->N * 4) != hipSuccess) {
-    rpca_destroy(c);
-    return RPCA_EHIP;
-  }
-#undef TRY
-  *out = c;
-  return RPCA_OK;
+  return rpca::create_ctx(m, n, k, lam_s, lam_l, mask, 0, out);
 }
+
+int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
+                      int32_t target_waves, rpca_ctx** out) {
+  if (target_waves < 0 || target_waves > (1 << 20)) return RPCA_EINVAL;
+  return rpca::create_ctx(m, n, k, lam_s, lam_l, mask, target_waves, out);
+}
+
 
 int rpca_objgrad(rpca_ctx* c, const float* X, const float* U, const float* V, double* f, float* gU,
                  float* gV, void* stream) {
@@ -619,46 +632,33 @@ int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts
 // End of a solve: copy the iterate out, certify (tightening the stopping tests
 // and continuing while the gap is above the target, at most five rounds), and
 // fill `info`.  Returns the rpca_status of the solve.
-int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
-                 double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
-                 hipStream_t s) {
-  const int64_t mk = c->m * c->k, nk = c->n * c->k;
-  double rel_gap = NAN;
-  int certified = 0, rounds = 0, rc;
-  double ftol = o.ftol;
-  HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (;;) {
-    const int cur = c->st_host->cur;
-    HIPCHK(hipMemcpyAsync(U, c->x[cur], mk * 4, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(V, c->x[cur] + mk, nk * 4, hipMemcpyDeviceToDevice, s));
-    const int stop = c->st_host->stop;
-    if (!o.certify || stop == STOP_NONFINITE) break;
-    rpca_cert cert;
-    const int crc = certificate_impl(c, X, U, V, &cert, o.cert_tol, s);
-    if (crc < 0) return crc;
-    ++rounds;
-    rel_gap = cert.rel_gap;
-    certified = rel_gap <= o.cert_tol;
-    if (certified || stop == STOP_MAXITER || rounds >= 8) break;
-    // Not certified yet: continue from here.  Near the optimum f changes by less
-    // than its FP32 evaluation noise per iteration while the gradient still
-    // carries the structure the certificate measures, so the round runs with
-    // the stopping tests off, for half a preconditioner cycle (plain variables: a
-    // tenfold tighter gradient test), and ends at the cycle's cap or when the
-    // line search can no longer make progress.
-    if (o.precond) {
-      gtol = 0.0;
-      ftol = 0.0;
-    } else {
-      gtol *= 0.1;
-      ftol = 0.0;
-    }
-    const int round_budget = o.precond ? (o.precond_cycle > 1 ? o.precond_cycle / 2 : 1) : 0;
-    if ((rc = run_cycles(c, X, o, final_bf16, gtol, ftol, true, round_budget, s))) return rc;
-    if (c->st_host->stop == STOP_MAXITER && c->st_host->iter < o.max_iter) c->st_host->stop = STOP_GTOL;
-  }
-  HIPCHK(hipStreamSynchronize(s));
+// U, V <- the plain iterate x[cur] (host state current).
+int copy_out(rpca_ctx* c, float* U, float* V, hipStream_t s) {
+  const int cur = c->st_host->cur;
+  HIPCHK(hipMemcpyAsync(U, c->x[cur], c->m * c->k * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(V, c->x[cur] + c->m * c->k, c->n * c->k * 4, hipMemcpyDeviceToDevice, s));
+  return RPCA_OK;
+}
+
+// Tolerances of a certification round: near the optimum f changes by less than
+// its FP32 evaluation noise per iteration while the gradient still carries the
+// structure the certificate measures, so a round runs with the f test off and,
+// in preconditioned variables, the gradient test off too for half a cycle
+// (plain variables: a tenfold tighter gradient test, no budget).
+int round_tolerances(const rpca_opts& o, double* gtol, double* ftol) {
+  *gtol = o.precond ? 0.0 : *gtol * 0.1;
+  *ftol = 0.0;
+  return o.precond ? (o.precond_cycle > 1 ? o.precond_cycle / 2 : 1) : 0;
+}
+
+// A round that ran out of its budget (not of max_iter) ends like a gradient stop.
+void end_round(rpca_ctx* c, const rpca_opts& o) {
+  if (c->st_host->stop == STOP_MAXITER && c->st_host->iter < o.max_iter) c->st_host->stop = STOP_GTOL;
+}
+
+// Status and info of a finished solve (host state current).
+int finish_status(rpca_ctx* c, const rpca_opts& o, int certified, double rel_gap, int rounds, int iters_bf16,
+                  std::chrono::steady_clock::time_point t0, rpca_info* info) {
   const SolverState fin = *c->st_host;
   int status;
   switch (fin.stop) {
@@ -686,6 +686,34 @@ int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opt
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return status;
+}
+
+int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
+                 double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
+                 hipStream_t s) {
+  double rel_gap = NAN;
+  int certified = 0, rounds = 0, rc;
+  double ftol = o.ftol;
+  HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (;;) {
+    if ((rc = copy_out(c, U, V, s))) return rc;
+    const int stop = c->st_host->stop;
+    if (!o.certify || stop == STOP_NONFINITE) break;
+    rpca_cert cert;
+    const int crc = certificate_impl(c, X, U, V, &cert, o.cert_tol, s);
+    if (crc < 0) return crc;
+    ++rounds;
+    rel_gap = cert.rel_gap;
+    certified = rel_gap <= o.cert_tol;
+    if (certified || stop == STOP_MAXITER || rounds >= CERT_ROUNDS) break;
+    // not certified yet: continue from here
+    const int budget = round_tolerances(o, &gtol, &ftol);
+    if ((rc = run_cycles(c, X, o, final_bf16, gtol, ftol, true, budget, s))) return rc;
+    end_round(c, o);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return finish_status(c, o, certified, rel_gap, rounds, iters_bf16, t0, info);
 }
 
 }  // namespace rpca

@@ -22,6 +22,11 @@
 
 namespace {
 
+// Sweep waves per compute unit that a batch's decomposition aims at (per tile
+// class), and the fewest strips a wave of a batched sweep is given.
+constexpr int BATCH_WAVES_PER_CU = 16;
+constexpr int BATCH_MIN_STRIPS = 4;
+
 __global__ void k_gather_phase(SolverState* const* st, int count, int* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) out[i] = st[i]->phase;
@@ -44,6 +49,7 @@ void dfree(void* p) {
 struct rpca_batch {
   int count = 0;
   std::vector<rpca_ctx*> ctx;
+  std::vector<int> waves;  // sweep wave target per instance
   bool masked = false;
   // decomposition (fixed by the shapes): sweep items grouped by tile class
   struct SweepClass {
@@ -203,6 +209,70 @@ int batched_run(rpca_batch* b, const rpca_opts& o, bool bf16, bool use_graph) {
   return RPCA_OK;
 }
 
+
+// Solver cycles over the instances in `start` (the others stay done): each
+// restarts from its plain iterate with its own gradient tolerance and
+// iteration limit; in preconditioned variables it runs cycles of
+// o.precond_cycle iterations, each with a fresh preconditioner and an empty
+// memory, while it keeps stopping at a cycle's cap below its limit.  Ends
+// with every instance's x[cur] plain and its host state current.
+int batch_cycles(rpca_batch* b, const float* const* X, const rpca_opts& o, bool bf16,
+                 const std::vector<double>& gtol, double ftol, const std::vector<int>& limit,
+                 const std::vector<char>& start) {
+  hipStream_t s = b->stream;
+  const int n = b->count;
+  std::vector<rpca::InstanceArgs> ia(n);
+  int rc;
+  for (int cyc = 0;; ++cyc) {
+    std::vector<char> active(n, 0);
+    int nact = 0;
+    for (int i = 0; i < n; ++i) {
+      const SolverState* h = rpca::ctx_state_host(b->ctx[i]);
+      if (cyc == 0) active[i] = start[i];
+      else active[i] = o.precond && h->stop == STOP_MAXITER && h->iter < limit[i];
+      nact += active[i];
+    }
+    if (!nact) break;
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      rpca_ctx* c = b->ctx[i];
+      const SolverState* h = rpca::ctx_state_host(c);
+      int cap = limit[i];
+      if (o.precond) {
+        if ((rc = rpca::precond_refresh(c, h->cur, s))) return rc;
+        cap = (limit[i] - h->iter > o.precond_cycle) ? h->iter + o.precond_cycle : limit[i];
+      }
+      if ((rc = rpca::restart_state(c, gtol[i], ftol, cap, o.precond != 0, s))) return rc;
+    }
+    // argument tables at each instance's current iterate and variables
+    std::vector<SweepArgs> sl(n), se(n);
+    std::vector<FinishArgs> fl(n), fe(n);
+    std::vector<LbfgsArgs> lu(n), ld(n);
+    for (int i = 0; i < n; ++i) {
+      rpca::instance_args(b->ctx[i], X[i], rpca::ctx_state_host(b->ctx[i])->cur, &ia[i]);
+      sl[i] = ia[i].sa_loop;
+      se[i] = ia[i].sa_eval;
+      fl[i] = ia[i].fa_loop;
+      fe[i] = ia[i].fa_eval;
+      if (!active[i]) fe[i].f_out = nullptr;  // a finished instance keeps its f
+      lu[i] = ia[i].lu;
+      ld[i] = ia[i].ld;
+    }
+    if (upload_tables(b, sl, se, fl, fe, lu, ld) != hipSuccess) return RPCA_EHIP;
+    if (batched_objgrad(b, false, bf16) != hipSuccess) return RPCA_EHIP;
+    if ((rc = batched_run(b, o, bf16, b->use_graphs))) return rc;
+    for (int i = 0; i < n; ++i)
+      if (hipMemcpyAsync(ia[i].state_host, ia[i].state_dev, sizeof(SolverState), hipMemcpyDeviceToHost, s) !=
+          hipSuccess)
+        return RPCA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  }
+  for (int i = 0; i < n; ++i) {
+    rpca_ctx* c = b->ctx[i];
+    if ((rc = rpca::precond_to_plain(c, rpca::ctx_state_host(c)->cur, s))) return rc;
+  }
+  return RPCA_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -219,8 +289,35 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
   rpca_batch* b = new rpca_batch;
   b->count = count;
   b->ctx.assign(count, nullptr);
+  b->waves.assign(count, 0);
+  // The tile classes' persistent sweeps run one after another, so each class
+  // shares one chip's worth of waves (BATCH_WAVES_PER_CU per CU) over its
+  // instances in proportion to their work: the queue holds a few items per
+  // resident workgroup for balance, and no wave gets fewer than BATCH_MIN_STRIPS
+  // strips (each item carries the staging of a V chunk and a partial G^T U
+  // write, which short items cannot amortise).
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  std::vector<double> icost(count);
+  std::vector<int> icls(count);
+  std::vector<double> class_cost(64 * 3, 0.0);
   for (int i = 0; i < count; ++i) {
-    const int rc = rpca_create(m[i], n[i], k[i], lam_s[i], lam_l[i], nullptr, &b->ctx[i]);
+    const int kb = (k[i] + 15) / 16;
+    int rg0, spw0, cw0, nch0;
+    rpca::sweep_blocks_for(m[i], n[i], k[i], &rg0, &spw0, &cw0, &nch0, 1024);
+    const int tm = rpca::sweep_tmax_class(kb, (int)((std::min<int64_t>(n[i], cw0) + 15) / 16));
+    icls[i] = kb * 64 + tm;
+    icost[i] = (double)m[i] * (double)n[i] * (1.0 + 0.6 * (kb - 1));
+    class_cost[icls[i]] += icost[i];
+  }
+  for (int i = 0; i < count; ++i) {
+    const int64_t nstrips = (m[i] + 15) / 16;
+    const int64_t cap = std::max<int64_t>(4, nstrips / BATCH_MIN_STRIPS);
+    const int64_t share = llround(BATCH_WAVES_PER_CU * (double)cus * icost[i] / class_cost[icls[i]]);
+    b->waves[i] = (int)std::max<int64_t>(4, std::min<int64_t>(share, cap));
+    const int rc = rpca::create_ctx(m[i], n[i], k[i], lam_s[i], lam_l[i], nullptr, b->waves[i], &b->ctx[i]);
     if (rc != RPCA_OK) {
       destroy_batch(b);
       return rc;
@@ -241,8 +338,8 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
     for (int rg = 0; rg < ia[i].row_groups; ++rg)
       for (int ch = 0; ch < ia[i].nchunks; ++ch) {
         items.push_back({i, rg, ch, kb, tmax});
-        int64_t s0 = (int64_t)rg * 4 * ia[i].spw, s1 = s0 + 4 * (int64_t)ia[i].spw;
-        if (s1 > nstrips) s1 = nstrips;
+        const int64_t s0 = (int64_t)rg * nstrips / ia[i].row_groups;
+        const int64_t s1 = ((int64_t)rg + 1) * nstrips / ia[i].row_groups;
         const int64_t c0 = (int64_t)ch * ia[i].chunk_w;
         const int64_t cols = std::min<int64_t>(ia[i].chunk_w, n[i] - c0);
         cost.push_back((double)std::max<int64_t>(s1 - s0, 0) * (double)cols * (1.0 + 0.6 * (kb - 1)));
@@ -370,74 +467,62 @@ int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, floa
     return RPCA_EHIP;
   rpca::SolvePhase phases[2];
   const int nph = rpca::solve_phases(o, phases);
+  const int n = b->count;
   int rc;
-  for (int i = 0; i < b->count; ++i)
+  for (int i = 0; i < n; ++i)
     if ((rc = rpca::solve_setup(b->ctx[i], X[i], U[i], V[i], o, phases[0].gtol, s))) return rc;
-  const bool use_graph = b->use_graphs;
-  std::vector<rpca::InstanceArgs> ia(b->count);
-  std::vector<int> iters_bf16(b->count, 0);
-  std::vector<char> failed(b->count, 0);
+  std::vector<int> iters_bf16(n, 0), limit(n, o.max_iter);
+  std::vector<char> open(n, 1);
   bool final_bf16 = phases[0].bf16;
   for (int ph = 0; ph < nph; ++ph) {
-    // cycles: every instance that starts a cycle gets a fresh preconditioner (if
-    // enabled), an iteration cap and an empty memory; the others stay done
-    for (int cyc = 0;; ++cyc) {
-      std::vector<char> active(b->count, 0);
-      int nact = 0;
-      for (int i = 0; i < b->count; ++i) {
-        const SolverState* h = rpca::ctx_state_host(b->ctx[i]);
-        if (cyc == 0) active[i] = !failed[i];
-        else active[i] = o.precond && h->stop == STOP_MAXITER && h->iter < o.max_iter;
-        nact += active[i];
-      }
-      if (!nact) break;
-      for (int i = 0; i < b->count; ++i) {
-        if (!active[i]) continue;
-        rpca_ctx* c = b->ctx[i];
-        const SolverState* h = rpca::ctx_state_host(c);
-        int cap = o.max_iter;
-        if (o.precond) {
-          if ((rc = rpca::precond_refresh(c, h->cur, s))) return rc;
-          cap = (o.max_iter - h->iter > o.precond_cycle) ? h->iter + o.precond_cycle : o.max_iter;
-        }
-        if ((rc = rpca::restart_state(c, phases[ph].gtol, o.ftol, cap, o.precond != 0, s))) return rc;
-      }
-      // argument tables at each instance's current iterate and variables
-      std::vector<SweepArgs> sl(b->count), se(b->count);
-      std::vector<FinishArgs> fl(b->count), fe(b->count);
-      std::vector<LbfgsArgs> lu(b->count), ld(b->count);
-      for (int i = 0; i < b->count; ++i) {
-        rpca::instance_args(b->ctx[i], X[i], rpca::ctx_state_host(b->ctx[i])->cur, &ia[i]);
-        sl[i] = ia[i].sa_loop;
-        se[i] = ia[i].sa_eval;
-        fl[i] = ia[i].fa_loop;
-        fe[i] = ia[i].fa_eval;
-        lu[i] = ia[i].lu;
-        ld[i] = ia[i].ld;
-      }
-      if (upload_tables(b, sl, se, fl, fe, lu, ld) != hipSuccess) return RPCA_EHIP;
-      if (batched_objgrad(b, false, phases[ph].bf16) != hipSuccess) return RPCA_EHIP;
-      if ((rc = batched_run(b, o, phases[ph].bf16, use_graph))) return rc;
-      for (int i = 0; i < b->count; ++i)
-        if (hipMemcpyAsync(ia[i].state_host, ia[i].state_dev, sizeof(SolverState), hipMemcpyDeviceToHost, s) !=
-            hipSuccess)
-          return RPCA_EHIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
-    }
-    for (int i = 0; i < b->count; ++i) {
-      rpca_ctx* c = b->ctx[i];
-      if ((rc = rpca::precond_to_plain(c, rpca::ctx_state_host(c)->cur, s))) return rc;
-      const SolverState* h = rpca::ctx_state_host(c);
+    std::vector<double> gt(n, phases[ph].gtol);
+    if ((rc = batch_cycles(b, X, o, phases[ph].bf16, gt, o.ftol, limit, open))) return rc;
+    for (int i = 0; i < n; ++i) {
+      const SolverState* h = rpca::ctx_state_host(b->ctx[i]);
       if (ph == 0 && phases[0].bf16) iters_bf16[i] = h->iter;
-      if (h->stop == STOP_NONFINITE || h->stop == STOP_MAXITER) failed[i] = 1;
+      if (h->stop == STOP_NONFINITE || h->stop == STOP_MAXITER) open[i] = 0;
     }
     final_bf16 = phases[ph].bf16;
   }
+  // Certification rounds, batched: every instance still open takes a
+  // certificate; those not certified yet continue together for one round.
+  std::vector<int> rounds(n, 0), certified(n, 0);
+  std::vector<double> gap(n, NAN), gtol(n, phases[nph - 1].gtol);
+  double round_ftol = o.ftol;
+  open.assign(n, 1);
+  for (;;) {
+    std::vector<char> again(n, 0);
+    int nagain = 0, budget = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!open[i]) continue;
+      rpca_ctx* c = b->ctx[i];
+      if ((rc = rpca::copy_out(c, U[i], V[i], s))) return rc;
+      const int stop = rpca::ctx_state_host(c)->stop;
+      open[i] = 0;
+      if (!o.certify || stop == STOP_NONFINITE) continue;
+      rpca_cert cert;
+      const int crc = rpca::certificate_impl(c, X[i], U[i], V[i], &cert, o.cert_tol, s);
+      if (crc < 0) return crc;
+      ++rounds[i];
+      gap[i] = cert.rel_gap;
+      certified[i] = gap[i] <= o.cert_tol;
+      if (certified[i] || stop == STOP_MAXITER || rounds[i] >= rpca::CERT_ROUNDS) continue;
+      budget = rpca::round_tolerances(o, &gtol[i], &round_ftol);
+      const int it = rpca::ctx_state_host(c)->iter;
+      limit[i] = (budget > 0 && o.max_iter - it > budget) ? it + budget : o.max_iter;
+      again[i] = open[i] = 1;
+      ++nagain;
+    }
+    if (!nagain) break;
+    if ((rc = batch_cycles(b, X, o, final_bf16, gtol, round_ftol, limit, again))) return rc;
+    for (int i = 0; i < n; ++i)
+      if (again[i]) rpca::end_round(b->ctx[i], o);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   int worst = RPCA_OK;
-  for (int i = 0; i < b->count; ++i) {
-    rc = rpca::solve_finish(b->ctx[i], X[i], U[i], V[i], o, final_bf16, phases[nph - 1].gtol, iters_bf16[i], t0,
-                            info ? &info[i] : nullptr, s);
-    if (rc < 0) return rc;
+  for (int i = 0; i < n; ++i) {
+    rc = rpca::finish_status(b->ctx[i], o, certified[i], gap[i], rounds[i], iters_bf16[i], t0,
+                             info ? &info[i] : nullptr);
     if (rc > worst) worst = rc;
   }
   if (hipEventRecord(b->ev_out, s) != hipSuccess || hipStreamWaitEvent(cs, b->ev_out, 0) != hipSuccess)
@@ -460,6 +545,12 @@ int rpca_batch_info(rpca_batch* b, rpca_batch_layout* out) {
   out->lds_bytes = b->lds_max * 4;
   out->graphs = (int32_t)b->graphs.size();
   out->sweep_classes = (int32_t)b->classes.size();
+  return RPCA_OK;
+}
+
+int rpca_batch_instance_waves(rpca_batch* b, int32_t i, int32_t* waves) {
+  if (!b || !waves || i < 0 || i >= b->count) return RPCA_EINVAL;
+  *waves = b->waves[i];
   return RPCA_OK;
 }
 

@@ -207,7 +207,7 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
   }
   if (!TRIAL) {
     if (tid == 0) {
-      *a.f_out = fd + 0.5 * (double)lam_l * (uu + p0);
+      if (a.f_out) *a.f_out = fd + 0.5 * (double)lam_l * (uu + p0);
       if (a.aux_out) {
         a.aux_out[0] = fd;  // phi(U V^T)
         a.aux_out[1] = uu;  // ||U||^2
@@ -285,7 +285,7 @@ bool g_tune_init = false;
 void tune_defaults() {
   if (g_tune_init) return;
   for (int a = 0; a < TUNE_KB; ++a)
-    for (int b = 0; b < TUNE_NB; ++b) g_tune[a][b] = SweepTune{2048, 1};
+    for (int b = 0; b < TUNE_NB; ++b) g_tune[a][b] = SweepTune{1024, 1};
   g_tune_init = true;
 }
 }  // namespace
@@ -306,8 +306,9 @@ void tune_set(int kbucket, int nbucket, SweepTune t) {
 // Column chunks (each fitting the sweep's LDS budget) and the wave/workgroup
 // split of the rows, from the tuning table.
 int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wave, int* chunk_w,
-                     int* nchunks) {
-  const SweepTune t = tune_get(k, n);
+                     int* nchunks, int target_waves) {
+  SweepTune t = tune_get(k, n);
+  if (target_waves > 0) t.target_waves = target_waves;
   const int kb = (k + 15) / 16;
   int cmax = rpca_sweep::max_chunk(kb, k);
   if (t.chunk_div > 1) cmax = ((cmax / t.chunk_div + 15) / 16) * 16;
@@ -321,11 +322,13 @@ int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_p
   int64_t target = (t.target_waves + nch - 1) / nch;
   if (target > nstrips) target = nstrips;
   if (target < 1) target = 1;
-  const int64_t spw = (nstrips + target - 1) / target;
-  const int64_t waves = (nstrips + spw - 1) / spw;
-  const int64_t wgs = (waves + rpca_sweep::WAVES - 1) / rpca_sweep::WAVES;
+  // workgroup rows split the strips as evenly as integers allow (the kernel
+  // gives row rg the strips [rg S / R, (rg + 1) S / R))
+  int64_t wgs = (target + rpca_sweep::WAVES - 1) / rpca_sweep::WAVES;
+  if (wgs > nstrips) wgs = nstrips;
+  const int64_t per_wg = (nstrips + wgs - 1) / wgs;
   *row_groups = (int)wgs;
-  *strips_per_wave = (int)spw;
+  *strips_per_wave = (int)((per_wg + rpca_sweep::WAVES - 1) / rpca_sweep::WAVES);
   *chunk_w = cw;
   *nchunks = nch;
   return (int)(wgs * nch);

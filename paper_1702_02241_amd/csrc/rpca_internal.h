@@ -109,7 +109,7 @@ struct SweepArgs {
   float* gvpart;          // [row_groups][n*k] partial G^T U (one per workgroup row)
   double* spart;          // [row_groups*chunks][RPCA_NSCAL] scalar partials
   const float* pc;        // preconditioner [W | M_U | M_V] (k x k each) or null (plain variables)
-  int32_t strips_per_wave;  // 16-row strips per wave (contiguous)
+  int32_t strips_per_wave;  // most 16-row strips of one wave (row group rg of R owns strips [rg S/R, (rg+1) S/R))
   int32_t chunk_w;        // columns per chunk (multiple of 16)
   int32_t nchunks;
   int32_t row_groups;     // workgroups along the rows (grid.x)
@@ -138,7 +138,7 @@ struct FinishArgs {
   double* level2;         // [segs][n*k] first-level sums of the G^T U partials
   double* fpart;          // [blocks][3] partials of the second reduction
   unsigned int* counter;  // last-block counter (zero between launches)
-  double* f_out;          // plain mode: receives f
+  double* f_out;          // plain mode: receives f (null: not stored)
   double* aux_out;        // plain mode, optional: phi, ||U||^2, ||V||^2, ||G||_F^2
   int32_t nchunks, row_groups, sweep_wgs;
   int32_t segs, rows_per_seg;  // workgroup rows are summed in segs segments
@@ -175,8 +175,13 @@ int tune_k_bucket(int k);
 int tune_n_bucket(int64_t n);
 SweepTune tune_get(int k, int64_t n);
 void tune_set(int kbucket, int nbucket, SweepTune t);
-int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wg,
-                     int* chunk_w, int* nchunks);
+// Sweep decomposition of an m x n, rank-k instance; target_waves > 0 replaces
+// the table's wave target (a batch spreads one chip's waves over many instances).
+int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_per_wg, int* chunk_w,
+                     int* nchunks, int target_waves = 0);
+// rpca_create with the sweep's wave target given (0: the tuning table's).
+int create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
+               int target_waves, rpca_ctx** out);
 hipError_t launch_objgrad(const SweepArgs& sa, const FinishArgs& fa, bool trial, bool bf16,
                           hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream);
@@ -253,6 +258,13 @@ constexpr int PC_GRAM_BLOCKS = 256;
 int precond_refresh(rpca_ctx* c, int cur, hipStream_t s);
 int precond_to_plain(rpca_ctx* c, int cur, hipStream_t s);
 SolverState* ctx_state_host(rpca_ctx* c);
+// Certificates a solve takes at most (each but the last followed by a round).
+constexpr int CERT_ROUNDS = 8;
+int copy_out(rpca_ctx* c, float* U, float* V, hipStream_t s);
+int round_tolerances(const rpca_opts& o, double* gtol, double* ftol);
+void end_round(rpca_ctx* c, const rpca_opts& o);
+int finish_status(rpca_ctx* c, const rpca_opts& o, int certified, double rel_gap, int rounds, int iters_bf16,
+                  std::chrono::steady_clock::time_point t0, rpca_info* info);
 int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
                  double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
                  hipStream_t s);

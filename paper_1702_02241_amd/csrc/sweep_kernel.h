@@ -16,7 +16,10 @@
 // strips.  X is read with buffer loads: the tile's column base is scalar,
 // the lane offset one VGPR, and columns past the chunk fall outside the
 // resource's range and read as zero.  Per 16x16 tile:
-//   * R on MFMA with the accumulator seeded by -X.  In the MFMA output layout
+//   * -R = X - U V^T on MFMA: the accumulator is seeded with X and the A
+//     operand holds -U, so no per-entry negation is needed; the Huber step
+//     then yields -G, and the products -G^T U and -G V are negated once, when
+//     written.  In the MFMA output layout
 //     (column j = lane%16, rows 4*(lane/16)+r) G is already the A operand of
 //     G^T U with K running over rows, so the tile's G^T U goes straight into
 //     that tile's accumulator, kept in (accumulation) registers across all
@@ -68,6 +71,22 @@ __device__ __forceinline__ s4 pack_bf16(float a, float b, float c, float d) {
   return s4{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
 }
 
+// Huber value and derivative at one entry of the negated residual Rn = -R (the
+// tiles compute X - U V^T).  Returns Gn = clip(Rn, +-lam_s) = -G and adds
+// rho(R) = G (R - G / 2) = Gn (Rn - Gn / 2) to f and Gn^2 to g2; an unobserved
+// entry (observed = 0) contributes nothing.
+__device__ __forceinline__ float huber(float Rn, float lam_s, uint32_t observed, float& f, float& g2) {
+  float gn = __builtin_amdgcn_fmed3f(Rn, -lam_s, lam_s);
+  float h = fmaf(-0.5f, gn, Rn);
+  if (!observed) {  // whatever X holds there (even a NaN) stays out of f and G
+    gn = 0.f;
+    h = 0.f;
+  }
+  f = fmaf(gn, h, f);
+  g2 = fmaf(gn, gn, g2);
+  return gn;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -80,17 +99,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Dynamic LDS (floats): sVt[cwp][16 kb + 1] | sGV[WAVES][cwp][k] | sT[WAVES][16*LDT]
+// Transpose tiles per wave: the tiles of a group use distinct ones so that their
+// G -> G^T round trips through LDS overlap (k <= 16: all PF = 4 at once; k > 16,
+// where LDS is scarcer, two at a time).
+__host__ __device__ constexpr int ntb(int kb) { return kb == 1 ? 4 : 2; }
+
+// Dynamic LDS (floats): sVt[cwp][16 kb + 1] | sGV[WAVES][cwp][k] | sT[WAVES][ntb][16*LDT]
 __host__ __device__ constexpr int lds_floats(int kb, int k, int cwp) {
-  return cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * 16 * LDT;
+  return cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * ntb(kb) * 16 * LDT;
 }
 
 // Widest chunk (multiple of 16 columns) that fits the LDS budget and the
 // register accumulators.
 __host__ __device__ constexpr int max_chunk(int kb, int k) {
-  return 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k))) <
+  return 16 * ((LDS_LIMIT_FLOATS - WAVES * ntb(kb) * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k))) <
                  16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2)
-             ? 16 * ((LDS_LIMIT_FLOATS - WAVES * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)))
+             ? 16 * ((LDS_LIMIT_FLOATS - WAVES * ntb(kb) * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)))
              : 16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2);
 }
 
@@ -99,13 +123,17 @@ __host__ __device__ constexpr int tmax_class(int kb, int ntiles) {
   return ntiles <= 4 ? 4 : (ntiles <= 8 || kb == 2) ? 8 : 16;
 }
 
-// Loads in flight per wave: PF tiles per group, an even number of groups per strip
-// (the two group buffers line up at every strip start).
+// Load pipeline of a wave: PF tiles per group, NG groups per strip, and a ring
+// of NBUF group buffers (NG a multiple of NBUF, so the ring lines up at every
+// strip start) of which NBUF - 1 are in flight while one is computed.  One
+// workgroup per CU leaves the registers for a deep ring: up to 12 tiles (12 KB)
+// per wave in flight is what covers HBM latency at this occupancy.
 template <int TMAX>
 struct Pipe {
-  static constexpr int PF = TMAX <= 4 ? 2 : 4;
-  static constexpr int NG0 = (TMAX + PF - 1) / PF;
-  static constexpr int NG = NG0 + (NG0 & 1);
+  static constexpr int PF = TMAX >= 16 ? 4 : 2;
+  static constexpr int NG = (TMAX + PF - 1) / PF;
+  static constexpr int NBUF = NG >= 4 ? 4 : 2;
+  static_assert(NG % NBUF == 0, "group ring must line up with strips");
 };
 
 template <int KB>
@@ -115,8 +143,14 @@ struct StripOps {
   float dub[4][KB];   // dU at the ub positions (trial)
 };
 
-template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
-__device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, const int ch, float* lds,
+// Argument tables of the batched sweep are read through the constant address
+// space: every field load is a scalar load the compiler may repeat at its use
+// instead of holding some fifty fields live in registers across the item loop.
+typedef __attribute__((address_space(4))) SweepArgs ConstSweepArgs;
+
+// `Args` is SweepArgs (a kernel argument) or ConstSweepArgs (a batch table entry).
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, typename Args>
+__device__ __forceinline__ void sweep_item(const Args& a, const int rg, const int ch, float* lds,
                                             double* sRed) {
   constexpr int KMAX = 16 * KB;
   constexpr int KQ = 4 * KB;
@@ -124,6 +158,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
   using P = Pipe<TMAX>;
   constexpr int PF = P::PF;
   constexpr int NG = P::NG;
+  constexpr int NBUF = P::NBUF;
 
   int cur = 0, outi = 0;
   float alpha = 0.f;
@@ -134,7 +169,8 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     alpha = (float)st->alpha;
     outi = 1 - cur;
   }
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: strip control stays scalar
   const int c = lane & 15, g = lane >> 4;
   const int64_t m = a.m, n = a.n;
   const int k = a.k;
@@ -150,7 +186,8 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
   const int cwp = ntiles * 16;
   float* sVt = lds;
   float* sGVall = lds + cwp * LDV;
-  float* myT = sGVall + WAVES * cwp * k + w * 16 * LDT;
+  constexpr int NTB = ntb(KB);
+  float* myT = sGVall + WAVES * cwp * k + w * NTB * 16 * LDT;  // transpose tile 0 of this wave
 
   // Preconditioned variables (the solver's A, B with U = A P_U, V = B P_V): the
   // product U V^T = A (B W^T)^T with W = P_U P_V, so the staged rows are B W^T
@@ -204,17 +241,17 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     for (int kb = 0; kb < KB; ++kb) gva[t][kb] = f4{0.f, 0.f, 0.f, 0.f};
 
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
-  // The workgroup owns strips [rg * WAVES * spw, (rg + 1) * WAVES * spw); wave w
-  // takes every WAVES-th of them starting at w.  A 16-row strip reads half of
-  // each 128-byte line of a column; the neighbouring wave reads the other half
-  // at about the same time, so each line comes from HBM once.
+  // Workgroup row rg of R owns the strips [rg S / R, (rg + 1) S / R) of the S
+  // strips (as even a split as integers allow); wave w takes every WAVES-th of
+  // them starting at w.  A 16-row strip reads half of each 128-byte line of a
+  // column; the neighbouring wave reads the other half at about the same time,
+  // so each line comes from HBM once.
   const int64_t nstrips = (m + 15) >> 4;
-  const int64_t s_first = (int64_t)rg * WAVES * a.strips_per_wave + w;
+  const int64_t R = a.row_groups;
+  const int64_t s_lo = (int64_t)rg * nstrips / R, s_hi = ((int64_t)rg + 1) * nstrips / R;
+  const int64_t s_first = s_lo + w;
   int64_t n_all = 0;  // strips of this wave: s_first + WAVES * j, j < n_all
-  if (s_first < nstrips) {
-    n_all = (nstrips - s_first + WAVES - 1) / WAVES;
-    if (n_all > a.strips_per_wave) n_all = a.strips_per_wave;
-  }
+  if (s_first < s_hi) n_all = (s_hi - s_first + WAVES - 1) / WAVES;
   const bool vec = a.xvec != 0;
   // strips whose 16 rows are all inside X (a prefix of the wave's list) take the
   // pipelined vector path
@@ -237,7 +274,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
       const int kkc = kk < k ? kk : k - 1;
       float v = U[i_c * k + kkc];
       if (TRIAL) v = fmaf(alpha, dU[i_c * k + kkc], v);
-      o.ua[q] = (kk < k && row_c_ok) ? v : 0.f;
+      o.ua[q] = (kk < k && row_c_ok) ? -v : 0.f;  // -U: the tile product is X - U V^T = -R
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -263,14 +300,15 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
   // loads: the tile's column base is scalar, the lane offset one VGPR, and
   // columns past the chunk fall outside the resource's range and read zero.
   const uint32_t lane_off = (uint32_t)(c * m * 4 + 16 * g);
-  auto load_group = [&](int64_t s, int gi, f4(&xr)[PF], uint32_t(&br)[PF]) {
+  // live = false: a strip past the wave's last (the ring's tail) reads nothing.
+  auto load_group = [&](int64_t s, int gi, f4(&xr)[PF], uint32_t(&br)[PF], bool live) {
     const uint32_t voff = lane_off + (uint32_t)(s * 64);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int t = gi * PF + u;
       if (t < TMAX) {
         int valid = ncols - 16 * t;
-        valid = valid < 0 ? 0 : (valid > 16 ? 16 : valid);
+        valid = (valid < 0 || !live) ? 0 : (valid > 16 ? 16 : valid);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(X + (j_begin + 16 * t) * m), (short)0, (int)(valid * m * 4), BUF_DWORD3);
         xr[u] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 0));
@@ -290,10 +328,11 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     const bool jok = jl < ncols;
     const f4 xv = jok ? xraw : f4{0.f, 0.f, 0.f, 0.f};
     const uint32_t bits = MASKED ? (jok ? braw : 0u) : 0xFu;
-    f4 acc = -xv;
+    f4 acc = xv;
     if (!BF16) {
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) acc = mfma_f32(o.ua[q], sVt[jl * LDV + 4 * q + g], acc);
+      for (int q = 0; q < KQ; ++q)
+        if (4 * q < k) acc = mfma_f32(o.ua[q], sVt[jl * LDV + 4 * q + g], acc);  // steps past k add zero
     } else {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
@@ -305,18 +344,9 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     float G[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float R = acc[r];
-      const float ar = fabsf(R);
-      float rho = (ar <= lam_s) ? 0.5f * R * R : lam_s * (ar - 0.5f * lam_s);
-      float gr = fminf(fmaxf(R, -lam_s), lam_s);
-      if (MASKED && !((bits >> r) & 1u)) {
-        rho = 0.f;
-        gr = 0.f;
-      }
-      ftile += rho;
-      gtile = fmaf(gr, gr, gtile);
-      G[r] = gr;
-      myT[(4 * g + r) * LDT + c] = gr;
+      const float gn = huber(acc[r], lam_s, MASKED ? ((bits >> r) & 1u) : 1u, ftile, gtile);
+      G[r] = gn;
+      myT[(4 * g + r) * LDT + c] = gn;
     }
     if (!BF16) {
 #pragma unroll
@@ -343,6 +373,95 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
       for (int kb = 0; kb < KB; ++kb) {
         const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
         gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
+      }
+    }
+  };
+
+  // A whole group of PF tiles (all inside the chunk), step by step across the
+  // group so that the tiles' independent MFMA chains and LDS round trips
+  // overlap: R for every tile, then per NTB tiles the Huber epilogue with its
+  // transposes, the G^T U and the G V products.  Same arithmetic, same order per
+  // accumulator as PF calls of `tile`.
+  auto tile_group = [&](int gi, const StripOps<KB>& o, const f4(&xr)[PF], const uint32_t(&br)[PF],
+                        float& ftile, float& gtile, f4(&gu)[KB]) {
+    f4 acc[PF];  // columns past the chunk were read as zero by the buffer loads
+#pragma unroll
+    for (int u = 0; u < PF; ++u) acc[u] = xr[u];
+    if (!BF16) {
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (4 * q >= k) continue;  // K-steps past k would add zero (k is uniform)
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+          acc[u] = mfma_f32(o.ua[q], sVt[(16 * (gi * PF + u) + c) * LDV + 4 * q + g], acc[u]);
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const s4 ua4 = pack_bf16(o.ua[4 * kb + 0], o.ua[4 * kb + 1], o.ua[4 * kb + 2], o.ua[4 * kb + 3]);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const float* vr = sVt + (16 * (gi * PF + u) + c) * LDV + 16 * kb + 4 * g;
+          acc[u] = mfma_bf16(ua4, pack_bf16(vr[0], vr[1], vr[2], vr[3]), acc[u]);
+        }
+      }
+    }
+    constexpr int NB = NTB < PF ? NTB : PF;  // tiles per transpose round (PF = 2 when TMAX = 4)
+    static_assert(PF % NB == 0, "transpose rounds split the group evenly");
+#pragma unroll
+    for (int h = 0; h < PF; h += NB) {
+      float G[NB][4];
+#pragma unroll
+      for (int v = 0; v < NB; ++v) {
+        const int u = h + v;
+        const int jl = 16 * (gi * PF + u) + c;
+        const uint32_t bits = MASKED ? ((jl < ncols) ? br[u] : 0u) : 0xFu;
+        float* tT = myT + v * 16 * LDT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float gn = huber(acc[u][r], lam_s, MASKED ? ((bits >> r) & 1u) : 1u, ftile, gtile);
+          G[v][r] = gn;
+          tT[(4 * g + r) * LDT + c] = gn;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NB; ++v) {
+        const int t = gi * PF + h + v;
+        const int ts = t < TMAX ? t : TMAX - 1;  // t < TMAX wherever a whole group is used
+        if (!BF16) {
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gva[ts][kb] = mfma_f32(G[v][r], o.ub[r][kb], gva[ts][kb]);
+        } else {
+          const s4 gb = pack_bf16(G[v][0], G[v][1], G[v][2], G[v][3]);
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb)
+            gva[ts][kb] =
+                mfma_bf16(gb, pack_bf16(o.ub[0][kb], o.ub[1][kb], o.ub[2][kb], o.ub[3][kb]), gva[ts][kb]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NB; ++v) {
+        const int t = gi * PF + h + v;
+        const float* tT = myT + v * 16 * LDT;
+        if (!BF16) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float gt = tT[c * LDT + 4 * q + g];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+              gu[kb] = mfma_f32(gt, sVt[(16 * t + 4 * q + g) * LDV + 16 * kb + c], gu[kb]);
+          }
+        } else {
+          const float* tr = tT + c * LDT + 4 * g;
+          const s4 gtb = pack_bf16(tr[0], tr[1], tr[2], tr[3]);
+#pragma unroll
+          for (int kb = 0; kb < KB; ++kb) {
+            const float* vc = sVt + (16 * t + 4 * g) * LDV + 16 * kb + c;
+            gu[kb] = mfma_bf16(gtb, pack_bf16(vc[0], vc[LDV], vc[2 * LDV], vc[3 * LDV]), gu[kb]);
+          }
+        }
       }
     }
   };
@@ -388,11 +507,11 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
         if (kk < k && i < m) {
           const int64_t oo = i * k + kk;
           if (a.nchunks == 1) {
-            const float gval = fmaf(lam_l, reg[r][kb], gu[kb][r]);
+            const float gval = fmaf(lam_l, reg[r][kb], -gu[kb][r]);  // gu holds -G V
             a.gU[outi][oo] = gval;
             if (TRIAL) gud_acc += (double)gval * (double)o.dub[r][kb];
           } else {
-            a.gupart[(int64_t)ch * m * k + oo] = gu[kb][r];
+            a.gupart[(int64_t)ch * m * k + oo] = -gu[kb][r];
           }
           if (ch == 0) {
             uu_acc += (double)o.ub[r][kb] * (double)reg[r][kb];
@@ -403,37 +522,44 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
     }
   };
 
-  // ---- pipelined strips: group gi+1 (or the next strip's group 0 and operands) is in flight
-  //      while group gi is computed
+  // ---- pipelined strips: while group gi is computed, the next NBUF - 1 groups (running on
+  //      into the next strip, whose operands are requested with its first group) are in flight
   if (n_pipe > 0) {
-    StripOps<KB> ops;
+    constexpr int D = NBUF - 1;
+    StripOps<KB> ops, nops;
     load_ops(s_first, ops);
-    f4 xbuf[2][PF];
-    uint32_t bbuf[2][PF] = {};
-    load_group(s_first, 0, xbuf[0], bbuf[0]);
+    f4 xbuf[NBUF][PF];
+    uint32_t bbuf[NBUF][PF] = {};
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_group(s_first, d, xbuf[d], bbuf[d], true);
     for (int64_t j = 0; j < n_pipe; ++j) {
       const int64_t s = s_first + WAVES * j;
-      const int64_t sn = (j + 1 < n_pipe) ? s + WAVES : s;
-      StripOps<KB> nops;
+      const bool more = j + 1 < n_pipe;
+      const int64_t sn = more ? s + WAVES : s;
       f4 gu[KB];
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) gu[kb] = f4{0.f, 0.f, 0.f, 0.f};
       float ftile = 0.f, gtile = 0.f;
 #pragma unroll
       for (int gi = 0; gi < NG; ++gi) {
-        const int cb = gi & 1, nb = cb ^ 1;
-        if (gi + 1 < NG) {
-          load_group(s, gi + 1, xbuf[nb], bbuf[nb]);
+        const int ga = gi + D;  // the group requested now
+        if (ga < NG) {
+          load_group(s, ga, xbuf[ga % NBUF], bbuf[ga % NBUF], true);
         } else {
-          load_ops(sn, nops);
-          load_group(sn, 0, xbuf[nb], bbuf[nb]);
+          if (ga == NG) load_ops(sn, nops);
+          load_group(sn, ga - NG, xbuf[ga % NBUF], bbuf[ga % NBUF], more);
         }
         __builtin_amdgcn_sched_barrier(0);
+        const int cb = gi % NBUF;
+        if ((gi + 1) * PF <= TMAX && (gi + 1) * PF <= ntiles) {
+          tile_group(gi, ops, xbuf[cb], bbuf[cb], ftile, gtile, gu);
+        } else {
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          const int t = gi * PF + u;
-          if (t < TMAX) {
-            if (t < ntiles) tile(t, ops, xbuf[cb][u], bbuf[cb][u], ftile, gtile, gu);
+          for (int u = 0; u < PF; ++u) {
+            const int t = gi * PF + u;
+            if (t < TMAX) {
+              if (t < ntiles) tile(t, ops, xbuf[cb][u], bbuf[cb][u], ftile, gtile, gu);
+            }
           }
         }
       }
@@ -485,7 +611,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs& a, const int rg, con
         const int kk = 16 * kb + c;
         if (kk < k) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sGV[(16 * t + 4 * g + r) * k + kk] = gva[t][kb][r];
+          for (int r = 0; r < 4; ++r) sGV[(16 * t + 4 * g + r) * k + kk] = -gva[t][kb][r];  // -G^T U
         }
       }
     }
@@ -542,8 +668,8 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* __restrict_
     const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
     const int rg = __builtin_amdgcn_readfirstlane(items[it].rg);
     const int ch = __builtin_amdgcn_readfirstlane(items[it].ch);
-    const SweepArgs a = args[inst];
-    sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(a, rg, ch, lds, sRed);
+    sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(((const ConstSweepArgs*)args)[inst], rg, ch, lds,
+                                              sRed);
     __syncthreads();
   }
 }

@@ -58,7 +58,7 @@ int rpca_autotune(int64_t m_probe, int32_t reps, void* stream) {
       const int k = K_REP[kb];
       const int64_t n = N_REP[nb];
       float best = INFINITY;
-      rpca::SweepTune best_t{2048, 1};
+      rpca::SweepTune best_t{1024, 1};
       for (int w : WAVE_CAND) {
         for (int d : DIV_CAND) {
           rpca::tune_set(kb, nb, rpca::SweepTune{w, d});

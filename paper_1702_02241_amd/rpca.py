@@ -99,6 +99,7 @@ def lib():
         sig = {
             "rpca_default_opts": (None, [ctypes.POINTER(rpca_opts)]),
             "rpca_create": (I32, [I64, I64, I32, D, D, P, ctypes.POINTER(P)]),
+            "rpca_create_waves": (I32, [I64, I64, I32, D, D, P, I32, ctypes.POINTER(P)]),
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
@@ -127,6 +128,7 @@ def lib():
             "rpca_batch_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), P, P]),
             "rpca_batch_set_graphs": (I32, [P, I32]),
             "rpca_batch_info": (I32, [P, ctypes.POINTER(rpca_batch_layout)]),
+            "rpca_batch_instance_waves": (I32, [P, I32, ctypes.POINTER(I32)]),
             "rpca_batch_destroy": (None, [P]),
             "rpca_autotune": (I32, [I64, I32, P]),
             "rpca_tune_get": (I32, [I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
@@ -146,9 +148,10 @@ def default_opts():
     return o
 
 
-def rpca_create(m, n, k, lam_s, lam_l, mask=None):
+def rpca_create(m, n, k, lam_s, lam_l, mask=None, waves=None):
     """mask: None or a host numpy uint8 array (m x n, Fortran order or any order;
-    it is converted to column-major bytes).  Returns (status, ctx)."""
+    it is converted to column-major bytes).  waves: None (rpca_create) or the
+    sweep's wave target (rpca_create_waves).  Returns (status, ctx)."""
     ctx = ctypes.c_void_p()
     mptr = None
     keep = None
@@ -156,7 +159,10 @@ def rpca_create(m, n, k, lam_s, lam_l, mask=None):
         import numpy as np
         keep = np.asfortranarray(np.asarray(mask) != 0, dtype=np.uint8)
         mptr = keep.ctypes.data
-    rc = lib().rpca_create(m, n, k, lam_s, lam_l, mptr, ctypes.byref(ctx))
+    if waves is None:
+        rc = lib().rpca_create(m, n, k, lam_s, lam_l, mptr, ctypes.byref(ctx))
+    else:
+        rc = lib().rpca_create_waves(m, n, k, lam_s, lam_l, mptr, int(waves), ctypes.byref(ctx))
     return rc, ctx
 
 
@@ -292,6 +298,12 @@ def rpca_batch_info(b):
     out = rpca_batch_layout()
     rc = lib().rpca_batch_info(b, ctypes.byref(out))
     return rc, out
+
+
+def rpca_batch_instance_waves(b, i):
+    w = ctypes.c_int32()
+    rc = lib().rpca_batch_instance_waves(b, int(i), ctypes.byref(w))
+    return rc, w.value
 
 
 def rpca_batch_destroy(b):

@@ -27,8 +27,8 @@ def to_device_factor(A, device="cuda"):
 class Context:
     """Owns an rpca_ctx for one problem shape."""
 
-    def __init__(self, m, n, k, lam_s, lam_l, mask=None):
-        rc, self.ctx = R.rpca_create(m, n, k, lam_s, lam_l, mask)
+    def __init__(self, m, n, k, lam_s, lam_l, mask=None, waves=None):
+        rc, self.ctx = R.rpca_create(m, n, k, lam_s, lam_l, mask, waves)
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_create failed: {R.rpca_status_string(rc)}")
         self.m, self.n, self.k = m, n, k
@@ -230,6 +230,12 @@ class Batch:
 
     def layout(self):
         return R.rpca_batch_info(self.b)[1]
+
+    def instance_waves(self, i):
+        rc, w = R.rpca_batch_instance_waves(self.b, i)
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_batch_instance_waves failed: {R.rpca_status_string(rc)}")
+        return w
 
     def objgrad(self, Xs, Us, Vs, precision=R.RPCA_PREC_FP32):
         dev = Us[0].device

@@ -49,6 +49,15 @@ def test_create_rejects_bad_arguments_before_hip(args):
     assert not ctx.value
 
 
+@pytest.mark.parametrize("waves", [-1, (1 << 20) + 1])
+def test_create_waves_rejects_bad_target(waves):
+    rc, ctx = R.rpca_create(100, 20, 5, 0.1, 1.0, None, waves)
+    assert rc == R.RPCA_EINVAL
+    assert not ctx.value
+    rc, ctx = R.rpca_create(100, 20, 0, 0.1, 1.0, None, 64)    # k = 0 fails before any HIP call
+    assert rc == R.RPCA_EINVAL
+
+
 def test_null_context_rejected():
     assert R.rpca_objgrad(None, 1, 1, 1, 1, 1, 1, 0) == R.RPCA_EINVAL
     rc, _ = R.rpca_solve(None, 1, 1, 1)
@@ -115,4 +124,5 @@ def test_batch_entry_points_reject_bad_arguments_before_hip():
     rc, _ = R.rpca_batch_solve(None, [1], [1], [1])
     assert rc == R.RPCA_EINVAL
     assert R.rpca_batch_set_graphs(None, 1) == R.RPCA_EINVAL
+    assert R.rpca_batch_instance_waves(None, 0)[0] == R.RPCA_EINVAL
     R.rpca_batch_destroy(None)

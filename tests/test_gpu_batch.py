@@ -3,8 +3,10 @@ reductions / L-BFGS passes for all instances, under a captured hipGraph.
 
 The batched kernels run the same per-item arithmetic in the same fixed
 reduction orders as the single-instance path, so the bar against
-rpca_objgrad / rpca_solve on the same inputs is bitwise equality; the
-oracle bars of the single path (1e-5 FP32) carry over and are checked too.
+rpca_objgrad / rpca_solve of a context with the same sweep decomposition
+(rpca_create_waves with the batch's wave target for that instance) on the
+same inputs is bitwise equality; the oracle bars of the single path (1e-5
+FP32) carry over and are checked too.
 """
 import numpy as np
 import pytest
@@ -50,7 +52,7 @@ def test_batched_objgrad_bitwise_equals_single(precision):
     print(f"[batch objgrad prec={precision}] items {lay.sweep_items} grid {lay.sweep_grid_fp32}/"
           f"{lay.sweep_grid_bf16} lds {lay.lds_bytes} B")
     for j, p in enumerate(ps):
-        ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+        ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l, waves=B.instance_waves(j))
         f1, gU1, gV1 = ctx.objgrad(Xs[j], Us[j], Vs[j], precision)
         torch.cuda.synchronize()
         assert torch.equal(fs[j], f1) and torch.equal(gUs[j], gU1) and torch.equal(gVs[j], gV1), j
@@ -79,7 +81,7 @@ def test_batched_solve_bitwise_equals_single(graphs):
     rc, infos = B.solve(Xs, Us, Vs, certify=0, max_iter=400)
     torch.cuda.synchronize()
     for j, p in enumerate(ps):
-        ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+        ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l, waves=B.instance_waves(j))
         U1 = T.to_device_factor(starts[j][0], dev)
         V1 = T.to_device_factor(starts[j][1], dev)
         rc1, info1 = ctx.solve(Xs[j], U1, V1, certify=0, max_iter=400)
