@@ -22,16 +22,6 @@ __device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ short bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
-__device__ __forceinline__ s4 pack_bf16(float a, float b, float c, float d) {
-  return s4{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
-}
-
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   constexpr int W = NT / 64;

@@ -61,14 +61,15 @@ __device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ short bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
+// FP32 -> BF16, round to nearest even, four at a time by the hardware
+// conversion (v_cvt_pk_bf16_f32, two values per instruction).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ s4 pack_bf16(float a, float b, float c, float d) {
-  return s4{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
+  const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf16x2));
+  const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{c, d}, bf16x2));
+  return __builtin_bit_cast(s4, u2v{lo, hi});
 }
 
 // Huber value and derivative at one entry of the negated residual Rn = -R (the
