@@ -629,9 +629,6 @@ int solve_setup(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts
   return RPCA_OK;
 }
 
-// End of a solve: copy the iterate out, certify (tightening the stopping tests
-// and continuing while the gap is above the target, at most five rounds), and
-// fill `info`.  Returns the rpca_status of the solve.
 // U, V <- the plain iterate x[cur] (host state current).
 int copy_out(rpca_ctx* c, float* U, float* V, hipStream_t s) {
   const int cur = c->st_host->cur;
@@ -688,6 +685,9 @@ int finish_status(rpca_ctx* c, const rpca_opts& o, int certified, double rel_gap
   return status;
 }
 
+// End of a solve: copy the iterate out, certify (continuing with the stopping
+// tests off, or tightened, while the gap is above the target, at most
+// CERT_ROUNDS certificates), and fill `info`.  Returns the rpca_status of the solve.
 int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
                  double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
                  hipStream_t s) {

@@ -15,12 +15,16 @@
 #include <algorithm>
 #include <chrono>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/rpca_batch.h"
 #include "rpca_internal.h"
 
 namespace {
+
+// Host worker threads (and streams) of the per-instance phases of a batched solve.
+constexpr int BATCH_WORKERS = 4;
 
 // Sweep waves per compute unit that a batch's decomposition aims at (per tile
 // class), and the fewest strips a wave of a batched sweep is given.
@@ -80,6 +84,11 @@ struct rpca_batch {
   // the batch runs on its own stream, ordered after / before the caller's by events
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // per-instance host-driven phases (rSVD start, certificates: each with its own
+  // host synchronisations) run on worker threads, one stream each, ordered
+  // after / before the batch stream by events
+  hipStream_t aux[BATCH_WORKERS] = {};
+  hipEvent_t ev_aux[BATCH_WORKERS] = {};
   // captured slot groups, keyed by (bf16, mem, slots)
   struct Graph {
     bool bf16;
@@ -111,6 +120,10 @@ void destroy_batch(rpca_batch* b) {
   dfree(b->d_states);
   dfree(b->d_phase);
   if (b->h_phase) (void)hipHostFree(b->h_phase);
+  for (int t = 0; t < BATCH_WORKERS; ++t) {
+    if (b->ev_aux[t]) (void)hipEventDestroy(b->ev_aux[t]);
+    if (b->aux[t]) (void)hipStreamDestroy(b->aux[t]);
+  }
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -209,6 +222,40 @@ int batched_run(rpca_batch* b, const rpca_opts& o, bool bf16, bool use_graph) {
   return RPCA_OK;
 }
 
+
+// Run fn(i, stream) for every instance i with sel[i] on the worker threads
+// (instance i on worker i % BATCH_WORKERS, in increasing i), each worker on its
+// own stream ordered after the batch stream; the batch stream is then ordered
+// after every worker's work.  Returns the first error.
+template <typename Fn>
+int on_workers(rpca_batch* b, const std::vector<char>& sel, Fn fn) {
+  if (hipEventRecord(b->ev_in, b->stream) != hipSuccess) return RPCA_EHIP;
+  int rc[BATCH_WORKERS] = {};
+  auto work = [&](int t) {
+    if (hipStreamWaitEvent(b->aux[t], b->ev_in, 0) != hipSuccess) {
+      rc[t] = RPCA_EHIP;
+      return;
+    }
+    for (int i = t; i < b->count; i += BATCH_WORKERS) {
+      if (!sel[i]) continue;
+      const int r = fn(i, b->aux[t]);
+      if (r < 0) {
+        rc[t] = r;
+        return;
+      }
+    }
+    if (hipEventRecord(b->ev_aux[t], b->aux[t]) != hipSuccess) rc[t] = RPCA_EHIP;
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < BATCH_WORKERS; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  for (int t = 0; t < BATCH_WORKERS; ++t)
+    if (rc[t]) return rc[t];
+  for (int t = 0; t < BATCH_WORKERS; ++t)
+    if (hipStreamWaitEvent(b->stream, b->ev_aux[t], 0) != hipSuccess) return RPCA_EHIP;
+  return RPCA_OK;
+}
 
 // Solver cycles over the instances in `start` (the others stay done): each
 // restarts from its plain iterate with its own gradient tolerance and
@@ -396,6 +443,9 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess;
+  for (int t = 0; t < BATCH_WORKERS && ok; ++t)
+    ok = hipStreamCreateWithFlags(&b->aux[t], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->ev_aux[t], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     destroy_batch(b);
     return RPCA_EHIP;
@@ -469,8 +519,11 @@ int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, floa
   const int nph = rpca::solve_phases(o, phases);
   const int n = b->count;
   int rc;
-  for (int i = 0; i < n; ++i)
-    if ((rc = rpca::solve_setup(b->ctx[i], X[i], U[i], V[i], o, phases[0].gtol, s))) return rc;
+  std::vector<char> all(n, 1);
+  if ((rc = on_workers(b, all, [&](int i, hipStream_t ws) -> int {
+         return rpca::solve_setup(b->ctx[i], X[i], U[i], V[i], o, phases[0].gtol, ws);
+       })))
+    return rc;
   std::vector<int> iters_bf16(n, 0), limit(n, o.max_iter);
   std::vector<char> open(n, 1);
   bool final_bf16 = phases[0].bf16;
@@ -485,34 +538,43 @@ int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, floa
     final_bf16 = phases[ph].bf16;
   }
   // Certification rounds, batched: every instance still open takes a
-  // certificate; those not certified yet continue together for one round.
+  // certificate (on the workers); those not certified yet continue together
+  // for one round.
   std::vector<int> rounds(n, 0), certified(n, 0);
   std::vector<double> gap(n, NAN), gtol(n, phases[nph - 1].gtol);
   double round_ftol = o.ftol;
+  int round_budget = 0;
+  {
+    double g0 = 1.0;
+    round_budget = rpca::round_tolerances(o, &g0, &round_ftol);
+  }
   open.assign(n, 1);
   for (;;) {
     std::vector<char> again(n, 0);
-    int nagain = 0, budget = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!open[i]) continue;
-      rpca_ctx* c = b->ctx[i];
-      if ((rc = rpca::copy_out(c, U[i], V[i], s))) return rc;
-      const int stop = rpca::ctx_state_host(c)->stop;
-      open[i] = 0;
-      if (!o.certify || stop == STOP_NONFINITE) continue;
-      rpca_cert cert;
-      const int crc = rpca::certificate_impl(c, X[i], U[i], V[i], &cert, o.cert_tol, s);
-      if (crc < 0) return crc;
-      ++rounds[i];
-      gap[i] = cert.rel_gap;
-      certified[i] = gap[i] <= o.cert_tol;
-      if (certified[i] || stop == STOP_MAXITER || rounds[i] >= rpca::CERT_ROUNDS) continue;
-      budget = rpca::round_tolerances(o, &gtol[i], &round_ftol);
-      const int it = rpca::ctx_state_host(c)->iter;
-      limit[i] = (budget > 0 && o.max_iter - it > budget) ? it + budget : o.max_iter;
-      again[i] = open[i] = 1;
-      ++nagain;
-    }
+    if ((rc = on_workers(b, open, [&](int i, hipStream_t ws) -> int {
+           rpca_ctx* c = b->ctx[i];
+           int r = rpca::copy_out(c, U[i], V[i], ws);
+           if (r) return r;
+           const int stop = rpca::ctx_state_host(c)->stop;
+           if (!o.certify || stop == STOP_NONFINITE) return RPCA_OK;
+           rpca_cert cert;
+           r = rpca::certificate_impl(c, X[i], U[i], V[i], &cert, o.cert_tol, ws);
+           if (r < 0) return r;
+           ++rounds[i];
+           gap[i] = cert.rel_gap;
+           certified[i] = gap[i] <= o.cert_tol;
+           if (certified[i] || stop == STOP_MAXITER || rounds[i] >= rpca::CERT_ROUNDS) return RPCA_OK;
+           double ft;
+           rpca::round_tolerances(o, &gtol[i], &ft);
+           const int it = rpca::ctx_state_host(c)->iter;
+           limit[i] = (round_budget > 0 && o.max_iter - it > round_budget) ? it + round_budget : o.max_iter;
+           again[i] = 1;
+           return RPCA_OK;
+         })))
+      return rc;
+    open = again;
+    int nagain = 0;
+    for (int i = 0; i < n; ++i) nagain += again[i];
     if (!nagain) break;
     if ((rc = batch_cycles(b, X, o, final_bf16, gtol, round_ftol, limit, again))) return rc;
     for (int i = 0; i < n; ++i)

@@ -62,30 +62,62 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Operator values for the 4 rows i0+4g+r of column j (held by lane (g, c)).
+// Loads of one 16-column tile of the operator for the 4 rows i0+4g+r of column
+// j (held by lane (g, c)): X (one 16-byte load when the strip lies inside X and
+// X allows vector loads), the residual's V operands and the mask bits.  Split
+// from the arithmetic (tile_op) so that the next tile's loads are in flight
+// while the current tile is computed.  Columns past n load column n-1 (in
+// bounds) and are zeroed by tile_op.
+struct TileIn {
+  f4 x;
+  float vb[8];
+  uint32_t bits;
+};
+
 template <int SRC, bool MASKED>
-__device__ __forceinline__ void op_tile(const GArgs& a, int64_t i0, int64_t j, bool jok,
-                                        const float (&ua)[8], int KS, float (&G)[4]) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+__device__ __forceinline__ void tile_load(const GArgs& a, int64_t i0, int64_t j, bool jok, bool vec, int KS,
+                                          TileIn& t) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t jc = jok ? j : a.n - 1;
+  const float* col = a.X + jc * a.m;
+  if (vec) {
+    t.x = *reinterpret_cast<const f4*>(col + i0 + 4 * g);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 4 * g + r;
+      t.x[r] = col[i < a.m ? i : a.m - 1];
+    }
+  }
+  t.bits = 0xFu;
+  if (MASKED) t.bits = (a.mask[jc * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
+  if (SRC == SRC_RESID) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < KS) {
+        const int kk = 4 * q + g;
+        t.vb[q] = a.V[jc * a.k + (kk < a.k ? kk : a.k - 1)];
+      }
+    }
+  }
+}
+
+// Operator values of a loaded tile: G = Omega .* clip(U V^T - X) (residual) or
+// Omega .* X (data), zero outside the matrix.
+template <int SRC, bool MASKED>
+__device__ __forceinline__ void tile_op(const GArgs& a, const TileIn& t, int64_t i0, bool jok, const float (&ua)[8],
+                                        int KS, float (&G)[4]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
   float x[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t i = i0 + 4 * g + r;
-    x[r] = (jok && i < a.m) ? a.X[j * a.m + i] : 0.f;
-  }
-  uint32_t bits = 0xFu;
-  if (MASKED) {
-    bits = 0u;
-    if (jok) bits = (a.mask[j * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
-  }
+  for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? t.x[r] : 0.f;
   if (SRC == SRC_RESID) {
     f4 acc = f4{-x[0], -x[1], -x[2], -x[3]};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (q < KS) {
         const int kk = 4 * q + g;
-        const float vb = (jok && kk < a.k) ? a.V[j * a.k + kk] : 0.f;
-        acc = mfma4(ua[q], vb, acc);
+        acc = mfma4(ua[q], (jok && kk < a.k) ? t.vb[q] : 0.f, acc);
       }
     }
 #pragma unroll
@@ -94,23 +126,32 @@ __device__ __forceinline__ void op_tile(const GArgs& a, int64_t i0, int64_t j, b
 #pragma unroll
     for (int r = 0; r < 4; ++r) G[r] = x[r];
   }
-  (void)c;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    if (MASKED && !((bits >> r) & 1u)) G[r] = 0.f;
+    if (MASKED && !(jok && ((t.bits >> r) & 1u))) G[r] = 0.f;
 }
 
 template <int SRC>
 __device__ __forceinline__ void load_ua(const GArgs& a, int64_t i0, int KS, float (&ua)[8]) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t i = i0 + c < a.m ? i0 + c : a.m - 1;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kk = 4 * q + g;
-    const int64_t i = i0 + c;
-    ua[q] = (SRC == SRC_RESID && q < KS && kk < a.k && i < a.m) ? a.U[i * a.k + kk] : 0.f;
+    float v = 0.f;
+    if (SRC == SRC_RESID && q < KS) v = a.U[i * a.k + (kk < a.k ? kk : a.k - 1)];
+    ua[q] = (SRC == SRC_RESID && q < KS && kk < a.k && i0 + c < a.m) ? v : 0.f;
   }
 }
 
+// X may be read 16 bytes at a time for strips that lie inside it.
+__device__ __forceinline__ bool x_vec_ok(const GArgs& a, int64_t i0) {
+  return ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0) && ((a.m & 3) == 0) && (i0 + 16 <= a.m);
+}
+
+// Y[:, col0 + p] = Op W[:, col0 + p] (p < bw).  Wave = 16-row strip; the strip's
+// column tiles are double-buffered (the loads of tile j0 + 16, X, V, W rows and
+// mask, are issued before tile j0 is computed).
 template <int SRC, bool MASKED>
 __global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -120,8 +161,14 @@ __global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
   const int64_t s_begin = (int64_t)blockIdx.x * a.strips_per_wg;
   int64_t s_end = s_begin + a.strips_per_wg;
   if (s_end > nstrips) s_end = nstrips;
+  auto load_w = [&](int64_t j, bool jok, double (&w)[BP]) {
+    const int64_t jc = jok ? j : a.n - 1;
+#pragma unroll
+    for (int p = 0; p < BP; ++p) w[p] = (p < a.bw) ? a.W[jc * a.ldw + a.col0 + p] : 0.0;
+  };
   for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
     const int64_t i0 = s * 16;
+    const bool vec = x_vec_ok(a, i0);
     float ua[8];
     load_ua<SRC>(a, i0, KS, ua);
     double acc[4][BP];
@@ -129,18 +176,34 @@ __global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int p = 0; p < BP; ++p) acc[r][p] = 0.0;
-    for (int64_t j0 = 0; j0 < a.n; j0 += 16) {
-      const int64_t j = j0 + c;
-      const bool jok = j < a.n;
+    auto step = [&](const TileIn& t, const double (&w)[BP], int64_t j, bool jok) {
       float G[4];
-      op_tile<SRC, MASKED>(a, i0, j, jok, ua, KS, G);
-      double w[BP];
-#pragma unroll
-      for (int p = 0; p < BP; ++p) w[p] = (jok && p < a.bw) ? a.W[j * a.ldw + a.col0 + p] : 0.0;
+      tile_op<SRC, MASKED>(a, t, i0, jok, ua, KS, G);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int p = 0; p < BP; ++p) acc[r][p] = fma((double)G[r], w[p], acc[r][p]);
+        for (int p = 0; p < BP; ++p) acc[r][p] = fma((double)G[r], jok ? w[p] : 0.0, acc[r][p]);
+    };
+    TileIn t0, t1;
+    double w0[BP], w1[BP];
+    tile_load<SRC, MASKED>(a, i0, c, c < a.n, vec, KS, t0);
+    load_w(c, c < a.n, w0);
+    for (int64_t j0 = 0; j0 < a.n; j0 += 32) {
+      const int64_t ja = j0 + c, jb = j0 + 16 + c;
+      const bool more = j0 + 16 < a.n;
+      if (more) {
+        tile_load<SRC, MASKED>(a, i0, jb, jb < a.n, vec, KS, t1);
+        load_w(jb, jb < a.n, w1);
+      }
+      step(t0, w0, ja, ja < a.n);
+      if (more) {
+        const int64_t jn = j0 + 32 + c;
+        if (j0 + 32 < a.n) {
+          tile_load<SRC, MASKED>(a, i0, jn, jn < a.n, vec, KS, t0);
+          load_w(jn, jn < a.n, w0);
+        }
+        step(t1, w1, jb, jb < a.n);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -164,6 +227,10 @@ __global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
   }
 }
 
+// Per-row-group partials of Z[:, col0 + p] = Op^T Y[:, col0 + p] over one chunk of
+// RJT column tiles.  Wave = every WAVES-th strip of the row group; all loads of
+// a strip (its Y rows, U rows and the chunk's tiles) are issued together, before
+// any of its arithmetic.
 template <int SRC, bool MASKED>
 __global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
   __shared__ double sZ[RJT * 16 * BP];
@@ -182,33 +249,52 @@ __global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
   for (int t = 0; t < RJT; ++t)
 #pragma unroll
     for (int p = 0; p < BP; ++p) z[t][p] = 0.0;
-  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
-    const int64_t i0 = s * 16;
+  struct StripIn {
     float ua[8];
-    load_ua<SRC>(a, i0, KS, ua);
     double y[4][BP];
+    TileIn t[RJT];
+  };
+  auto load_strip = [&](int64_t s, StripIn& S) {
+    const int64_t i0 = s * 16;
+    const bool vec = x_vec_ok(a, i0);
+    load_ua<SRC>(a, i0, KS, S.ua);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t i = i0 + 4 * g + r;
+      const int64_t ic = i < a.m ? i : a.m - 1;
 #pragma unroll
-      for (int p = 0; p < BP; ++p) y[r][p] = (i < a.m && p < a.bw) ? a.Y[i * a.ldy + a.col0 + p] : 0.0;
+      for (int p = 0; p < BP; ++p) S.y[r][p] = (p < a.bw) ? a.Y[ic * a.ldy + a.col0 + p] : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < RJT; ++t) {
       if (t * 16 < ncols) {
-        const int64_t j = j_begin + t * 16 + c;
+        const int jl = t * 16 + c;
+        tile_load<SRC, MASKED>(a, i0, j_begin + jl, jl < ncols, vec, KS, S.t[t]);
+      }
+    }
+  };
+  auto compute_strip = [&](int64_t s, const StripIn& S) {
+    const int64_t i0 = s * 16;
+#pragma unroll
+    for (int t = 0; t < RJT; ++t) {
+      if (t * 16 < ncols) {
         const bool jok = (t * 16 + c) < ncols;
         float G[4];
-        op_tile<SRC, MASKED>(a, i0, j, jok, ua, KS, G);
+        tile_op<SRC, MASKED>(a, S.t[t], i0, jok, S.ua, KS, G);
 #pragma unroll
         for (int p = 0; p < BP; ++p) {
           double v = z[t][p];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v = fma((double)G[r], y[r][p], v);
+          for (int r = 0; r < 4; ++r) v = fma((double)G[r], (i0 + 4 * g + r < a.m) ? S.y[r][p] : 0.0, v);
           z[t][p] = v;
         }
       }
     }
+  };
+  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
+    StripIn S;
+    load_strip(s, S);
+    compute_strip(s, S);
   }
 #pragma unroll
   for (int t = 0; t < RJT; ++t)

@@ -243,21 +243,26 @@ __device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, in
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const int64_t stride = (int64_t)nb * THREADS;
   for (int64_t e = (int64_t)bx * THREADS + threadIdx.x; e < n4; e += stride) {
+    // every slot is read (unused ones point at slot 0 and their dots are ignored),
+    // and all loads are issued before the new pair is stored (the spare slot may
+    // alias a stored one as far as the compiler knows), so they are in flight together
+    f4 Sv[MEM], Yv[MEM];
+#pragma unroll
+    for (int i = 0; i < MEM; ++i) {
+      Sv[i] = __builtin_nontemporal_load(&Sp[i][e]);
+      Yv[i] = __builtin_nontemporal_load(&Yp[i][e]);
+    }
     const f4 g1 = gn[e];
     const f4 y = g1 - go[e];
     const f4 s = alpha * dd[e];
     Ssp[e] = s;
     Ysp[e] = y;
-    // every slot is read (unused ones point at slot 0 and their dots are ignored),
-    // so the loads carry no branch and can all be in flight together
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
-      const f4 Si = Sp[i][e];
-      const f4 Yi = Yp[i][e];
-      acc[4 * i + 0] += dot4(Si, g1);
-      acc[4 * i + 1] += dot4(Yi, g1);
-      acc[4 * i + 2] += dot4(Si, y);
-      acc[4 * i + 3] += dot4(Yi, y);
+      acc[4 * i + 0] += dot4(Sv[i], g1);
+      acc[4 * i + 1] += dot4(Yv[i], g1);
+      acc[4 * i + 2] += dot4(Sv[i], y);
+      acc[4 * i + 3] += dot4(Yv[i], y);
     }
     acc[I::SY] += dot4(s, y);
     acc[I::YY] += dot4(y, y);
@@ -339,15 +344,19 @@ __device__ __forceinline__ void lbfgs_direction_body(const LbfgsArgs& a, int bx,
   double acc[3] = {0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)nb * THREADS;
   for (int64_t e = (int64_t)bx * THREADS + threadIdx.x; e < n4; e += stride) {
-    const f4 gv = g[e];
-    f4 h = gamma * gv;
+    // unused slots carry zero coefficients; no branch around the loads, all of
+    // which are issued before the first is used
+    f4 Sv[MEM], Yv[MEM];
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
-      // unused slots carry zero coefficients; no branch around the loads
-      const f4 Si = reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N)[e];
-      const f4 Yi = reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N)[e];
-      h += cs[i] * Si + cy[i] * Yi;
+      Sv[i] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N) + e);
+      Yv[i] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N) + e);
     }
+    const f4 gv = g[e];
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
+    f4 h = gamma * gv;
+#pragma unroll
+    for (int i = 0; i < MEM; ++i) h += cs[i] * Sv[i] + cy[i] * Yv[i];
     const f4 dv = -h;
     d[e] = dv;
     acc[0] += dot4(gv, dv);

@@ -3,7 +3,10 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "linesearch.h"
+
 #include "rpca_internal.h"
 #include "sweep_kernel.h"
 
@@ -268,15 +271,20 @@ hipError_t launch_sweep_bf16_trial(const SweepArgs&, bool, hipStream_t);
 // waves the strips are spread over and the divisor of the widest chunk.
 // Defaults are what the cfg-sized measurements favoured; rpca_autotune
 // replaces entries by timing the candidates on the device.
+// The table is process-wide: reads and writes hold its mutex (contexts of a
+// batch are set up from several host threads).
 namespace {
-SweepTune g_tune[TUNE_KB][TUNE_NB];
-bool g_tune_init = false;
-
-void tune_defaults() {
-  if (g_tune_init) return;
-  for (int a = 0; a < TUNE_KB; ++a)
-    for (int b = 0; b < TUNE_NB; ++b) g_tune[a][b] = SweepTune{1024, 1};
-  g_tune_init = true;
+struct TuneTable {
+  std::mutex mu;
+  SweepTune t[TUNE_KB][TUNE_NB];
+  TuneTable() {
+    for (int a = 0; a < TUNE_KB; ++a)
+      for (int b = 0; b < TUNE_NB; ++b) t[a][b] = SweepTune{1024, 1};
+  }
+};
+TuneTable& tune_table() {
+  static TuneTable tt;  // initialised once, thread-safely
+  return tt;
 }
 }  // namespace
 
@@ -284,13 +292,15 @@ int tune_k_bucket(int k) { return k <= 8 ? 0 : k <= 16 ? 1 : k <= 24 ? 2 : 3; }
 int tune_n_bucket(int64_t n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4; }
 
 SweepTune tune_get(int k, int64_t n) {
-  tune_defaults();
-  return g_tune[tune_k_bucket(k)][tune_n_bucket(n)];
+  TuneTable& tt = tune_table();
+  std::lock_guard<std::mutex> lock(tt.mu);
+  return tt.t[tune_k_bucket(k)][tune_n_bucket(n)];
 }
 
 void tune_set(int kbucket, int nbucket, SweepTune t) {
-  tune_defaults();
-  g_tune[kbucket][nbucket] = t;
+  TuneTable& tt = tune_table();
+  std::lock_guard<std::mutex> lock(tt.mu);
+  tt.t[kbucket][nbucket] = t;
 }
 
 // Column chunks (each fitting the sweep's LDS budget) and the wave/workgroup
