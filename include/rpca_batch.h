@@ -63,7 +63,12 @@ int rpca_batch_objgrad(rpca_batch* b, const float* const* X, const float* const*
  * input (unless opts->init is RPCA_INIT_RSVD) and the solutions on output.
  * opts applies to all instances (NULL = defaults).  info: host array of
  * `count` records, or NULL.  Blocks until every instance is done.  Returns
- * the largest per-instance status (warnings > 0), or the first error < 0. */
+ * the largest per-instance status (warnings > 0), or the first error < 0.
+ * The solver slots run batched on the batch's stream; the per-instance steps
+ * that synchronise with the host (rSVD start, preconditioner refresh and
+ * restart between cycles, certificates) run on up to 16 host worker threads,
+ * each with its own stream of the batch, so a batch must not be used from
+ * two host threads at once. */
 int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, float* const* V,
                      const rpca_opts* opts, rpca_info* info, void* stream);
 

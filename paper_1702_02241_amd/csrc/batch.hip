@@ -23,8 +23,18 @@
 
 namespace {
 
-// Host worker threads (and streams) of the per-instance phases of a batched solve.
-constexpr int BATCH_WORKERS = 4;
+// Host worker threads (and streams) of the per-instance phases of a batched solve
+// (at most; fewer when the host has fewer hardware threads).  Measured on the
+// 64-instance batch: 4 workers 686 ms, 8 573 ms, 16 540 ms per solve.
+constexpr int BATCH_WORKERS = 16;
+
+int worker_count() {
+  static const int w = [] {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min((unsigned)BATCH_WORKERS, hw ? hw : 1u));
+  }();
+  return w;
+}
 
 // Sweep waves per compute unit that a batch's decomposition aims at (per tile
 // class), and the fewest strips a wave of a batched sweep is given.
@@ -224,19 +234,20 @@ int batched_run(rpca_batch* b, const rpca_opts& o, bool bf16, bool use_graph) {
 
 
 // Run fn(i, stream) for every instance i with sel[i] on the worker threads
-// (instance i on worker i % BATCH_WORKERS, in increasing i), each worker on its
+// (instance i on worker i % worker_count(), in increasing i), each worker on its
 // own stream ordered after the batch stream; the batch stream is then ordered
 // after every worker's work.  Returns the first error.
 template <typename Fn>
 int on_workers(rpca_batch* b, const std::vector<char>& sel, Fn fn) {
   if (hipEventRecord(b->ev_in, b->stream) != hipSuccess) return RPCA_EHIP;
+  const int nw = worker_count();
   int rc[BATCH_WORKERS] = {};
   auto work = [&](int t) {
     if (hipStreamWaitEvent(b->aux[t], b->ev_in, 0) != hipSuccess) {
       rc[t] = RPCA_EHIP;
       return;
     }
-    for (int i = t; i < b->count; i += BATCH_WORKERS) {
+    for (int i = t; i < b->count; i += nw) {
       if (!sel[i]) continue;
       const int r = fn(i, b->aux[t]);
       if (r < 0) {
@@ -247,12 +258,12 @@ int on_workers(rpca_batch* b, const std::vector<char>& sel, Fn fn) {
     if (hipEventRecord(b->ev_aux[t], b->aux[t]) != hipSuccess) rc[t] = RPCA_EHIP;
   };
   std::vector<std::thread> th;
-  for (int t = 1; t < BATCH_WORKERS; ++t) th.emplace_back(work, t);
+  for (int t = 1; t < nw; ++t) th.emplace_back(work, t);
   work(0);
   for (auto& x : th) x.join();
-  for (int t = 0; t < BATCH_WORKERS; ++t)
+  for (int t = 0; t < nw; ++t)
     if (rc[t]) return rc[t];
-  for (int t = 0; t < BATCH_WORKERS; ++t)
+  for (int t = 0; t < nw; ++t)
     if (hipStreamWaitEvent(b->stream, b->ev_aux[t], 0) != hipSuccess) return RPCA_EHIP;
   return RPCA_OK;
 }
@@ -280,17 +291,19 @@ int batch_cycles(rpca_batch* b, const float* const* X, const rpca_opts& o, bool 
       nact += active[i];
     }
     if (!nact) break;
-    for (int i = 0; i < n; ++i) {
-      if (!active[i]) continue;
-      rpca_ctx* c = b->ctx[i];
-      const SolverState* h = rpca::ctx_state_host(c);
-      int cap = limit[i];
-      if (o.precond) {
-        if ((rc = rpca::precond_refresh(c, h->cur, s))) return rc;
-        cap = (limit[i] - h->iter > o.precond_cycle) ? h->iter + o.precond_cycle : limit[i];
-      }
-      if ((rc = rpca::restart_state(c, gtol[i], ftol, cap, o.precond != 0, s))) return rc;
-    }
+    // fresh preconditioners and restarted states (host-synchronising steps) on the workers
+    if ((rc = on_workers(b, active, [&](int i, hipStream_t ws) -> int {
+           rpca_ctx* c = b->ctx[i];
+           const SolverState* h = rpca::ctx_state_host(c);
+           int cap = limit[i];
+           int r;
+           if (o.precond) {
+             if ((r = rpca::precond_refresh(c, h->cur, ws))) return r;
+             cap = (limit[i] - h->iter > o.precond_cycle) ? h->iter + o.precond_cycle : limit[i];
+           }
+           return rpca::restart_state(c, gtol[i], ftol, cap, o.precond != 0, ws);
+         })))
+      return rc;
     // argument tables at each instance's current iterate and variables
     std::vector<SweepArgs> sl(n), se(n);
     std::vector<FinishArgs> fl(n), fe(n);
