@@ -561,6 +561,9 @@ int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows
                        (const double*)Y, ld, l, (const double*)ws.T, l, rows, tmp, (float*)nullptr, ld);
     if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
     if (hipMemcpyAsync(Y, tmp, (size_t)rows * ld * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return RPCA_EHIP;
+    // T is the host source of an asynchronous copy from pageable memory: the
+    // runtime may read it after the call returns, so it must outlive the copy
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   }
   return RPCA_OK;
 }
