@@ -88,16 +88,25 @@ __device__ __forceinline__ float huber(float Rn, float lam_s, uint32_t observed,
   return gn;
 }
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+// Four block sums at once (sh: 4 * WAVES doubles); results in v on thread 0,
+// each summed in a fixed order (the wave tree, then the waves in order).
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[e] += __shfl_xor(v[e], o, 64);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh[e * WAVES + (threadIdx.x >> 6)] = v[e];
   __syncthreads();
-  double r = 0.0;
   if (threadIdx.x == 0)
-    for (int w = 0; w < WAVES; ++w) r += sh[w];
-  return r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double r = 0.0;
+      for (int w = 0; w < WAVES; ++w) r += sh[e * WAVES + w];
+      v[e] = r;
+    }
 }
 
 // Transpose tiles per wave: the tiles of a group use distinct ones so that their
@@ -219,18 +228,30 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
       sVt[jl * LDV + kk] = v;
     }
   } else {
-    for (int idx = tid; idx < cwp * KMAX; idx += NT) {
+    // every thread's loads first (at most SLOTS each), then the LDS stores: the
+    // loads are in flight together instead of one latency per element
+    constexpr int SLOTS = (TMAX * 16 * KMAX + NT - 1) / NT;
+    float vs[SLOTS];
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int idx = tid + u * NT;
       const int jl = idx / KMAX, kk = idx % KMAX;
       float v = 0.f;
-      if (jl < ncols && kk < k) {
+      if (idx < cwp * KMAX && jl < ncols && kk < k) {
         const int64_t o = (j_begin + jl) * k + kk;
         v = V[o];
-        if (TRIAL) {
-          v = fmaf(alpha, a.dV[o], v);
-          if (rg == 0) a.Vt[outi][o] = v;
-        }
+        if (TRIAL) v = fmaf(alpha, a.dV[o], v);
       }
-      sVt[jl * LDV + kk] = v;
+      vs[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < cwp * KMAX) {
+        const int jl = idx / KMAX, kk = idx % KMAX;
+        sVt[jl * LDV + kk] = vs[u];
+        if (TRIAL && rg == 0 && jl < ncols && kk < k) a.Vt[outi][(j_begin + jl) * k + kk] = vs[u];
+      }
     }
   }
   __syncthreads();
@@ -626,15 +647,13 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
     gvp[j_begin * k + idx] = acc;
   }
   double* sp = a.spart + ((int64_t)rg * a.nchunks + ch) * RPCA_NSCAL;
-  const double v0 = block_sum(f_acc, sRed);
-  const double v1 = block_sum(uu_acc, sRed);
-  const double v2 = block_sum(gud_acc, sRed);
-  const double v3 = block_sum(gg_acc, sRed);
+  double v4[4] = {f_acc, uu_acc, gud_acc, gg_acc};
+  block_sum4(v4, sRed);
   if (tid == 0) {
-    sp[0] = v0;
-    sp[1] = v1;
-    sp[2] = v2;
-    sp[3] = v3;
+    sp[0] = v4[0];
+    sp[1] = v4[1];
+    sp[2] = v4[2];
+    sp[3] = v4[3];
   }
 }
 
@@ -642,7 +661,7 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
 template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
 __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   extern __shared__ float lds[];
-  __shared__ double sRed[WAVES];
+  __shared__ double sRed[4 * WAVES];
   sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(a, blockIdx.x, blockIdx.y, lds, sRed);
 }
 
@@ -657,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* __restrict_
                                                     const SweepItem* __restrict__ items, int nitems,
                                                     unsigned* head) {
   extern __shared__ float lds[];
-  __shared__ double sRed[WAVES];
+  __shared__ double sRed[4 * WAVES];
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
