@@ -105,95 +105,132 @@ struct DotIdx {
   static constexpr int NV = SY + 8;
 };
 
-// Pair bookkeeping of the update (one thread): norms, the keep test, the new
-// pair's inner products into the slot matrices, the ring order, gamma.  The
-// ordered a = S^T g and b = Y^T g go to a_ord / b_ord.
+// Value of lane `src` (a constant) to every lane, through the scalar unit.
+__device__ __forceinline__ double bcast(double v, int src) {
+  const unsigned long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ int bcast_int(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+// The small algebra of an update, by one wave on the LDS copy of the state; lane
+// i owns stored pair i (in age order).  Pair bookkeeping: norms, the keep test,
+// the new pair's inner products into the slot matrices, the ring order, gamma.
+// Then the compact-form coefficients from R[i][j] = s_i^T y_j and Q[i][j] =
+// y_i^T y_j (ordered), with a = S^T g, b = Y^T g:
+//   u = R^{-1} a                               (back substitution)
+//   w_i = R_ii u_i - gamma b_i + gamma (Q u)_i
+//   p = R^{-T} w                               (forward substitution)
+//   coef_s = p, coef_y = -gamma u              (scattered to the slots)
+// Both substitutions run column by column: the solved entry is broadcast from
+// its lane through the scalar unit and every lane updates its own entry, so a
+// step costs one broadcast and one FMA.
 template <int MEM>
-__device__ void update_pairs(SolverState* st, const double* D, double* a_ord, double* b_ord) {
+__device__ void update_wave(SolverState* st, const double* D) {
   using I = DotIdx<MEM>;
+  const int lane = threadIdx.x & 63;
   const int cnt = st->count;
   const double sy = D[I::SY], yy = D[I::YY], ss = D[I::SS];
-  st->iter += 1;
-  st->gnorm_inf = D[I::GINF];
-  st->gnorm1 = D[I::G1];
-  st->gg = D[I::GG];
-  for (int i = 0; i < cnt; ++i) {
-    a_ord[i] = D[4 * i + 0];
-    b_ord[i] = D[4 * i + 1];
+  if (lane == 0) {
+    st->iter += 1;
+    st->gnorm_inf = D[I::GINF];
+    st->gnorm1 = D[I::G1];
+    st->gg = D[I::GG];
   }
+  double av = (lane < cnt) ? D[4 * lane + 0] : 0.0;
+  double bv = (lane < cnt) ? D[4 * lane + 1] : 0.0;
+  int ord = (lane < cnt) ? st->order[lane] : 0;
+  int h = cnt;
   const bool keep = sy > 1e-10 * sqrt(ss * yy) && isfinite(sy) && isfinite(yy);
   if (keep) {
     const int sn = st->spare;
-    for (int i = 0; i < cnt; ++i) {
-      const int so = st->order[i];
-      st->SY[so][sn] = D[4 * i + 2];
-      st->YY[so][sn] = D[4 * i + 3];
-      st->YY[sn][so] = D[4 * i + 3];
+    if (lane < cnt) {
+      st->SY[ord][sn] = D[4 * lane + 2];
+      st->YY[ord][sn] = D[4 * lane + 3];
+      st->YY[sn][ord] = D[4 * lane + 3];
     }
-    st->SY[sn][sn] = sy;
-    st->YY[sn][sn] = yy;
-    int h = cnt;
+    if (lane == 0) {
+      st->SY[sn][sn] = sy;
+      st->YY[sn][sn] = yy;
+    }
     int next_spare;
     if (h < st->mem) {
-      st->order[h] = sn;
-      a_ord[h] = D[I::SG];
-      b_ord[h] = D[I::YG];
+      if (lane == h) {
+        ord = sn;
+        av = D[I::SG];
+        bv = D[I::YG];
+      }
       h += 1;
       next_spare = h;
     } else {
-      next_spare = st->order[0];
-      for (int i = 0; i + 1 < h; ++i) {
-        st->order[i] = st->order[i + 1];
-        a_ord[i] = a_ord[i + 1];
-        b_ord[i] = b_ord[i + 1];
+      // full: the oldest pair leaves, the others move down one place
+      next_spare = bcast_int(ord, 0);
+      const int ord_up = __shfl_down(ord, 1, 64);
+      const double av_up = __shfl_down(av, 1, 64), bv_up = __shfl_down(bv, 1, 64);
+      if (lane < h - 1) {
+        ord = ord_up;
+        av = av_up;
+        bv = bv_up;
+      } else if (lane == h - 1) {
+        ord = sn;
+        av = D[I::SG];
+        bv = D[I::YG];
       }
-      st->order[h - 1] = sn;
-      a_ord[h - 1] = D[I::SG];
-      b_ord[h - 1] = D[I::YG];
     }
-    st->count = h;
-    st->spare = next_spare;
-    st->newest = sn;
-    st->gamma = sy / yy;
+    if (lane < h) st->order[lane] = ord;
+    if (lane == 0) {
+      st->count = h;
+      st->spare = next_spare;
+      st->newest = sn;
+      st->gamma = sy / yy;
+    }
   }
-}
-
-// Compact-form coefficients from dense, ordered copies R[i][j] = s_i^T y_j and
-// Q[i][j] = y_i^T y_j, by one wave: lane j holds entry j of the sums, the
-// triangular solves step through i with a wave reduction each (h <= 15 steps).
-// u, w, p live in LDS (us, ps) so every lane sees them.
-__device__ void compact_wave(SolverState* st, const double (*R)[RPCA_MEMMAX], const double (*Q)[RPCA_MEMMAX],
-                             const double* a_ord, const double* b_ord, double* us, double* ps) {
-  const int lane = threadIdx.x & 63;
-  const int h = st->count;
-  const double gamma = st->gamma;
-  // u = R^{-1} a  (R upper triangular): u_i = (a_i - sum_{j>i} R_ij u_j) / R_ii
-  for (int i = h - 1; i >= 0; --i) {
-    double t = (lane > i && lane < h) ? R[i][lane] * us[lane] : 0.0;
-    t = wave_sum(t);
-    if (lane == 0) us[i] = (a_ord[i] - t) / R[i][i];
+  if (h == 0) return;
+  const double gamma = keep ? sy / yy : st->gamma;
+  // this lane's row and column of R and row of Q (ordered pairs)
+  double rowR[MEM], colR[MEM], rowQ[MEM];
+  double diag = 1.0;
+#pragma unroll
+  for (int i = 0; i < MEM; ++i) {
+    const int oi = bcast_int(ord, i);
+    const bool in = lane < h && i < h;
+    rowR[i] = in ? st->SY[ord][oi] : 0.0;
+    colR[i] = in ? st->SY[oi][ord] : 0.0;
+    rowQ[i] = in ? st->YY[ord][oi] : 0.0;
+    if (i == lane) diag = in ? rowR[i] : 1.0;
   }
-  // w_i = R_ii u_i - gamma b_i + gamma sum_j Q_ij u_j  (lane i)
-  double wv = 0.0;
-  if (lane < h) {
-    double acc = R[lane][lane] * us[lane] - gamma * b_ord[lane];
-    for (int j2 = 0; j2 < h; ++j2) acc += gamma * Q[lane][j2] * us[j2];
-    wv = acc;
+  const double dinv = 1.0 / diag;
+  double u = (lane < h) ? av : 0.0;
+#pragma unroll
+  for (int i = MEM - 1; i >= 0; --i) {
+    if (i < h) {
+      const double ui = bcast(u * dinv, i);
+      if (lane == i) u = ui;
+      else if (lane < i) u = fma(-rowR[i], ui, u);
+    }
   }
-  // p = R^{-T} w: p_i = (w_i - sum_{j<i} R_ji p_j) / R_ii
-  for (int i = 0; i < h; ++i) {
-    double t = (lane < i) ? R[lane][i] * ps[lane] : 0.0;
-    t = wave_sum(t);
-    const double wi = __shfl(wv, i, 64);
-    if (lane == 0) ps[i] = (wi - t) / R[i][i];
+  double qu = 0.0;
+#pragma unroll
+  for (int j = 0; j < MEM; ++j)
+    if (j < h) qu = fma(rowQ[j], bcast(u, j), qu);
+  double p = (lane < h) ? diag * u - gamma * bv + gamma * qu : 0.0;
+#pragma unroll
+  for (int i = 0; i < MEM; ++i) {
+    if (i < h) {
+      const double pi = bcast(p * dinv, i);
+      if (lane == i) p = pi;
+      else if (lane > i && lane < h) p = fma(-colR[i], pi, p);
+    }
   }
   if (lane < RPCA_MEMMAX) {
     st->coef_s[lane] = 0.0;
     st->coef_y[lane] = 0.0;
   }
   if (lane < h) {
-    st->coef_s[st->order[lane]] = ps[lane];
-    st->coef_y[st->order[lane]] = -gamma * us[lane];
+    st->coef_s[ord] = p;
+    st->coef_y[ord] = -gamma * u;
   }
 }
 
@@ -294,26 +331,12 @@ __device__ __forceinline__ void lbfgs_update_final_body(const LbfgsArgs& a, int 
   __shared__ double D[NV];
   combine_partials<NV, I::GINF>(a.part, nb, D);
   __shared__ SolverState sst;
-  __shared__ double a_ord[RPCA_MEMMAX], b_ord[RPCA_MEMMAX];
-  __shared__ double R[RPCA_MEMMAX][RPCA_MEMMAX], Q[RPCA_MEMMAX][RPCA_MEMMAX];
   copy_state_block(&sst, st);
   __syncthreads();
-  if (threadIdx.x == 0) update_pairs<MEM>(&sst, D, a_ord, b_ord);
-  __syncthreads();
-  {
-    // dense ordered copies of the pair matrices (one entry per thread)
-    const int h = sst.count;
-    const int i = threadIdx.x / RPCA_MEMMAX, j = threadIdx.x % RPCA_MEMMAX;
-    if (i < h && j < h) {
-      R[i][j] = sst.SY[sst.order[i]][sst.order[j]];
-      Q[i][j] = sst.YY[sst.order[i]][sst.order[j]];
-    }
+  if (threadIdx.x < 64) {
+    update_wave<MEM>(&sst, D);
+    if (threadIdx.x == 0) update_stops<MEM>(&sst, D);
   }
-  __syncthreads();
-  __shared__ double us[RPCA_MEMMAX], ps[RPCA_MEMMAX];
-  if (threadIdx.x < 64 && sst.count > 0) compact_wave(&sst, R, Q, a_ord, b_ord, us, ps);
-  __syncthreads();
-  if (threadIdx.x == 0) update_stops<MEM>(&sst, D);
   __syncthreads();
   copy_state_block(st, &sst);
 }
