@@ -38,6 +38,7 @@ constexpr int THREADS = 256;
 constexpr int WAVES = 4;
 constexpr int BP = 8;      // columns per pass of a thin product
 constexpr int RJT = 4;     // 16-column tiles per chunk of the right sweep
+constexpr size_t LEFT_LDS_MAX = 48 * 1024;  // W and V staged in LDS up to this size
 
 enum { SRC_RESID = 0, SRC_DATA = 1 };
 
@@ -227,19 +228,171 @@ __global__ __launch_bounds__(THREADS) void k_left(GArgs a) {
   }
 }
 
-// Per-row-group partials of Z[:, col0 + p] = Op^T Y[:, col0 + p] over one chunk of
-// RJT column tiles.  Wave = every WAVES-th strip of the row group; all loads of
-// a strip (its Y rows, U rows and the chunk's tiles) are issued together, before
-// any of its arithmetic.
+// Y[:, col0 + p] = Op W[:, col0 + p] (p < bw) with W (and V, for the residual)
+// staged in LDS once per workgroup, so the only global loads of the strip loop
+// are X: each strip issues the X loads of LB column tiles at once (one latency
+// per LB tiles instead of one per tile).  Used when W and V fit the LDS budget.
+constexpr int LB = 8;
 template <int SRC, bool MASKED>
-__global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
+__global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
+  extern __shared__ double lds_left[];
+  constexpr int LW = BP + 1;                              // padded row: 16 columns hit distinct banks
+  double* sW = lds_left;                                  // [n][LW]
+  float* sV = reinterpret_cast<float*>(sW + a.n * LW);    // [n][k] (residual only)
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = lane & 15, g = lane >> 4;
+  const int KS = (a.k + 3) >> 2;
+  {
+    const int64_t nw = a.n * BP;
+    for (int64_t base = threadIdx.x; base < nw; base += 4 * THREADS) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t idx = base + u * THREADS;
+        const int p = (int)(idx % BP);
+        v[u] = (idx < nw && p < a.bw) ? a.W[(idx / BP) * a.ldw + a.col0 + p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t idx = base + u * THREADS;
+        if (idx < nw) sW[(idx / BP) * LW + idx % BP] = v[u];
+      }
+    }
+    if (SRC == SRC_RESID) {
+      const int64_t nv = a.n * a.k;
+      for (int64_t base = threadIdx.x; base < nv; base += 4 * THREADS) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (base + u * THREADS < nv) ? a.V[base + u * THREADS] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (base + u * THREADS < nv) sV[base + u * THREADS] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t nstrips = (a.m + 15) >> 4;
+  const int64_t s_begin = (int64_t)blockIdx.x * a.strips_per_wg;
+  int64_t s_end = s_begin + a.strips_per_wg;
+  if (s_end > nstrips) s_end = nstrips;
+  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
+    const int64_t i0 = s * 16;
+    const bool vec = x_vec_ok(a, i0);
+    float ua[8];
+    load_ua<SRC>(a, i0, KS, ua);
+    double acc[4][BP];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int p = 0; p < BP; ++p) acc[r][p] = 0.0;
+    for (int64_t jb = 0; jb < a.n; jb += 16 * LB) {
+      f4 xs[LB];
+      uint32_t bits[LB];
+#pragma unroll
+      for (int t = 0; t < LB; ++t) {
+        if (jb + 16 * t < a.n) {
+          const int64_t j = jb + 16 * t + c;
+          const int64_t jc = j < a.n ? j : a.n - 1;
+          const float* col = a.X + jc * a.m;
+          if (vec) {
+            xs[t] = *reinterpret_cast<const f4*>(col + i0 + 4 * g);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int64_t i = i0 + 4 * g + r;
+              xs[t][r] = col[i < a.m ? i : a.m - 1];
+            }
+          }
+          bits[t] = MASKED ? (a.mask[jc * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu : 0xFu;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < LB; ++t) {
+        if (jb + 16 * t < a.n) {
+          const int64_t j = jb + 16 * t + c;
+          const bool jok = j < a.n;
+          const int64_t jc = jok ? j : a.n - 1;
+          float G[4];
+          float x[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? xs[t][r] : 0.f;
+          if (SRC == SRC_RESID) {
+            f4 r4 = f4{-x[0], -x[1], -x[2], -x[3]};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              if (q < KS) {
+                const int kk = 4 * q + g;
+                r4 = mfma4(ua[q], (jok && kk < a.k) ? sV[jc * a.k + kk] : 0.f, r4);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(r4[r], -a.lam_s), a.lam_s);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[r] = x[r];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (!jok || (MASKED && !((bits[t] >> r) & 1u))) G[r] = 0.f;
+          double w[BP];
+#pragma unroll
+          for (int p = 0; p < BP; ++p) w[p] = sW[jc * LW + p];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int p = 0; p < BP; ++p) acc[r][p] = fma((double)G[r], w[p], acc[r][p]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int p = 0; p < BP; ++p) {
+        double v = acc[r][p];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        acc[r][p] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + 4 * g + r;
+      double sel = 0.0;
+#pragma unroll
+      for (int p = 0; p < BP; ++p) sel = (p == c) ? acc[r][p] : sel;
+      if (c < a.bw && i < a.m) a.Y[i * a.ldy + a.col0 + c] = sel;
+    }
+  }
+}
+
+// LDS bytes of k_left_lds for n columns and rank k (0 residual / 1 data).
+size_t left_lds_bytes(int64_t n, int k, int src) {
+  return (size_t)n * (BP + 1) * 8 + (src == SRC_RESID ? (size_t)n * k * 4 : 0);
+}
+
+// Per-row-group partials of Z[:, col0 + p] = Op^T Y[:, col0 + p] over one chunk of
+// RJT column tiles (wave = every WAVES-th strip of the row group), with the
+// chunk's V columns staged in LDS and each strip's Y rows brought in once per wave (lane l loads two of the strip's 16 x BP values into
+// LDS; every lane then reads its rows from there instead of 32 scattered global
+// loads).  The next strip's X tiles, Y values and U rows are loaded into
+// registers while the current strip is computed.
+template <int SRC, bool MASKED>
+__global__ __launch_bounds__(THREADS) void k_right_lds(GArgs a) {
   __shared__ double sZ[RJT * 16 * BP];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ float sV[RJT * 16 * 32];
+  __shared__ double sY[WAVES][16 * BP];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = lane & 15, g = lane >> 4;
   const int KS = (a.k + 3) >> 2;
   const int rg = blockIdx.x, ch = blockIdx.y;
   const int64_t j_begin = (int64_t)ch * RJT * 16;
   const int ncols = (int)((a.n - j_begin) < RJT * 16 ? (a.n - j_begin) : RJT * 16);
+  if (SRC == SRC_RESID)
+    for (int idx = threadIdx.x; idx < ncols * a.k; idx += THREADS) sV[idx] = a.V[j_begin * a.k + idx];
+  __syncthreads();
   const int64_t nstrips = (a.m + 15) >> 4;
   const int64_t s_begin = (int64_t)rg * a.strips_per_wg;
   int64_t s_end = s_begin + a.strips_per_wg;
@@ -251,50 +404,93 @@ __global__ __launch_bounds__(THREADS) void k_right(GArgs a) {
     for (int p = 0; p < BP; ++p) z[t][p] = 0.0;
   struct StripIn {
     float ua[8];
-    double y[4][BP];
-    TileIn t[RJT];
+    double y2[2];  // Y[i0 + lane/4][col0 + 2 (lane%4) + {0, 1}]
+    f4 x[RJT];
+    uint32_t bits[RJT];
   };
+  const int yrow = lane >> 2, yp = 2 * (lane & 3);
   auto load_strip = [&](int64_t s, StripIn& S) {
     const int64_t i0 = s * 16;
     const bool vec = x_vec_ok(a, i0);
     load_ua<SRC>(a, i0, KS, S.ua);
+    const int64_t iy = (i0 + yrow < a.m) ? i0 + yrow : a.m - 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t i = i0 + 4 * g + r;
-      const int64_t ic = i < a.m ? i : a.m - 1;
-#pragma unroll
-      for (int p = 0; p < BP; ++p) S.y[r][p] = (p < a.bw) ? a.Y[ic * a.ldy + a.col0 + p] : 0.0;
-    }
+    for (int e = 0; e < 2; ++e) S.y2[e] = (yp + e < a.bw) ? a.Y[iy * a.ldy + a.col0 + yp + e] : 0.0;
 #pragma unroll
     for (int t = 0; t < RJT; ++t) {
       if (t * 16 < ncols) {
         const int jl = t * 16 + c;
-        tile_load<SRC, MASKED>(a, i0, j_begin + jl, jl < ncols, vec, KS, S.t[t]);
+        const int64_t jc = j_begin + (jl < ncols ? jl : ncols - 1);
+        const float* col = a.X + jc * a.m;
+        if (vec) {
+          S.x[t] = *reinterpret_cast<const f4*>(col + i0 + 4 * g);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + 4 * g + r;
+            S.x[t][r] = col[i < a.m ? i : a.m - 1];
+          }
+        }
+        S.bits[t] = MASKED ? (a.mask[jc * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu : 0xFu;
       }
     }
   };
   auto compute_strip = [&](int64_t s, const StripIn& S) {
     const int64_t i0 = s * 16;
+    double* y = sY[wave];
+    y[yrow * BP + yp] = (i0 + yrow < a.m) ? S.y2[0] : 0.0;
+    y[yrow * BP + yp + 1] = (i0 + yrow < a.m) ? S.y2[1] : 0.0;
+    // the wave's own LDS writes are visible to its later reads (in order within a wave)
 #pragma unroll
     for (int t = 0; t < RJT; ++t) {
       if (t * 16 < ncols) {
-        const bool jok = (t * 16 + c) < ncols;
+        const int jl = t * 16 + c;
+        const bool jok = jl < ncols;
+        float x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? S.x[t][r] : 0.f;
         float G[4];
-        tile_op<SRC, MASKED>(a, S.t[t], i0, jok, S.ua, KS, G);
+        if (SRC == SRC_RESID) {
+          f4 r4 = f4{-x[0], -x[1], -x[2], -x[3]};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (q < KS) {
+              const int kk = 4 * q + g;
+              r4 = mfma4(S.ua[q], (jok && kk < a.k) ? sV[jl * a.k + kk] : 0.f, r4);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(r4[r], -a.lam_s), a.lam_s);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) G[r] = x[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!jok || (MASKED && !((S.bits[t] >> r) & 1u))) G[r] = 0.f;
 #pragma unroll
         for (int p = 0; p < BP; ++p) {
           double v = z[t][p];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v = fma((double)G[r], (i0 + 4 * g + r < a.m) ? S.y[r][p] : 0.0, v);
+          for (int r = 0; r < 4; ++r) v = fma((double)G[r], y[(4 * g + r) * BP + p], v);
           z[t][p] = v;
         }
       }
     }
   };
-  for (int64_t s = s_begin + wave; s < s_end; s += WAVES) {
-    StripIn S;
-    load_strip(s, S);
-    compute_strip(s, S);
+  int64_t s = s_begin + wave;
+  if (s < s_end) {
+    StripIn A, B;
+    load_strip(s, A);
+    for (; s < s_end; s += 2 * WAVES) {
+      const int64_t sb = s + WAVES;
+      if (sb < s_end) load_strip(sb, B);
+      compute_strip(s, A);
+      if (sb < s_end) {
+        if (sb + WAVES < s_end) load_strip(sb + WAVES, A);
+        compute_strip(sb, B);
+      }
+    }
   }
 #pragma unroll
   for (int t = 0; t < RJT; ++t)
@@ -460,7 +656,16 @@ hipError_t left_product(const rpca::CtxView& cv, const Workspace& w, const float
     a.col0 = col0;
     a.bw = std::min(BP, l - col0);
     const dim3 grid(w.rg_left);
-    if (src == SRC_RESID) {
+    const size_t lb = left_lds_bytes(cv.n, cv.k, src);
+    if (lb <= LEFT_LDS_MAX) {
+      if (src == SRC_RESID) {
+        if (cv.mask) hipLaunchKernelGGL((k_left_lds<SRC_RESID, true>), grid, dim3(THREADS), lb, s, a);
+        else hipLaunchKernelGGL((k_left_lds<SRC_RESID, false>), grid, dim3(THREADS), lb, s, a);
+      } else {
+        if (cv.mask) hipLaunchKernelGGL((k_left_lds<SRC_DATA, true>), grid, dim3(THREADS), lb, s, a);
+        else hipLaunchKernelGGL((k_left_lds<SRC_DATA, false>), grid, dim3(THREADS), lb, s, a);
+      }
+    } else if (src == SRC_RESID) {
       if (cv.mask) hipLaunchKernelGGL((k_left<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
       else hipLaunchKernelGGL((k_left<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
     } else {
@@ -498,11 +703,11 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
     a.bw = std::min(BP, l - col0);
     const dim3 grid(w.rg_right, w.nch_right);
     if (src == SRC_RESID) {
-      if (cv.mask) hipLaunchKernelGGL((k_right<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
-      else hipLaunchKernelGGL((k_right<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
+      if (cv.mask) hipLaunchKernelGGL((k_right_lds<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_right_lds<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
     } else {
-      if (cv.mask) hipLaunchKernelGGL((k_right<SRC_DATA, true>), grid, dim3(THREADS), 0, s, a);
-      else hipLaunchKernelGGL((k_right<SRC_DATA, false>), grid, dim3(THREADS), 0, s, a);
+      if (cv.mask) hipLaunchKernelGGL((k_right_lds<SRC_DATA, true>), grid, dim3(THREADS), 0, s, a);
+      else hipLaunchKernelGGL((k_right_lds<SRC_DATA, false>), grid, dim3(THREADS), 0, s, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
