@@ -111,6 +111,42 @@ def test_certificate_matches_oracle_exact(small):
             assert abs(c.E - o["E"]) <= 1e-3 * o["E"]
 
 
+@pytest.mark.parametrize("m,n,k,p_obs", [
+    (500, 1100, 12, None),   # W and V exceed the LDS budget: global-operand left product
+    (400, 150, 9, 0.8),      # masked operator in both thin products (LDS path)
+    (333, 77, 5, 0.6),       # masked, ragged rows and a single partial column chunk
+])
+def test_certificate_other_paths_match_oracle(m, n, k, p_obs):
+    """The certificate at a near-optimal point (a few oracle L-BFGS iterations from
+    the rSVD start) on shapes that take the other code paths of the thin products;
+    same bars as the exact-certificate test (T1..T3 to 1e-3, the leading Ritz
+    value to 1e-3, ||M||_F^2 to 1e-4)."""
+    dev = device()
+    if p_obs is None:
+        p = synth.gaussian_rpca(m=m, n=n, r=max(1, k - 4), k=k, seed=600 + m, lam_s=1.0 / np.sqrt(max(m, n)))
+    else:
+        p = synth.partial_rpca(m=m, n=n, r=max(1, k - 4), k=k, p_obs=p_obs, seed=600 + m)
+    mask = p.mask
+    Om = synth.gaussian_matrix(p.n, p.k + 10, 12)
+    U0, V0 = rs.rsvd_factors(p.X, p.k, Om, mask=mask)
+    res = lb.lbfgs(ob.make_fg(p.X, p.lam_s, p.lam_l, p.k, mask), ob.pack(U0, V0), max_iter=30)
+    U, V = ob.unpack(res["x"], p.m, p.n, p.k)
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l, mask=mask)
+    Xcm = T.to_device_X(p.X, dev)
+    c = ctx.certificate(Xcm, T.to_device_factor(U, dev), T.to_device_factor(V, dev))
+    o = ce.certificate(f32(U), f32(V), f32(p.X), p.lam_s, p.lam_l, mask=mask, tau=1e-6)
+    print(f"[cert {m}x{n} k={k} p_obs={p_obs}] gpu T=({c.T1:.3e},{c.T2:.3e},{c.T3:.3e},{c.T4:.3e}) "
+          f"theta0 {c.theta[0]:.6e} normM2 {c.normM2:.6e} | oracle T=({o['T1']:.3e},{o['T2']:.3e},"
+          f"{o['T3']:.3e},{o['T4']:.3e}) sv0 {o['sv_perp'][0]:.6e} normM2 {o['normM2']:.6e}")
+    assert c.r == o["r"]
+    for key in ("T1", "T2", "T3"):
+        a, b = getattr(c, key), o[key]
+        assert abs(a - b) <= 1e-3 * max(b, 1.0) + 1e-5, key
+    assert abs(c.theta[0] - o["sv_perp"][0]) <= 1e-3 * o["sv_perp"][0] + 1e-5
+    assert abs(c.normM2 - o["normM2"]) <= 1e-4 * max(o["normM2"], 1.0)
+    ctx.close()
+
+
 def test_certificate_at_zero_matches_spectral_formula():
     p = synth.gaussian_rpca(m=300, n=120, r=3, k=6, seed=41, lam_l=0.05)
     dev = device()
