@@ -139,3 +139,45 @@ def test_pool_and_upsample_match_oracle(W, H, f, c):
     Up = T.upsample_rows(torch.from_numpy(Pr.astype(np.float32)).to(dev), W, H, f)
     Ur = om.upsample_rows(Pr.astype(np.float32).astype(np.float64), W, H, f)
     assert np.array_equal(Up.cpu().numpy(), Ur.astype(np.float32))
+
+
+def test_warm_start_pipeline_trains_predicts_and_falls_back():
+    """End to end on small frames (64 x 48 px, windows of 20 frames): training
+    windows solved from the cold rSVD start (each certified), Adam on the
+    rotation-invariant product loss (the training loss must fall to under half
+    its initial value), then on windows of an unseen video the start rule (the
+    predicted start is kept only when its objective is below the cold start's)
+    and a certified solve from whichever start is kept, whose objective must
+    agree with the cold-start solve's.  The iteration counts of both starts are
+    printed: the learned start's gain is measured, not asserted."""
+    from paper_1702_02241_amd import warmstart as W
+    dev = device()
+    # k = 8: at k = 5 these windows' optimum has more rank than the factors and the
+    # certificate (correctly) refuses them, rel_gap 0.02-0.2 after every round
+    spec = W.WindowSpec(width=64, height=48, frames=20, stride=5, factor=4, k=8, lam_s=0.05)
+    ws = W.WarmStart(spec, d_h=64, max_batch=16, seed=3, device=dev)
+    videos = [W.video_tensor(spec, 60, seed=s, device=dev) for s in (21, 22)]
+    F, TU, TV, recs = ws.build_dataset(videos)
+    print("[warm pipeline] training solves (video, start, status, iters, certified):",
+          [(r[0], r[1], r[2], r[3], r[4]) for r in recs])
+    assert len(recs) == 18 and all(r[4] == 1 for r in recs)
+    l0 = ws.eval_loss(F, TU, TV, batch=16)
+    ws.train(F, TU, TV, epochs=40, batch=8, lr=1e-3)
+    l1 = ws.eval_loss(F, TU, TV, batch=16)
+    print(f"[warm pipeline] {len(recs)} windows, loss {l0:.4g} -> {l1:.4g}")
+    assert l1 < 0.5 * l0
+    # an unseen scene, and later (partly unseen) frames of a training scene
+    cases = [("unseen scene", W.video_tensor(spec, 40, seed=23, device=dev), [0, 5, 10]),
+             ("same scene, later frames", W.video_tensor(spec, 80, seed=22, device=dev), [45, 55, 60])]
+    for label, held, starts in cases:
+      for t in starts:
+        Xw = held[t:t + spec.frames]
+        start, f_pred, f_cold = ws.start_for(Xw)
+        assert (start is None) == (f_pred >= f_cold)
+        _, info, _, _, _ = ws.solve(Xw, start)
+        _, info_c, _, _, _ = ws.solve(Xw)
+        print(f"[warm pipeline] {label}, window {t}: f(start) predicted {f_pred:.6g} cold {f_cold:.6g} -> "
+              f"{'predicted' if start is not None else 'cold'}; iterations {info.iters} vs cold {info_c.iters}")
+        assert info.certified == 1 and info_c.certified == 1
+        assert abs(info.f - info_c.f) <= 1e-4 * abs(info_c.f)
+    ws.close()
