@@ -165,11 +165,45 @@ int rpca_solve(rpca_ctx* ctx, const float* X, float* U, float* V,
 
 /* Convergence certificate at L = U V^T (Sec. 3.4): T1..T3 from the factor
  * SVD (footnote of Sec. 3.4) and one gradient sweep; T4 by projected block
- * power iteration on P_U^perp D P_V^perp (an estimate from Ritz values, see
- * the design notes); gap bound eq. Fbound.  X, U, V: device.  out: host.
+ * power iteration on P_U^perp D P_V^perp (from Ritz values: exact when the
+ * block holds every singular value above 1, an over-estimate otherwise); gap
+ * bound eq. Fbound.  X, U, V: device.  out: host.
  * Blocks until the result is in `out`. */
 int rpca_certificate(rpca_ctx* ctx, const float* X, const float* U, const float* V,
                      rpca_cert* out, void* stream);
+
+/* Rank-growth direction at L = U V^T (Sec. 4.1, which adds one column to U
+ * and V when the solver stops).  The column is read from the certificate's last
+ * block: (sigma, u, v) is the top singular triplet of P_U^perp D P_V^perp
+ * (D = grad phi(L) / lam_L; v from the certificate's block power iteration, u =
+ * P_U^perp D v / sigma, so u^T D v = sigma).  L is optimal only if sigma <= 1.
+ * When sigma > 1, the factors [U, u_col], [V, v_col] with u_col = sqrt(t) u,
+ * v_col = -sqrt(t) v and t = lam_L (sigma - 1) lower f by at least
+ * lam_L^2 (sigma - 1)^2 / 2 (phi's curvature along the unit-Frobenius u v^T is at
+ * most 1); when sigma <= 1 both columns are zero and t = 0.
+ * X, U, V: device (as rpca_solve).  u_col (m floats), v_col (n floats): device,
+ * written.  sigma, t: host.  Blocks until done.  RPCA_EINVAL on null pointers. */
+int rpca_rank_direction(rpca_ctx* ctx, const float* X, const float* U, const float* V,
+                        float* u_col, float* v_col, double* sigma, double* t, void* stream);
+
+/* rpca_solve with the rank grown on demand (Sec. 4.1): start at rank k0; below
+ * k_max each rank is solved without certification rounds and then certified
+ * once: certified -> done; not certified and the growth direction
+ * (rpca_rank_direction) has sigma > 1 -> append that column pair and continue
+ * from the grown factors at rank k + 1; otherwise (and at k_max) the solve
+ * continues with certification rounds as rpca_solve.  Each rank uses its own
+ * context (made and destroyed inside); the call blocks until done.  m, n,
+ * lam_S, lam_L, mask: as rpca_create; 1 <= k0 <= k_max <= 32, k_max <=
+ * min(m, n).  X: device.  U, V: device buffers of m * k_max and n * k_max
+ * floats; in: the start at rank k0 (the first m * k0 and n * k0 floats,
+ * row-major; ignored with RPCA_INIT_RSVD), out: the solution at rank *k_out
+ * (the first m * k_out and n * k_out floats).  opts as rpca_solve (certify is
+ * forced on).  info: status, f, gradient and certificate of the last rank;
+ * iters, evals and cert_rounds summed over all ranks.  Returns that status
+ * (RPCA_EINVAL on bad arguments before any HIP call). */
+int rpca_solve_grow(int64_t m, int64_t n, int32_t k0, int32_t k_max, double lam_S, double lam_L,
+                    const uint8_t* mask, const float* X, float* U, float* V, int32_t* k_out,
+                    const rpca_opts* opts, rpca_info* info, void* stream);
 
 /* Randomized-SVD start (Sec. 4.2): U0 = U_k S_k^{1/2}, V0 = V_k S_k^{1/2} from
  * the sketch Y = P_Omega(X) Omega_s, q power steps, B = Q^T P_Omega(X).

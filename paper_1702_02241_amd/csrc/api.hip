@@ -741,3 +741,106 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   }
   return rpca::solve_finish(c, X, U, V, o, final_bf16, phases[nph - 1].gtol, iters_bf16, t0, info, s);
 }
+
+// Rank grown on demand (Sec. 4.1): one context per rank.  Below k_max a rank is
+// solved without certification rounds, then one certificate decides: certified
+// -> done; growth column with sigma > 1 -> widen the factors in place and go on
+// at k + 1; otherwise the full certified solve continues at this rank.
+extern "C" int rpca_solve_grow(int64_t m, int64_t n, int32_t k0, int32_t k_max, double lam_s, double lam_l,
+                               const uint8_t* mask, const float* X, float* U, float* V, int32_t* k_out,
+                               const rpca_opts* opts, rpca_info* info, void* stream) {
+  if (!X || !U || !V || !k_out) return RPCA_EINVAL;
+  if (k0 < 1 || k_max < k0 || k_max > 32 || k_max > m || k_max > n) return RPCA_EINVAL;
+  rpca_opts o;
+  if (opts) o = *opts;
+  else rpca_default_opts(&o);
+  o.certify = 1;
+  if (!rpca::valid_opts(o)) return RPCA_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  // staging for the widened factors and the column pair
+  float* stage = nullptr;
+  const size_t wide = (size_t)(m + n) * (size_t)k_max, cols = (size_t)(m + n);
+  if (k_max > k0 && hipMalloc(&stage, (wide + cols) * sizeof(float)) != hipSuccess) return RPCA_ENOMEM;
+  int k = k0, rc = RPCA_OK;
+  int32_t iters = 0, evals = 0, iters_bf16 = 0, rounds = 0;
+  rpca_info last{};
+  auto tally = [&] {
+    iters += last.iters;
+    evals += last.evals;
+    iters_bf16 += last.iters_bf16;
+    rounds += last.cert_rounds;
+  };
+  for (;;) {
+    rpca_ctx* c = nullptr;
+    if ((rc = rpca_create(m, n, k, lam_s, lam_l, mask, &c))) break;
+    if (k == k_max) {
+      rc = rpca_solve(c, X, U, V, &o, &last, stream);
+      if (rc >= 0) tally();
+      rpca_destroy(c);
+      break;
+    }
+    rpca_opts quick = o;
+    quick.certify = 0;
+    rc = rpca_solve(c, X, U, V, &quick, &last, stream);
+    if (rc >= 0) tally();
+    if (rc < 0 || rc == RPCA_ENOTCONV) {
+      rpca_destroy(c);
+      break;
+    }
+    rpca_cert cert;
+    double sigma = 0.0, t = 0.0;
+    float* Ug = stage;
+    float* Vg = stage + (size_t)m * (k + 1);
+    float* ucol = stage + wide;
+    float* vcol = ucol + m;
+    rc = rpca::growth_direction_impl(c, X, U, V, ucol, vcol, &sigma, &t, s, &cert);
+    if (rc) {
+      rpca_destroy(c);
+      break;
+    }
+    ++rounds;
+    if (cert.rel_gap <= o.cert_tol) {  // certified at this rank
+      rpca_destroy(c);
+      last.status = rc = RPCA_OK;
+      last.certified = 1;
+      last.rel_gap = cert.rel_gap;
+      break;
+    }
+    if (!(sigma > 1.0)) {  // no descent column: the gap is not from the rank bound
+      rpca_opts more = o;
+      more.init = RPCA_INIT_GIVEN;
+      rc = rpca_solve(c, X, U, V, &more, &last, stream);
+      if (rc >= 0) tally();
+      rpca_destroy(c);
+      break;
+    }
+    rpca_destroy(c);
+    const size_t f4 = sizeof(float), wk = (size_t)k * f4, wk1 = (size_t)(k + 1) * f4;
+    if (hipMemcpy2DAsync(Ug, wk1, U, wk, wk, (size_t)m, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpy2DAsync(Ug + k, wk1, ucol, f4, f4, (size_t)m, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpy2DAsync(Vg, wk1, V, wk, wk, (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpy2DAsync(Vg + k, wk1, vcol, f4, f4, (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(U, Ug, (size_t)m * wk1, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(V, Vg, (size_t)n * wk1, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      rc = RPCA_EHIP;
+      break;
+    }
+    ++k;
+    o.init = RPCA_INIT_GIVEN;
+  }
+  if (stage) {
+    if (hipStreamSynchronize(s) != hipSuccess && rc >= 0) rc = RPCA_EHIP;
+    (void)hipFree(stage);
+  }
+  *k_out = k;
+  if (info && rc >= 0) {
+    *info = last;
+    info->iters = iters;
+    info->evals = evals;
+    info->iters_bf16 = iters_bf16;
+    info->cert_rounds = rounds;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
+}

@@ -852,7 +852,7 @@ namespace rpca {
 // iteration already put rel_gap above quick_tol the power iteration is skipped
 // (T4 = 0 then, rel_gap is the lower bound it gives, certified = 0).
 int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V, rpca_cert* out,
-                     double quick_tol, hipStream_t s) {
+                     double quick_tol, hipStream_t s, CertExtra* extra) {
   const rpca::CtxView cv = rpca::ctx_view(c);
   const int64_t m = cv.m, n = cv.n;
   const int k = cv.k;
@@ -1118,6 +1118,14 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
       }
       const double d0 = fabs(ritz[0] - prev[0]);
       for (int p = 0; p < b; ++p) prev[p] = ritz[p];
+      if (extra) {  // the top Ritz vector of this step: X w_0
+        extra->v.assign((size_t)n, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+          double sacc = 0.0;
+          for (int q = 0; q < b; ++q) sacc += Xb[(size_t)i * b + q] * HW[(size_t)q * b + 0];
+          extra->v[(size_t)i] = sacc;
+        }
+      }
       Xb = Zb;
       orth_host(Xb, b);
       const bool all_conv = dmax <= 1e-8 * std::max(ritz[0], 1e-300);
@@ -1190,6 +1198,78 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   out->power_iters = it;
   out->block = b;
   out->certified = out->rel_gap <= 1e-3;
+  if (extra) {
+    extra->r = r;
+    extra->TU = TU;
+  }
+  return RPCA_OK;
+}
+
+// Rank-growth direction (Sec. 4.1, read through the certificate's last block):
+// the top Ritz vector v of M^T M from the certificate's power iteration, then
+// u = P_U^perp D v / ||P_U^perp D v|| with sigma = ||P_U^perp D v|| (so u^T D v =
+// sigma).  When sigma > 1 the column pair (sqrt(t) u, -sqrt(t) v) with t =
+// lam_L (sigma - 1) lowers f by at least lam_L^2 (sigma - 1)^2 / 2 (phi's curvature
+// along the unit-norm u v^T is at most 1); otherwise the columns are zero.
+int growth_direction_impl(rpca_ctx* c, const float* X, const float* U, const float* V, float* u_col,
+                          float* v_col, double* sigma_out, double* t_out, hipStream_t s, rpca_cert* cert_out) {
+  const rpca::CtxView cv = rpca::ctx_view(c);
+  const int64_t m = cv.m, n = cv.n;
+  const int k = cv.k;
+  const double lam_l = cv.lam_l;
+  rpca_cert cert;
+  CertExtra ex;
+  int rc = certificate_impl(c, X, U, V, &cert, 0.0, s, &ex);
+  if (rc < 0) return rc;
+  if (cert_out) *cert_out = cert;
+  Workspace ws;
+  if ((rc = get_workspace(c, &ws, s))) return rc;
+  double sigma = 0.0;
+  std::vector<double> u((size_t)m, 0.0);
+  if (!ex.v.empty()) {
+    // y = D v = G v / lam_L (one left product, b = 1)
+    if (hipMemcpyAsync(ws.Wd, ex.v.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, 1, ws.Yd, 1, 1, s) != hipSuccess) return RPCA_EHIP;
+    std::vector<double> y((size_t)m);
+    std::vector<float> Uh((size_t)m * k);
+    if (hipMemcpyAsync(y.data(), ws.Yd, (size_t)m * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(Uh.data(), U, (size_t)m * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return RPCA_EHIP;
+    for (auto& x : y) x /= lam_l;
+    // P_U^perp y = y - U1 (U1^T y), U1 = U T_U (m x r)
+    const int r = ex.r;
+    if (r) {
+      std::vector<double> Uty((size_t)k, 0.0), coef((size_t)r, 0.0), back((size_t)k, 0.0);
+      for (int64_t i = 0; i < m; ++i)
+        for (int j = 0; j < k; ++j) Uty[(size_t)j] += (double)Uh[(size_t)i * k + j] * y[(size_t)i];
+      for (int q = 0; q < r; ++q)
+        for (int j = 0; j < k; ++j) coef[(size_t)q] += ex.TU[(size_t)j * r + q] * Uty[(size_t)j];
+      for (int j = 0; j < k; ++j)
+        for (int q = 0; q < r; ++q) back[(size_t)j] += ex.TU[(size_t)j * r + q] * coef[(size_t)q];
+      for (int64_t i = 0; i < m; ++i) {
+        double sacc = 0.0;
+        for (int j = 0; j < k; ++j) sacc += (double)Uh[(size_t)i * k + j] * back[(size_t)j];
+        y[(size_t)i] -= sacc;
+      }
+    }
+    double nn = 0.0;
+    for (double x : y) nn += x * x;
+    sigma = sqrt(nn);
+    if (sigma > 0)
+      for (int64_t i = 0; i < m; ++i) u[(size_t)i] = y[(size_t)i] / sigma;
+  }
+  const double t = sigma > 1.0 ? lam_l * (sigma - 1.0) : 0.0;
+  const double st = sqrt(t);
+  std::vector<float> uc((size_t)m), vc((size_t)n);
+  for (int64_t i = 0; i < m; ++i) uc[(size_t)i] = (float)(st * u[(size_t)i]);
+  for (int64_t j = 0; j < n; ++j) vc[(size_t)j] = ex.v.empty() ? 0.f : (float)(-st * ex.v[(size_t)j]);
+  if (hipMemcpyAsync(u_col, uc.data(), (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(v_col, vc.data(), (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)  // the host sources die with this frame
+    return RPCA_EHIP;
+  *sigma_out = sigma;
+  *t_out = t;
   return RPCA_OK;
 }
 
@@ -1198,7 +1278,13 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
 extern "C" int rpca_certificate(rpca_ctx* c, const float* X, const float* U, const float* V,
                                 rpca_cert* out, void* stream) {
   if (!c || !X || !U || !V || !out) return RPCA_EINVAL;
-  return rpca::certificate_impl(c, X, U, V, out, 0.0, (hipStream_t)stream);
+  return rpca::certificate_impl(c, X, U, V, out, 0.0, (hipStream_t)stream, nullptr);
+}
+
+extern "C" int rpca_rank_direction(rpca_ctx* c, const float* X, const float* U, const float* V, float* u_col,
+                                   float* v_col, double* sigma, double* t, void* stream) {
+  if (!c || !X || !U || !V || !u_col || !v_col || !sigma || !t) return RPCA_EINVAL;
+  return rpca::growth_direction_impl(c, X, U, V, u_col, v_col, sigma, t, (hipStream_t)stream);
 }
 
 extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s, int32_t oversample,

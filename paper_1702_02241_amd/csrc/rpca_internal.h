@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <chrono>
+#include <vector>
 
 #include "../../include/rpca.h"
 
@@ -220,8 +221,19 @@ struct CtxView {
   const void** phi0_X;   // the X it belongs to
 };
 CtxView ctx_view(rpca_ctx* c);
+// Optional outputs of the certificate's power iteration: the top Ritz vector v of
+// M^T M (n values, P_V^perp-projected, unit norm) and the k x r map T_U with
+// U1 = U T_U (the left singular vectors of L).
+struct CertExtra {
+  std::vector<double> v;
+  std::vector<double> TU;
+  int r = 0;
+};
 int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V, rpca_cert* out,
-                     double quick_tol, hipStream_t s);
+                     double quick_tol, hipStream_t s, CertExtra* extra = nullptr);
+int growth_direction_impl(rpca_ctx* c, const float* X, const float* U, const float* V, float* u_col,
+                          float* v_col, double* sigma, double* t, hipStream_t s,
+                          rpca_cert* cert_out = nullptr);
 int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V, double* f_dev,
                     double* aux_dev, float* gU, float* gV, hipStream_t s);
 // Device workspace owned by the context, grown on demand; *fresh = 1 when newly allocated.

@@ -104,6 +104,9 @@ def lib():
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_certificate": (I32, [P, P, P, P, ctypes.POINTER(rpca_cert), P]),
+            "rpca_rank_direction": (I32, [P, P, P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D), P]),
+            "rpca_solve_grow": (I32, [I64, I64, I32, I32, D, D, P, P, P, P, ctypes.POINTER(I32),
+                                      ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_init_rsvd": (I32, [P, P, P, I32, I32, U64, P, P, P]),
             "rpca_destroy": (None, [P]),
             "rpca_status_string": (ctypes.c_char_p, [I32]),
@@ -185,6 +188,33 @@ def rpca_certificate(ctx, X, U, V, stream=0):
     cert = rpca_cert()
     rc = lib().rpca_certificate(ctx, X, U, V, ctypes.byref(cert), stream)
     return rc, cert
+
+
+def rpca_rank_direction(ctx, X, U, V, u_col, v_col, stream=0):
+    """Growth column pair (device u_col: m, v_col: n floats).  Returns
+    (status, sigma, t)."""
+    sigma, t = ctypes.c_double(), ctypes.c_double()
+    rc = lib().rpca_rank_direction(ctx, X, U, V, u_col, v_col, ctypes.byref(sigma), ctypes.byref(t), stream)
+    return rc, sigma.value, t.value
+
+
+def rpca_solve_grow(m, n, k0, k_max, lam_s, lam_l, mask, X, U, V, opts=None, stream=0):
+    """Solve with the rank grown on demand.  mask: None or host array (as
+    rpca_create).  U, V: device buffers of m*k_max, n*k_max floats.  Returns
+    (status, k, info)."""
+    info = rpca_info()
+    k = ctypes.c_int32()
+    mptr = None
+    keep = None
+    if mask is not None:
+        import numpy as np
+        keep = np.asfortranarray(np.asarray(mask) != 0, dtype=np.uint8)
+        mptr = keep.ctypes.data
+    rc = lib().rpca_solve_grow(m, n, k0, k_max, lam_s, lam_l, mptr, X, U, V, ctypes.byref(k),
+                               ctypes.byref(opts) if opts is not None else None, ctypes.byref(info),
+                               stream)
+    del keep
+    return rc, k.value, info
 
 
 def rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream=0):

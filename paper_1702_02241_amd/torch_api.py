@@ -69,6 +69,16 @@ class Context:
             raise RuntimeError(f"rpca_certificate failed: {R.rpca_status_string(rc)}")
         return cert
 
+    def rank_direction(self, Xcm, U, V):
+        """Growth column pair at L = U V^T: (sigma, t, u_col (m,), v_col (n,))."""
+        u_col = torch.empty(self.m, dtype=torch.float32, device=U.device)
+        v_col = torch.empty(self.n, dtype=torch.float32, device=U.device)
+        rc, sigma, t = R.rpca_rank_direction(self.ctx, Xcm.data_ptr(), U.data_ptr(), V.data_ptr(),
+                                             u_col.data_ptr(), v_col.data_ptr(), _stream())
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_rank_direction failed: {R.rpca_status_string(rc)}")
+        return sigma, t, u_col, v_col
+
     def init_rsvd(self, Xcm, Omega=None, oversample=10, power_steps=2, seed=12345):
         U = torch.empty(self.m, self.k, dtype=torch.float32, device=Xcm.device)
         V = torch.empty(self.n, self.k, dtype=torch.float32, device=Xcm.device)
@@ -80,6 +90,27 @@ class Context:
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_init_rsvd failed: {R.rpca_status_string(rc)}")
         return U, V
+
+
+def solve_grow(Xcm, m, n, k0, k_max, lam_s, lam_l, mask=None, U0=None, V0=None, **opts):
+    """Solve with the rank grown from k0 up to k_max on demand (rpca_solve_grow).
+    U0, V0: (m, k0), (n, k0) start, or None for the randomized-SVD start.
+    Returns (status, info, U (m, k), V (n, k))."""
+    o = R.default_opts()
+    for key, val in opts.items():
+        setattr(o, key, val)
+    Ub = torch.zeros(m * k_max, dtype=torch.float32, device=Xcm.device)
+    Vb = torch.zeros(n * k_max, dtype=torch.float32, device=Xcm.device)
+    if U0 is None:
+        o.init = R.RPCA_INIT_RSVD
+    else:
+        Ub[: m * k0].copy_(U0.reshape(-1))
+        Vb[: n * k0].copy_(V0.reshape(-1))
+    rc, k, info = R.rpca_solve_grow(m, n, k0, k_max, lam_s, lam_l, mask, Xcm.data_ptr(), Ub.data_ptr(),
+                                    Vb.data_ptr(), o, _stream())
+    if rc < 0:
+        raise RuntimeError(f"rpca_solve_grow failed: {R.rpca_status_string(rc)}")
+    return rc, info, Ub[: m * k].view(m, k), Vb[: n * k].view(n, k)
 
 
 class WarmNet:

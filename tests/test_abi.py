@@ -64,7 +64,22 @@ def test_null_context_rejected():
     assert rc == R.RPCA_EINVAL
     rc, _ = R.rpca_certificate(None, 1, 1, 1)
     assert rc == R.RPCA_EINVAL
+    assert R.rpca_rank_direction(None, 1, 1, 1, 1, 1)[0] == R.RPCA_EINVAL
     R.rpca_destroy(None)
+
+
+@pytest.mark.parametrize("k0,k_max,m,n", [(0, 4, 50, 40), (5, 4, 50, 40), (2, 33, 64, 64),
+                                          (2, 6, 5, 40), (2, 6, 50, 5)])
+def test_solve_grow_rejects_bad_ranks_before_hip(k0, k_max, m, n):
+    rc, k, _ = R.rpca_solve_grow(m, n, k0, k_max, 0.1, 1.0, None, 1, 1, 1)
+    assert rc == R.RPCA_EINVAL
+
+
+def test_solve_grow_rejects_null_buffers_and_bad_opts():
+    assert R.rpca_solve_grow(50, 40, 2, 4, 0.1, 1.0, None, None, 1, 1)[0] == R.RPCA_EINVAL
+    o = R.default_opts()
+    o.mem = 0
+    assert R.rpca_solve_grow(50, 40, 2, 4, 0.1, 1.0, None, 1, 1, 1, o)[0] == R.RPCA_EINVAL
 
 
 def test_status_strings():
