@@ -1,0 +1,726 @@
+// Frank-Wolfe with the sparse part marginalised (Sec. 6.2, Alg. 1).  The
+// iteration and its quantities are defined in rpca_fw.h.
+//
+// Every kernel here streams m x n FP32 matrices (L, X, G) from HBM with no
+// reuse worth a matrix core, so the roofline is HBM bandwidth.  Layout follows
+// X: column-major, column j contiguous, 16-byte vector accesses when m is a
+// multiple of 4 and the buffers are 16-byte aligned.  Per iteration:
+//   linear minimisation: block power iteration on G^T G with a block of BLK
+//     vectors and Rayleigh-Ritz (FP64, host) after every step: Y = G Xb
+//     (column chunks -> partial Y, fixed-order sum), Z = G^T Y (row chunks x a
+//     few columns -> FP64 partials, fixed-order sum); it stops when the top Ritz
+//     pair's residual is small, and its Ritz block starts the next iteration;
+//   bilinear pass (when the vertex is nonzero): u^T P_Omega(L) v and
+//     sum_Omega u_i^2 v_j^2 with u = y / sigma, y = G v;
+//   update pass: L <- a L + b y v^T, G = P_Omega(clip(L - X)), and FP64 sums of
+//     phi(L), <G, L>, sum_Omega L^2 (per-block partials, fixed-order total).
+// Every reduction has a fixed order, so results are reproducible run to run.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "rpca.h"
+#include "rpca_fw.h"
+#include "smalllinalg.h"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int TH = 256;         // threads per block of the streaming kernels
+constexpr int BLK = 8;          // vectors in the power-iteration block
+constexpr int LEFT_COLS = 32;   // columns per block of Y = G Xb
+constexpr int RIGHT_COLS = 4;   // columns per block of Z = G^T Y
+constexpr int RIGHT_ITER = 4;   // row groups per thread in Z = G^T Y
+constexpr int COL_ITER = 8;     // row groups per thread in the bilinear pass
+constexpr int FIN_TH = 1024;    // threads of the single-block finishing kernels
+constexpr int POWER_MAX = 100;  // power steps per iteration at most
+constexpr double POWER_TOL = 1e-4;  // default bound on the top Ritz pair's relative residual
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sums of Q values (fixed order); thread 0 gets them in out[].
+template <int Q, int NT>
+__device__ __forceinline__ void block_sums(double (&v)[Q], double* out) {
+  __shared__ double red[Q][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    v[q] = wave_sum(v[q]);
+    if (lane == 0) red[q][w] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += red[q][i];
+      out[q] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ f4 load4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+__device__ __forceinline__ void store4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+
+// Observation bits of rows i .. i+VEC-1 of column j (all ones without a mask).
+template <int VEC, bool MASK>
+__device__ __forceinline__ unsigned obs_bits(const uint32_t* mask, int mw, int64_t j, int64_t i) {
+  if (!MASK) return (1u << VEC) - 1u;
+  return (mask[j * mw + (i >> 5)] >> (unsigned)(i & 31)) & ((1u << VEC) - 1u);
+}
+
+// L <- a L + b y_i v_j;  G = P_Omega(clip(L - X));  block partials of
+// phi(L), <G, L>, sum_Omega L^2.  Block b covers rows (b % rb) * TH * VEC ... of
+// column b / rb.
+template <int VEC, bool MASK>
+__global__ __launch_bounds__(TH) void k_fw_update(float* __restrict__ L, const float* __restrict__ X,
+                                                  const uint32_t* __restrict__ mask, int mw, int64_t m,
+                                                  int64_t rb, float a, float b, const float* __restrict__ y,
+                                                  const float* __restrict__ v, float lam_s,
+                                                  float* __restrict__ G, double* __restrict__ part) {
+  const int64_t blk = blockIdx.x;
+  const int64_t j = blk / rb;
+  const int64_t i0 = (blk % rb) * (TH * VEC) + (int64_t)threadIdx.x * VEC;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (i0 < m) {
+    const float bv = b != 0.f ? b * v[j] : 0.f;
+    const int64_t off = j * m + i0;
+    float l[VEC], x[VEC], yy[VEC];
+    if (VEC == 4) {
+      const f4 lv = load4(L + off), xv = load4(X + off);
+      const f4 yv = bv != 0.f ? load4(y + i0) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        l[c] = lv[c];
+        x[c] = xv[c];
+        yy[c] = yv[c];
+      }
+    } else {
+      l[0] = L[off];
+      x[0] = X[off];
+      yy[0] = bv != 0.f ? y[i0] : 0.f;
+    }
+    const unsigned bits = obs_bits<VEC, MASK>(mask, mw, j, i0);
+    float g[VEC];
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) {
+      l[c] = fmaf(bv, yy[c], a * l[c]);
+      const float r = l[c] - x[c];
+      const bool o = (bits >> c) & 1u;
+      const float gc = fminf(fmaxf(r, -lam_s), lam_s);
+      g[c] = o ? gc : 0.f;
+      if (o) {
+        s[0] += (double)(gc * (r - 0.5f * gc));
+        s[1] += (double)gc * (double)l[c];
+        s[2] += (double)l[c] * (double)l[c];
+      }
+    }
+    if (VEC == 4) {
+      store4(L + off, f4{l[0], l[1], l[2], l[3]});
+      store4(G + off, f4{g[0], g[1], g[2], g[3]});
+    } else {
+      L[off] = l[0];
+      G[off] = g[0];
+    }
+  }
+  block_sums<3, TH>(s, part + blk * 3);
+}
+
+// Fixed-order total of Q-wide block partials into res[0..Q).
+template <int Q>
+__global__ __launch_bounds__(FIN_TH) void k_sum_parts(const double* __restrict__ part, int64_t nblocks,
+                                                      double* __restrict__ res) {
+  double s[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) s[q] = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += FIN_TH)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] += part[b * Q + q];
+  block_sums<Q, FIN_TH>(s, res);
+}
+
+// Partial Y over a chunk of LEFT_COLS columns: ypart[(cc m + i) BLK + q] =
+// sum_{j in chunk cc} G_ij Xb[j BLK + q].
+template <int VEC>
+__global__ __launch_bounds__(TH) void k_fw_left(const float* __restrict__ G, const float* __restrict__ Xb, int64_t m,
+                                                int64_t n, int64_t rb, float* __restrict__ ypart) {
+  const int64_t blk = blockIdx.x;
+  const int64_t cc = blk / rb;
+  const int64_t i0 = (blk % rb) * (TH * VEC) + (int64_t)threadIdx.x * VEC;
+  if (i0 >= m) return;
+  const int64_t j0 = cc * LEFT_COLS;
+  const int ncol = (int)(n - j0 < LEFT_COLS ? n - j0 : LEFT_COLS);
+  float acc[VEC][BLK];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c)
+#pragma unroll
+    for (int q = 0; q < BLK; ++q) acc[c][q] = 0.f;
+#pragma unroll 8
+  for (int t = 0; t < ncol; ++t) {
+    const int64_t off = (j0 + t) * m + i0;
+    float g[VEC];
+    if (VEC == 4) {
+      const f4 v = load4(G + off);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) g[c] = v[c];
+    } else {
+      g[0] = G[off];
+    }
+    const float* xr = Xb + (j0 + t) * BLK;
+#pragma unroll
+    for (int q = 0; q < BLK; ++q) {
+      const float xq = xr[q];
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c][q] = fmaf(g[c], xq, acc[c][q]);
+    }
+  }
+  float* out = ypart + (cc * m + i0) * BLK;
+#pragma unroll
+  for (int c = 0; c < VEC; ++c)
+#pragma unroll
+    for (int q = 0; q < BLK; q += 4) store4(out + c * BLK + q, f4{acc[c][q], acc[c][q + 1], acc[c][q + 2], acc[c][q + 3]});
+}
+
+// Y[i BLK + q] = sum over column chunks of ypart (fixed order).
+__global__ __launch_bounds__(TH) void k_fw_left_finish(const float* __restrict__ ypart, int64_t nchunks, int64_t mb,
+                                                       float* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * TH + threadIdx.x;
+  if (e >= mb) return;
+  float s = 0.f;
+  for (int64_t c = 0; c < nchunks; ++c) s += ypart[c * mb + e];
+  Y[e] = s;
+}
+
+// Partial Z over a chunk of rows and RIGHT_COLS columns: part[((rc_i n) + j) BLK + q]
+// = sum_{i in chunk} G_ij Y[i BLK + q] (FP32 per thread, FP64 across the block).
+template <int VEC>
+__global__ __launch_bounds__(TH) void k_fw_right(const float* __restrict__ G, const float* __restrict__ Y, int64_t m,
+                                                 int64_t n, int64_t ncb, double* __restrict__ part) {
+  const int64_t blk = blockIdx.x;
+  const int64_t rci = blk / ncb;
+  const int64_t j0 = (blk % ncb) * RIGHT_COLS;
+  const int64_t base = rci * (int64_t)(TH * VEC * RIGHT_ITER);
+  float s[RIGHT_COLS][BLK];
+#pragma unroll
+  for (int c = 0; c < RIGHT_COLS; ++c)
+#pragma unroll
+    for (int q = 0; q < BLK; ++q) s[c][q] = 0.f;
+#pragma unroll
+  for (int it = 0; it < RIGHT_ITER; ++it) {
+    const int64_t i0 = base + (int64_t)it * TH * VEC + (int64_t)threadIdx.x * VEC;
+    if (i0 < m) {
+      float y[VEC][BLK];
+#pragma unroll
+      for (int r = 0; r < VEC; ++r)
+#pragma unroll
+        for (int q = 0; q < BLK; q += 4) {
+          const f4 v = load4(Y + (i0 + r) * BLK + q);
+          y[r][q] = v[0];
+          y[r][q + 1] = v[1];
+          y[r][q + 2] = v[2];
+          y[r][q + 3] = v[3];
+        }
+#pragma unroll
+      for (int c = 0; c < RIGHT_COLS; ++c) {
+        if (j0 + c < n) {
+          float g[VEC];
+          if (VEC == 4) {
+            const f4 v = load4(G + (j0 + c) * m + i0);
+#pragma unroll
+            for (int r = 0; r < VEC; ++r) g[r] = v[r];
+          } else {
+            g[0] = G[(j0 + c) * m + i0];
+          }
+#pragma unroll
+          for (int r = 0; r < VEC; ++r)
+#pragma unroll
+            for (int q = 0; q < BLK; ++q) s[c][q] = fmaf(g[r], y[r][q], s[c][q]);
+        }
+      }
+    }
+  }
+  // block totals: FP32 within each wave, FP64 across the four waves
+  __shared__ double red[RIGHT_COLS * BLK][TH / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < RIGHT_COLS; ++c)
+#pragma unroll
+    for (int q = 0; q < BLK; ++q) {
+      float v = s[c][q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[c * BLK + q][w] = (double)v;
+    }
+  __syncthreads();
+  if (threadIdx.x < RIGHT_COLS * BLK) {
+    const int c = threadIdx.x / BLK, q = threadIdx.x % BLK;
+    if (j0 + c < n) {
+      double t = 0.0;
+      for (int i = 0; i < TH / 64; ++i) t += red[threadIdx.x][i];
+      part[(rci * n + j0 + c) * BLK + q] = t;
+    }
+  }
+}
+
+// Z[j BLK + q] = sum over row chunks of the partials (fixed order).
+__global__ __launch_bounds__(TH) void k_fw_right_finish(const double* __restrict__ part, int64_t rc, int64_t nb,
+                                                        double* __restrict__ Z) {
+  const int64_t e = (int64_t)blockIdx.x * TH + threadIdx.x;
+  if (e >= nb) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rc; ++r) s += part[r * nb + e];
+  Z[e] = s;
+}
+
+struct Coef {
+  float w[BLK];
+};
+
+// y_i = sum_q Y[i BLK + q] w_q  (G v for v = Xb w).
+__global__ __launch_bounds__(TH) void k_fw_combine(const float* __restrict__ Y, Coef w, int64_t m,
+                                                   float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * TH + threadIdx.x;
+  if (i >= m) return;
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < BLK; ++q) s = fmaf(Y[i * BLK + q], w.w[q], s);
+  y[i] = s;
+}
+
+// Bilinear pass over a chunk of rows of column j (observed entries only):
+// part[0] = sum_i A_ij u_i, part[1] = sum_i u_i^2, u_i = ws w_i.
+template <int VEC, bool MASK>
+__global__ __launch_bounds__(TH) void k_fw_bilinear(const float* __restrict__ A, const float* __restrict__ w, float ws,
+                                                    const uint32_t* __restrict__ mask, int mw, int64_t m, int64_t rc,
+                                                    double* __restrict__ part) {
+  const int64_t blk = blockIdx.x;
+  const int64_t j = blk / rc;
+  const int64_t base = (blk % rc) * (int64_t)(TH * VEC * COL_ITER);
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int it = 0; it < COL_ITER; ++it) {
+    const int64_t i0 = base + (int64_t)it * TH * VEC + (int64_t)threadIdx.x * VEC;
+    if (i0 < m) {
+      float av[VEC], wv[VEC];
+      if (VEC == 4) {
+        const f4 qa = load4(A + j * m + i0), qw = load4(w + i0);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+          av[c] = qa[c];
+          wv[c] = qw[c];
+        }
+      } else {
+        av[0] = A[j * m + i0];
+        wv[0] = w[i0];
+      }
+      const unsigned bits = obs_bits<VEC, MASK>(mask, mw, j, i0);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        if ((bits >> c) & 1u) {
+          const float u = ws * wv[c];
+          s0 = fmaf(av[c], u, s0);
+          s1 = fmaf(u, u, s1);
+        }
+      }
+    }
+  }
+  double s[2] = {(double)s0, (double)s1};
+  block_sums<2, TH>(s, part + blk * 2);
+}
+
+// One block: res[2] = sum_j v_j p0_j, res[3] = sum_j v_j^2 p1_j over the
+// bilinear partials.
+__global__ __launch_bounds__(FIN_TH) void k_fw_bilinear_finish(const double* __restrict__ part, int64_t rc, int64_t n,
+                                                               const float* __restrict__ v, double* __restrict__ res) {
+  double s[2] = {0.0, 0.0};
+  for (int64_t j = threadIdx.x; j < n; j += FIN_TH) {
+    double p0 = 0.0, p1 = 0.0;
+    for (int64_t r = 0; r < rc; ++r) {
+      p0 += part[(j * rc + r) * 2];
+      p1 += part[(j * rc + r) * 2 + 1];
+    }
+    const double vj = (double)v[j];
+    s[0] += vj * p0;
+    s[1] += vj * vj * p1;
+  }
+  block_sums<2, FIN_TH>(s, res + 2);
+}
+
+// Deterministic start entries of the power-iteration block (SplitMix64 hash of
+// the index, centred; Steele, Lea & Flood 2014).
+double start_entry(uint64_t j) {
+  uint64_t z = j + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+}  // namespace
+
+struct rpca_fw {
+  int64_t m = 0, n = 0;
+  double lam_s = 0, lam_l = 0;
+  int mw = 0;
+  int vec = 1;
+  int b = BLK;                  // live block columns: min(BLK, n)
+  uint32_t* mask = nullptr;
+  float* G = nullptr;           // m x n
+  float* ypart = nullptr;       // left-product chunks x m x BLK
+  float* Y = nullptr;           // m x BLK
+  float* y = nullptr;           // m: G v
+  float* Xb = nullptr;          // n x BLK (orthonormal first b columns, zero padding)
+  float* v = nullptr;           // n: right singular vector
+  double* part = nullptr;       // block partials
+  double* Z = nullptr;          // n x BLK
+  double* res = nullptr;        // small device results
+  double* res_host = nullptr;   // pinned copy
+  std::vector<double> Xh;       // host copy of the block (FP64)
+  int64_t rb_upd = 0, nchunks_left = 0, rc_right = 0, rc_bil = 0;
+  bool x_valid = false;
+};
+
+namespace {
+
+void fw_free(rpca_fw* h) {
+  for (void* p : {(void*)h->mask, (void*)h->G, (void*)h->ypart, (void*)h->Y, (void*)h->y, (void*)h->Xb, (void*)h->v,
+                  (void*)h->part, (void*)h->Z, (void*)h->res})
+    if (p) (void)hipFree(p);
+  if (h->res_host) (void)hipHostFree(h->res_host);
+  delete h;
+}
+
+#define FWCHK(expr)                             \
+  do {                                          \
+    if ((expr) != hipSuccess) return RPCA_EHIP; \
+  } while (0)
+
+// L <- a L + b y v^T, G and the three sums into res[4..6] (host copy on return).
+int fw_update(rpca_fw* h, const float* X, float* L, float a, float b, hipStream_t s) {
+  const int64_t blocks = h->rb_upd * h->n;
+  const float ls = (float)h->lam_s;
+  if (h->vec == 4) {
+    if (h->mask)
+      hipLaunchKernelGGL((k_fw_update<4, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+    else
+      hipLaunchKernelGGL((k_fw_update<4, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+  } else {
+    if (h->mask)
+      hipLaunchKernelGGL((k_fw_update<1, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+    else
+      hipLaunchKernelGGL((k_fw_update<1, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+  }
+  FWCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts<3>, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, blocks, h->res + 4);
+  FWCHK(hipGetLastError());
+  FWCHK(hipMemcpyAsync(h->res_host + 4, h->res + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FWCHK(hipStreamSynchronize(s));
+  return RPCA_OK;
+}
+
+// Orthonormalise the first b columns of the n x BLK row-major block (modified
+// Gram-Schmidt, twice); a column that vanishes is replaced by hashed entries
+// (salt) and orthogonalised again, or left zero.
+void orth_block(std::vector<double>& Xh, int64_t n, int b, uint64_t salt) {
+  for (int q = 0; q < b; ++q) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      double before = 0.0;
+      for (int64_t j = 0; j < n; ++j) before += Xh[(size_t)j * BLK + q] * Xh[(size_t)j * BLK + q];
+      for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < q; ++p) {
+          double d = 0.0;
+          for (int64_t j = 0; j < n; ++j) d += Xh[(size_t)j * BLK + p] * Xh[(size_t)j * BLK + q];
+          for (int64_t j = 0; j < n; ++j) Xh[(size_t)j * BLK + q] -= d * Xh[(size_t)j * BLK + p];
+        }
+      double nn = 0.0;
+      for (int64_t j = 0; j < n; ++j) nn += Xh[(size_t)j * BLK + q] * Xh[(size_t)j * BLK + q];
+      if (nn > 1e-20 * before && nn > 0.0) {
+        const double inv = 1.0 / sqrt(nn);
+        for (int64_t j = 0; j < n; ++j) Xh[(size_t)j * BLK + q] *= inv;
+        break;
+      }
+      if (attempt == 0) {
+        for (int64_t j = 0; j < n; ++j) Xh[(size_t)j * BLK + q] = start_entry(salt + (uint64_t)(j * BLK + q));
+      } else {
+        for (int64_t j = 0; j < n; ++j) Xh[(size_t)j * BLK + q] = 0.0;
+      }
+    }
+  }
+  for (int64_t j = 0; j < n; ++j)
+    for (int q = b; q < BLK; ++q) Xh[(size_t)j * BLK + q] = 0.0;
+}
+
+int upload_block(rpca_fw* h, hipStream_t s) {
+  std::vector<float> xf(h->Xh.size());
+  for (size_t e = 0; e < xf.size(); ++e) xf[e] = (float)h->Xh[e];
+  FWCHK(hipMemcpyAsync(h->Xb, xf.data(), xf.size() * 4, hipMemcpyHostToDevice, s));
+  FWCHK(hipStreamSynchronize(s));  // xf dies with this frame
+  return RPCA_OK;
+}
+
+// Linear minimisation: top singular triplet of G by block power iteration with
+// Rayleigh-Ritz.  On return y = G v (device), v (device, unit), *sigma = ||G v||,
+// and the block holds the Ritz vectors (the next call's start).
+int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
+  const int64_t m = h->m, n = h->n;
+  const int b = h->b;
+  const int64_t lblocks = h->rb_upd * h->nchunks_left;
+  const int64_t ncb = (n + RIGHT_COLS - 1) / RIGHT_COLS;
+  const int64_t rblocks = h->rc_right * ncb;
+  std::vector<double> Zh((size_t)n * BLK), H((size_t)b * b), th(b), W((size_t)b * b), ZW((size_t)n * BLK);
+  for (int p = 0;; ++p) {
+    if (h->vec == 4)
+      hipLaunchKernelGGL(k_fw_left<4>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+    else
+      hipLaunchKernelGGL(k_fw_left<1>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+    FWCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_fw_left_finish, dim3((unsigned)((m * BLK + TH - 1) / TH)), dim3(TH), 0, s,
+                       (const float*)h->ypart, h->nchunks_left, m * BLK, h->Y);
+    FWCHK(hipGetLastError());
+    if (h->vec == 4)
+      hipLaunchKernelGGL(k_fw_right<4>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Y, m, n, ncb, h->part);
+    else
+      hipLaunchKernelGGL(k_fw_right<1>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Y, m, n, ncb, h->part);
+    FWCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_fw_right_finish, dim3((unsigned)((n * BLK + TH - 1) / TH)), dim3(TH), 0, s,
+                       (const double*)h->part, h->rc_right, n * BLK, h->Z);
+    FWCHK(hipGetLastError());
+    FWCHK(hipMemcpyAsync(Zh.data(), h->Z, Zh.size() * 8, hipMemcpyDeviceToHost, s));
+    FWCHK(hipStreamSynchronize(s));
+    ++*steps;
+    // Rayleigh-Ritz: H = Xb^T Z (b x b) = Xb^T G^T G Xb
+    for (int a = 0; a < b; ++a)
+      for (int c = 0; c < b; ++c) {
+        double d = 0.0;
+        for (int64_t j = 0; j < n; ++j) d += h->Xh[(size_t)j * BLK + a] * Zh[(size_t)j * BLK + c];
+        H[(size_t)a * b + c] = d;
+      }
+    for (int a = 0; a < b; ++a)
+      for (int c = a + 1; c < b; ++c) H[(size_t)a * b + c] = H[(size_t)c * b + a] =
+                                          0.5 * (H[(size_t)a * b + c] + H[(size_t)c * b + a]);
+    rpca::la::sym_eig(H.data(), b, th.data(), W.data());
+    const double th0 = std::max(th[0], 0.0);
+    // residual of the top Ritz pair: || Z w0 - th0 Xb w0 || / th0
+    double rr = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      double zw = 0.0, xw = 0.0;
+      for (int a = 0; a < b; ++a) {
+        zw += Zh[(size_t)j * BLK + a] * W[(size_t)a * b];
+        xw += h->Xh[(size_t)j * BLK + a] * W[(size_t)a * b];
+      }
+      rr += (zw - th0 * xw) * (zw - th0 * xw);
+    }
+    const double resid = th0 > 0 ? sqrt(rr) / th0 : 0.0;
+    const bool done = resid <= ptol || p + 1 == POWER_MAX || th0 == 0.0;
+    if (done) {
+      // v = Xb w0, y = Y w0 = G v, sigma = sqrt(th0)
+      std::vector<float> vf((size_t)n);
+      for (int64_t j = 0; j < n; ++j) {
+        double d = 0.0;
+        for (int a = 0; a < b; ++a) d += h->Xh[(size_t)j * BLK + a] * W[(size_t)a * b];
+        vf[(size_t)j] = (float)d;
+      }
+      Coef cw;
+      for (int a = 0; a < BLK; ++a) cw.w[a] = a < b ? (float)W[(size_t)a * b] : 0.f;
+      FWCHK(hipMemcpyAsync(h->v, vf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_fw_combine, dim3((unsigned)((m + TH - 1) / TH)), dim3(TH), 0, s, (const float*)h->Y, cw, m,
+                         h->y);
+      FWCHK(hipGetLastError());
+      FWCHK(hipStreamSynchronize(s));  // vf dies with this frame
+      *sigma = sqrt(th0);
+    }
+    // next block: the Ritz-rotated Z, orthonormalised
+    for (int64_t j = 0; j < n; ++j)
+      for (int c = 0; c < BLK; ++c) {
+        double d = 0.0;
+        if (c < b)
+          for (int a = 0; a < b; ++a) d += Zh[(size_t)j * BLK + a] * W[(size_t)a * b + c];
+        ZW[(size_t)j * BLK + c] = d;
+      }
+    h->Xh.swap(ZW);
+    orth_block(h->Xh, n, b, 0x51ull * (uint64_t)(p + 1));
+    int rc = upload_block(h, s);
+    if (rc) return rc;
+    if (done) return RPCA_OK;
+  }
+}
+
+// u^T P_Omega(L) v and sum_Omega u_i^2 v_j^2 with u = y / sigma.
+int fw_bilinear(rpca_fw* h, const float* L, double sigma, double* b1, double* b2, hipStream_t s) {
+  const int64_t cblocks = h->rc_bil * h->n;
+  const float ws = (float)(1.0 / sigma);
+  if (h->vec == 4) {
+    if (h->mask)
+      hipLaunchKernelGGL((k_fw_bilinear<4, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y, ws,
+                         (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+    else
+      hipLaunchKernelGGL((k_fw_bilinear<4, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                         ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+  } else {
+    if (h->mask)
+      hipLaunchKernelGGL((k_fw_bilinear<1, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y, ws,
+                         (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+    else
+      hipLaunchKernelGGL((k_fw_bilinear<1, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                         ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+  }
+  FWCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_fw_bilinear_finish, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, h->rc_bil, h->n,
+                     (const float*)h->v, h->res);
+  FWCHK(hipGetLastError());
+  FWCHK(hipMemcpyAsync(h->res_host + 2, h->res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  FWCHK(hipStreamSynchronize(s));
+  *b1 = h->res_host[2];
+  *b2 = h->res_host[3];
+  return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpca_fw_create(int64_t m, int64_t n, double lam_s, double lam_l, const uint8_t* mask, rpca_fw** out) {
+  if (!out) return RPCA_EINVAL;
+  *out = nullptr;
+  if (m < 1 || n < 1 || m > ((int64_t)1 << 31) || n > ((int64_t)1 << 24)) return RPCA_EINVAL;
+  if (!(lam_s > 0) || !(lam_l > 0) || !isfinite(lam_s) || !isfinite(lam_l)) return RPCA_EINVAL;
+  rpca_fw* h = new (std::nothrow) rpca_fw();
+  if (!h) return RPCA_ENOMEM;
+  h->m = m;
+  h->n = n;
+  h->lam_s = lam_s;
+  h->lam_l = lam_l;
+  h->b = (int)std::min<int64_t>(BLK, n);
+  h->nchunks_left = (n + LEFT_COLS - 1) / LEFT_COLS;
+  // partials sized for the scalar layout (the most blocks)
+  const int64_t rb1 = (m + TH - 1) / TH;
+  const int64_t rcr1 = (m + (int64_t)TH * RIGHT_ITER - 1) / ((int64_t)TH * RIGHT_ITER);
+  const int64_t rcb1 = (m + (int64_t)TH * COL_ITER - 1) / ((int64_t)TH * COL_ITER);
+  const int64_t parts = std::max(std::max(rb1 * n * 3, rcr1 * n * BLK), rcb1 * n * 2);
+  bool ok = true;
+  try {
+    h->Xh.assign((size_t)n * BLK, 0.0);
+  } catch (...) {
+    ok = false;
+  }
+  ok = ok && hipMalloc(&h->G, (size_t)(m * n) * 4) == hipSuccess &&
+       hipMalloc(&h->ypart, (size_t)(h->nchunks_left * m * BLK) * 4) == hipSuccess &&
+       hipMalloc(&h->Y, (size_t)(m * BLK) * 4) == hipSuccess && hipMalloc(&h->y, (size_t)m * 4) == hipSuccess &&
+       hipMalloc(&h->Xb, (size_t)(n * BLK) * 4) == hipSuccess && hipMalloc(&h->v, (size_t)n * 4) == hipSuccess &&
+       hipMalloc(&h->part, (size_t)parts * 8) == hipSuccess && hipMalloc(&h->Z, (size_t)(n * BLK) * 8) == hipSuccess &&
+       hipMalloc(&h->res, 16 * 8) == hipSuccess && hipHostMalloc(&h->res_host, 16 * 8, hipHostMallocDefault) == hipSuccess;
+  if (ok && (hipMemset(h->y, 0, (size_t)m * 4) != hipSuccess || hipMemset(h->v, 0, (size_t)n * 4) != hipSuccess))
+    ok = false;
+  if (ok && mask) {
+    h->mw = (int)((m + 31) / 32);
+    std::vector<uint32_t> bits((size_t)h->mw * (size_t)n, 0u);
+    for (int64_t j = 0; j < n; ++j) {
+      const uint8_t* col = mask + j * m;
+      uint32_t* w = bits.data() + j * h->mw;
+      for (int64_t i = 0; i < m; ++i)
+        if (col[i]) w[i >> 5] |= 1u << (i & 31);
+    }
+    ok = hipMalloc(&h->mask, bits.size() * 4) == hipSuccess &&
+         hipMemcpy(h->mask, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) {
+    fw_free(h);
+    return RPCA_ENOMEM;
+  }
+  *out = h;
+  return RPCA_OK;
+}
+
+void rpca_fw_destroy(rpca_fw* h) {
+  if (h) fw_free(h);
+}
+
+int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t max_iter, double tol,
+                  double power_tol, rpca_fw_info* info, void* stream) {
+  if (!h || !X || !L || !t_io) return RPCA_EINVAL;
+  if (max_iter < 0 || !(tol >= 0) || !isfinite(*t_io) || *t_io < 0 || !(power_tol >= 0)) return RPCA_EINVAL;
+  const double ptol = power_tol > 0 ? power_tol : POWER_TOL;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const double lam_l = h->lam_l;
+  // 16-byte vector accesses when every column start is 16-byte aligned
+  const bool al = ((uintptr_t)X % 16 == 0) && ((uintptr_t)L % 16 == 0);
+  h->vec = (h->m % 4 == 0 && al) ? 4 : 1;
+  h->rb_upd = (h->m + TH * h->vec - 1) / (TH * h->vec);
+  h->rc_right = (h->m + (int64_t)TH * h->vec * RIGHT_ITER - 1) / ((int64_t)TH * h->vec * RIGHT_ITER);
+  h->rc_bil = (h->m + (int64_t)TH * h->vec * COL_ITER - 1) / ((int64_t)TH * h->vec * COL_ITER);
+  int rc;
+  if (!h->x_valid) {
+    for (int64_t j = 0; j < h->n; ++j)
+      for (int q = 0; q < BLK; ++q) h->Xh[(size_t)j * BLK + q] = start_entry((uint64_t)(j * BLK + q));
+    orth_block(h->Xh, h->n, h->b, 0x9000ull);
+    if ((rc = upload_block(h, s))) return rc;
+    h->x_valid = true;
+  }
+  // G, phi, <G, L>, sum_Omega L^2 at the start
+  if ((rc = fw_update(h, X, L, 1.f, 0.f, s))) return rc;
+  double t = *t_io;
+  rpca_fw_info fin;
+  memset(&fin, 0, sizeof(fin));
+  for (int it = 0;; ++it) {
+    const double phi = h->res_host[4], gl = h->res_host[5], l2 = h->res_host[6];
+    if (!isfinite(phi) || !isfinite(gl) || !isfinite(l2)) {
+      *t_io = t;
+      return RPCA_ENONFINITE;
+    }
+    const double F = phi + lam_l * t;
+    const double B = phi / lam_l + t;
+    double sigma = 0.0;
+    if ((rc = fw_lmo(h, ptol, &sigma, &fin.power_iters, s))) return rc;
+    const bool step = sigma > lam_l;
+    double gap, eta = 0.0;
+    if (step) {
+      double b1 = 0.0, b2 = 0.0;
+      if ((rc = fw_bilinear(h, L, sigma, &b1, &b2, s))) return rc;
+      gap = gl + B * sigma + lam_l * (t - B);
+      const double dd = B * B * b2 + 2.0 * B * b1 + l2;
+      if (dd > 0.0) eta = (B * sigma + gl - lam_l * (B - t)) / dd;
+    } else {
+      gap = gl + lam_l * t;
+      if (l2 > 0.0) eta = (gl + lam_l * t) / l2;
+    }
+    eta = fmin(fmax(eta, 0.0), 1.0);
+    fin.F = F;
+    fin.phi = phi;
+    fin.gap = gap;
+    fin.sigma = sigma;
+    fin.last_step = step;
+    fin.iters = it;
+    if (gap <= tol * F || it == max_iter) break;
+    // L <- (1 - eta) L + eta V, V = -B u v^T = -(B / sigma) y v^T
+    const float a = (float)(1.0 - eta);
+    const float bsc = step ? (float)(-eta * B / sigma) : 0.f;
+    if ((rc = fw_update(h, X, L, a, bsc, s))) return rc;
+    t = (1.0 - eta) * t + eta * (step ? B : 0.0);
+    fin.eta = eta;
+  }
+  *t_io = t;
+  fin.status = (fin.gap <= tol * fin.F) ? RPCA_OK : RPCA_ENOTCONV;
+  fin.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = fin;
+  return fin.status;
+}
+
+}  // extern "C"

@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpca.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rpca.h")
 HEADER_PATHS = [HEADER_PATH, os.path.join(os.path.dirname(HEADER_PATH), "rpca_warm.h"),
-                os.path.join(os.path.dirname(HEADER_PATH), "rpca_batch.h")]
+                os.path.join(os.path.dirname(HEADER_PATH), "rpca_batch.h"),
+                os.path.join(os.path.dirname(HEADER_PATH), "rpca_fw.h")]
 
 RPCA_OK, RPCA_ENOTCONV, RPCA_ELINESEARCH, RPCA_ENOTCERT = 0, 1, 2, 3
 RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP, RPCA_ENONFINITE = -1, -2, -3, -4
@@ -70,6 +71,13 @@ class rpca_cert(ctypes.Structure):
         ("r", ctypes.c_int32), ("power_iters", ctypes.c_int32), ("block", ctypes.c_int32),
         ("certified", ctypes.c_int32),
     ]
+
+
+class rpca_fw_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+                ("last_step", ctypes.c_int32), ("F", ctypes.c_double), ("phi", ctypes.c_double),
+                ("gap", ctypes.c_double), ("sigma", ctypes.c_double), ("eta", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
 
 class rpca_batch_layout(ctypes.Structure):
@@ -134,6 +142,10 @@ def lib():
             "rpca_batch_instance_waves": (I32, [P, I32, ctypes.POINTER(I32)]),
             "rpca_batch_destroy": (None, [P]),
             "rpca_autotune": (I32, [I64, I32, P]),
+            # Frank-Wolfe with marginalisation (rpca_fw.h)
+            "rpca_fw_create": (I32, [I64, I64, D, D, P, ctypes.POINTER(P)]),
+            "rpca_fw_solve": (I32, [P, P, P, ctypes.POINTER(D), I32, D, D, ctypes.POINTER(rpca_fw_info), P]),
+            "rpca_fw_destroy": (None, [P]),
             "rpca_tune_get": (I32, [I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
             "rpca_tune_set": (I32, [I32, I64, I32, I32]),
         }
@@ -215,6 +227,33 @@ def rpca_solve_grow(m, n, k0, k_max, lam_s, lam_l, mask, X, U, V, opts=None, str
                                stream)
     del keep
     return rc, k.value, info
+
+
+def rpca_fw_create(m, n, lam_s, lam_l, mask=None):
+    """mask: None or host array (m x n, any order; converted to column-major bytes).
+    Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    mptr = None
+    keep = None
+    if mask is not None:
+        import numpy as np
+        keep = np.asfortranarray(np.asarray(mask) != 0, dtype=np.uint8)
+        mptr = keep.ctypes.data
+    rc = lib().rpca_fw_create(m, n, lam_s, lam_l, mptr, ctypes.byref(h))
+    del keep
+    return rc, h
+
+
+def rpca_fw_solve(h, X, L, t, max_iter, tol, power_tol=0.0, stream=0):
+    """Returns (status, t, info)."""
+    tt = ctypes.c_double(t)
+    info = rpca_fw_info()
+    rc = lib().rpca_fw_solve(h, X, L, ctypes.byref(tt), max_iter, tol, power_tol, ctypes.byref(info), stream)
+    return rc, tt.value, info
+
+
+def rpca_fw_destroy(h):
+    lib().rpca_fw_destroy(h)
 
 
 def rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream=0):

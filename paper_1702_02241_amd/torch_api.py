@@ -113,6 +113,39 @@ def solve_grow(Xcm, m, n, k0, k_max, lam_s, lam_l, mask=None, U0=None, V0=None, 
     return rc, info, Ub[: m * k].view(m, k), Vb[: n * k].view(n, k)
 
 
+class FrankWolfe:
+    """Owns an rpca_fw (rpca_fw.h): Frank-Wolfe with the sparse part marginalised.
+    L lives as an (n, m) contiguous tensor, the column-major layout of X_cm."""
+
+    def __init__(self, m, n, lam_s, lam_l, mask=None):
+        rc, self.h = R.rpca_fw_create(m, n, lam_s, lam_l, mask)
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_fw_create failed: {R.rpca_status_string(rc)}")
+        self.m, self.n = m, n
+
+    def close(self):
+        if self.h:
+            R.rpca_fw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, Xcm, Lcm=None, t=0.0, max_iter=1000, tol=1e-6, power_tol=0.0):
+        """Returns (status, Lcm, t, info); Lcm None starts from L = 0, t = 0."""
+        if Lcm is None:
+            Lcm = torch.zeros_like(Xcm)
+            t = 0.0
+        rc, t, info = R.rpca_fw_solve(self.h, Xcm.data_ptr(), Lcm.data_ptr(), t, max_iter, tol, power_tol,
+                                      _stream())
+        if rc < 0:
+            raise RuntimeError(f"rpca_fw_solve failed: {R.rpca_status_string(rc)}")
+        return rc, Lcm, t, info
+
+
 class WarmNet:
     """Owns an rpca_mlp (rpca_warm.h): the 2-layer warm-start network."""
 

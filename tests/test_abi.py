@@ -141,3 +141,20 @@ def test_batch_entry_points_reject_bad_arguments_before_hip():
     assert R.rpca_batch_set_graphs(None, 1) == R.RPCA_EINVAL
     assert R.rpca_batch_instance_waves(None, 0)[0] == R.RPCA_EINVAL
     R.rpca_batch_destroy(None)
+
+
+def test_frank_wolfe_entry_points_reject_bad_arguments_before_hip():
+    for args in [(0, 10, 0.1, 1.0), (10, 0, 0.1, 1.0), (10, 10, 0.0, 1.0), (10, 10, 0.1, -1.0),
+                 (10, 10, float("nan"), 1.0), ((1 << 31) + 1, 10, 0.1, 1.0), (10, (1 << 24) + 1, 0.1, 1.0)]:
+        rc, h = R.rpca_fw_create(*args)
+        assert rc == R.RPCA_EINVAL and not h.value
+    assert R.rpca_fw_solve(None, 1, 1, 0.0, 10, 1e-6)[0] == R.RPCA_EINVAL
+    assert R.rpca_fw_solve(None, 1, 1, 0.0, 10, 1e-6, -1.0)[0] == R.RPCA_EINVAL
+    R.rpca_fw_destroy(None)
+
+
+def test_frank_wolfe_info_layout_matches_header_order():
+    text = open(R.HEADER_PATHS[-1]).read()
+    body = re.search(r"typedef struct rpca_fw_info \{(.*?)\} rpca_fw_info;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    assert [f for f, _ in R.rpca_fw_info._fields_] == re.findall(r"(\w+)\s*;", body)
