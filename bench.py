@@ -48,9 +48,11 @@ def parse():
                     help="profiling aid: run --reps objective/gradient evaluations (or device copies of X, "
                          "the calibration of the HBM byte counters) at the workload's shape and exit")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--workload", choices=["video", "batch"], default="video",
+    ap.add_argument("--workload", choices=["video", "batch", "fw"], default="video",
                     help="video: the single 76,800 x 200 solve (default line); batch: the 64 uneven "
-                         "Gaussian instances solved by the batched path against one-by-one solves")
+                         "Gaussian instances solved by the batched path against one-by-one solves; fw: "
+                         "Frank-Wolfe with marginalisation on the video (--fw-iters iterations per step)")
+    ap.add_argument("--fw-iters", type=int, default=100)
     return ap.parse_args()
 
 
@@ -119,6 +121,97 @@ def run_batch(args):
         "sweep_items": lay.sweep_items, "sweep_classes": lay.sweep_classes, "graphs": lay.graphs,
     }
     print(json.dumps(out))
+
+
+def run_fw(args):
+    """Frank-Wolfe with the sparse part marginalised (Sec. 6.2, Alg. 1) on the
+    76,800 x 200 video: one step = --fw-iters iterations from L = 0, t = 0."""
+    import numpy as np
+    import torch
+
+    from paper_1702_02241_amd import rpca as R
+    from paper_1702_02241_amd import synth
+    from paper_1702_02241_amd import torch_api as T
+    dev = torch.device("cuda:0")
+    p = synth.video()
+    m, n = p.m, p.n
+    Xcm = T.to_device_X(p.X, dev)
+    fw = T.FrankWolfe(m, n, p.lam_s, p.lam_l)
+    iters = args.fw_iters
+
+    def step():
+        return fw.solve(Xcm, None, 0.0, max_iter=iters, tol=0.0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        rc, L, t, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    done = sum(i.iters for i in infos)
+    # the same steps with the library's per-launch HIP events on the launch stream
+    fw.profile(True)
+    fw.profile_read(reset=True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    launches, ms = fw.profile_read(reset=True)
+    fw.profile(False)
+    blk = 8
+    names = ["update", "left", "right", "bilinear"]
+    alg = [16 * m * n, 4 * m * n + 4 * blk * m, 4 * m * n + 4 * blk * m, 4 * m * n + 4 * m]
+    per = {nm: dict(launches=int(launches[i]) // max(args.steps, 1), ms=round(ms[i] / max(args.steps, 1), 3),
+                    us_per_launch=round(1000 * ms[i] / max(launches[i], 1), 2)) for i, nm in enumerate(names)}
+    dom = max(range(4), key=lambda i: ms[i])
+    k_ms = ms[dom] / max(launches[dom], 1)
+    achieved = alg[dom] / (k_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel=f"k_fw_{names[dom]}", kernel_ms=round(k_ms, 5), launches=int(launches[dom]),
+                    alg_bytes_per_launch=alg[dom])
+    cpu = None
+    if not args.no_cpu:
+        from oracle import frank_wolfe as ofw
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            threads = os.cpu_count() or 1
+        Lh, th = np.zeros((m, n)), 0.0
+        c0 = time.perf_counter()
+        k = 0
+        while True:
+            Lh, th, _ = ofw.fw_iteration(Lh, th, p.X, p.lam_s, p.lam_l)
+            k += 1
+            el = time.perf_counter() - c0
+            if el >= args.cpu_seconds or k >= 50:
+                break
+        cpu = dict(value=k / el, unit="FW iterations/s", cores=int(threads), kind="oracle",
+                   sample=f"{k} FP64 NumPy Frank-Wolfe iterations (LAPACK SVD for the linear minimisation) "
+                          f"from L = 0 at 76800x200 ({el:.1f} s); host cpu_count={os.cpu_count()}")
+    last = infos[-1]
+    out = {
+        "metric": "Frank-Wolfe (marginalised, Alg. 1) iterations/s, 76800x200",
+        "value": round(done / elapsed, 1),
+        "unit": "FW iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000 * elapsed / max(args.steps, 1), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded video generator; the paper's videos are not available)",
+        "config": {"workload": f"synthetic video 76800x200 FP32, lam_S={p.lam_s}, lam_L={p.lam_l:.4f}, "
+                               f"{iters} Frank-Wolfe iterations from L = 0 per step, block power LMO (8 vectors)"},
+        "F_after_step": last.F, "gap_after_step": last.gap,
+        "power_steps_per_iter": round(last.power_iters / max(last.iters, 1), 2),
+        "kernel_ms_per_step": per,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    fw.close()
 
 
 def probe(args):
@@ -207,11 +300,11 @@ def main():
     if args.probe:
         probe(args)
         return
-    if args.workload == "batch":
+    if args.workload in ("batch", "fw"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        run_batch(args)
+        (run_batch if args.workload == "batch" else run_fw)(args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is the single-GPU kernel; "

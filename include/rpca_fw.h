@@ -66,6 +66,23 @@ int rpca_fw_solve(rpca_fw* fw, const float* X, float* L, double* t, int32_t max_
 
 void rpca_fw_destroy(rpca_fw* fw);
 
+/* Kernel timing.  When on, rpca_fw_solve records an event pair around each
+ * streaming kernel (classes below; the small finishing kernels are not
+ * counted); rpca_fw_profile_read collects them (synchronising on the events)
+ * and optionally resets the counters.  RPCA_EINVAL on a null handle or out. */
+enum rpca_fw_kernel {
+  RPCA_FW_K_UPDATE = 0,    /* L <- a L + b y v^T and G: reads L, X; writes L, G */
+  RPCA_FW_K_LEFT = 1,      /* partial Y = G Xb over column chunks: reads G */
+  RPCA_FW_K_RIGHT = 2,     /* partial Z = G^T Y over row chunks: reads G and Y */
+  RPCA_FW_K_BILINEAR = 3   /* u^T P_Omega(L) v: reads L */
+};
+typedef struct rpca_fw_profile {
+  int64_t launches[4];
+  double ms[4];
+} rpca_fw_profile;
+int rpca_fw_profile_enable(rpca_fw* fw, int32_t on);
+int rpca_fw_profile_read(rpca_fw* fw, rpca_fw_profile* out, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

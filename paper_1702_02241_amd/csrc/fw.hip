@@ -387,11 +387,65 @@ struct rpca_fw {
   std::vector<double> Xh;       // host copy of the block (FP64)
   int64_t rb_upd = 0, nchunks_left = 0, rc_right = 0, rc_bil = 0;
   bool x_valid = false;
+  // optional kernel timing (rpca_fw_profile_*): event pairs per kernel class
+  bool prof_on = false;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_free;
+  int64_t launches[4] = {0, 0, 0, 0};
+  double ms[4] = {0, 0, 0, 0};
 };
 
 namespace {
 
+hipEvent_t fw_event(rpca_fw* h) {
+  if (!h->ev_free.empty()) {
+    hipEvent_t e = h->ev_free.back();
+    h->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Elapsed times of the recorded pairs (their stream has been synchronised).
+void fw_collect(rpca_fw* h) {
+  for (auto& p : h->pending) {
+    float t = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+      h->launches[p.cls] += 1;
+      h->ms[p.cls] += t;
+    }
+    h->ev_free.push_back(p.a);
+    h->ev_free.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
+// Launch with an event pair around it when timing is on.
+template <typename Fn>
+hipError_t fw_timed(rpca_fw* h, int cls, hipStream_t s, Fn&& launch) {
+  if (!h->prof_on) {
+    launch();
+    return hipGetLastError();
+  }
+  hipEvent_t a = fw_event(h), b = fw_event(h);
+  if (!a || !b || hipEventRecord(a, s) != hipSuccess) return hipErrorUnknown;
+  launch();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+  h->pending.push_back({cls, a, b});
+  if (h->pending.size() >= 4096) fw_collect(h);
+  return hipSuccess;
+}
+
 void fw_free(rpca_fw* h) {
+  fw_collect(h);
+  for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
   for (void* p : {(void*)h->mask, (void*)h->G, (void*)h->ypart, (void*)h->Y, (void*)h->y, (void*)h->Xb, (void*)h->v,
                   (void*)h->part, (void*)h->Z, (void*)h->res})
     if (p) (void)hipFree(p);
@@ -408,22 +462,23 @@ void fw_free(rpca_fw* h) {
 int fw_update(rpca_fw* h, const float* X, float* L, float a, float b, hipStream_t s) {
   const int64_t blocks = h->rb_upd * h->n;
   const float ls = (float)h->lam_s;
-  if (h->vec == 4) {
-    if (h->mask)
-      hipLaunchKernelGGL((k_fw_update<4, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
-    else
-      hipLaunchKernelGGL((k_fw_update<4, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
-  } else {
-    if (h->mask)
-      hipLaunchKernelGGL((k_fw_update<1, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
-    else
-      hipLaunchKernelGGL((k_fw_update<1, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                         h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
-  }
-  FWCHK(hipGetLastError());
+  FWCHK(fw_timed(h, RPCA_FW_K_UPDATE, s, [&] {
+    if (h->vec == 4) {
+      if (h->mask)
+        hipLaunchKernelGGL((k_fw_update<4, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                           h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+      else
+        hipLaunchKernelGGL((k_fw_update<4, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw,
+                           h->m, h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+    } else {
+      if (h->mask)
+        hipLaunchKernelGGL((k_fw_update<1, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
+                           h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+      else
+        hipLaunchKernelGGL((k_fw_update<1, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw,
+                           h->m, h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+    }
+  }));
   hipLaunchKernelGGL(k_sum_parts<3>, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, blocks, h->res + 4);
   FWCHK(hipGetLastError());
   FWCHK(hipMemcpyAsync(h->res_host + 4, h->res + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -482,23 +537,25 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
   const int64_t rblocks = h->rc_right * ncb;
   std::vector<double> Zh((size_t)n * BLK), H((size_t)b * b), th(b), W((size_t)b * b), ZW((size_t)n * BLK);
   for (int p = 0;; ++p) {
-    if (h->vec == 4)
-      hipLaunchKernelGGL(k_fw_left<4>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
-                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
-    else
-      hipLaunchKernelGGL(k_fw_left<1>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
-                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
-    FWCHK(hipGetLastError());
+    FWCHK(fw_timed(h, RPCA_FW_K_LEFT, s, [&] {
+      if (h->vec == 4)
+        hipLaunchKernelGGL(k_fw_left<4>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                           (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+      else
+        hipLaunchKernelGGL(k_fw_left<1>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                           (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+    }));
     hipLaunchKernelGGL(k_fw_left_finish, dim3((unsigned)((m * BLK + TH - 1) / TH)), dim3(TH), 0, s,
                        (const float*)h->ypart, h->nchunks_left, m * BLK, h->Y);
     FWCHK(hipGetLastError());
-    if (h->vec == 4)
-      hipLaunchKernelGGL(k_fw_right<4>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
-                         (const float*)h->Y, m, n, ncb, h->part);
-    else
-      hipLaunchKernelGGL(k_fw_right<1>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
-                         (const float*)h->Y, m, n, ncb, h->part);
-    FWCHK(hipGetLastError());
+    FWCHK(fw_timed(h, RPCA_FW_K_RIGHT, s, [&] {
+      if (h->vec == 4)
+        hipLaunchKernelGGL(k_fw_right<4>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                           (const float*)h->Y, m, n, ncb, h->part);
+      else
+        hipLaunchKernelGGL(k_fw_right<1>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                           (const float*)h->Y, m, n, ncb, h->part);
+    }));
     hipLaunchKernelGGL(k_fw_right_finish, dim3((unsigned)((n * BLK + TH - 1) / TH)), dim3(TH), 0, s,
                        (const double*)h->part, h->rc_right, n * BLK, h->Z);
     FWCHK(hipGetLastError());
@@ -566,22 +623,23 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
 int fw_bilinear(rpca_fw* h, const float* L, double sigma, double* b1, double* b2, hipStream_t s) {
   const int64_t cblocks = h->rc_bil * h->n;
   const float ws = (float)(1.0 / sigma);
-  if (h->vec == 4) {
-    if (h->mask)
-      hipLaunchKernelGGL((k_fw_bilinear<4, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y, ws,
-                         (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
-    else
-      hipLaunchKernelGGL((k_fw_bilinear<4, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                         ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
-  } else {
-    if (h->mask)
-      hipLaunchKernelGGL((k_fw_bilinear<1, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y, ws,
-                         (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
-    else
-      hipLaunchKernelGGL((k_fw_bilinear<1, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                         ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
-  }
-  FWCHK(hipGetLastError());
+  FWCHK(fw_timed(h, RPCA_FW_K_BILINEAR, s, [&] {
+    if (h->vec == 4) {
+      if (h->mask)
+        hipLaunchKernelGGL((k_fw_bilinear<4, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+      else
+        hipLaunchKernelGGL((k_fw_bilinear<4, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+    } else {
+      if (h->mask)
+        hipLaunchKernelGGL((k_fw_bilinear<1, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+      else
+        hipLaunchKernelGGL((k_fw_bilinear<1, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
+                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+    }
+  }));
   hipLaunchKernelGGL(k_fw_bilinear_finish, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, h->rc_bil, h->n,
                      (const float*)h->v, h->res);
   FWCHK(hipGetLastError());
@@ -650,6 +708,26 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_s, double lam_l, const uint8
 
 void rpca_fw_destroy(rpca_fw* h) {
   if (h) fw_free(h);
+}
+
+int rpca_fw_profile_enable(rpca_fw* h, int32_t on) {
+  if (!h) return RPCA_EINVAL;
+  h->prof_on = on != 0;
+  return RPCA_OK;
+}
+
+int rpca_fw_profile_read(rpca_fw* h, rpca_fw_profile* out, int32_t reset) {
+  if (!h || !out) return RPCA_EINVAL;
+  fw_collect(h);
+  for (int i = 0; i < 4; ++i) {
+    out->launches[i] = h->launches[i];
+    out->ms[i] = h->ms[i];
+    if (reset) {
+      h->launches[i] = 0;
+      h->ms[i] = 0.0;
+    }
+  }
+  return RPCA_OK;
 }
 
 int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t max_iter, double tol,

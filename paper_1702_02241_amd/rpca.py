@@ -91,6 +91,10 @@ class rpca_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
 
+class rpca_fw_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
+
+
 RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION, RPCA_K_TRIAL = 0, 1, 2, 3, 4
 
 _lib = None
@@ -146,6 +150,8 @@ def lib():
             "rpca_fw_create": (I32, [I64, I64, D, D, P, ctypes.POINTER(P)]),
             "rpca_fw_solve": (I32, [P, P, P, ctypes.POINTER(D), I32, D, D, ctypes.POINTER(rpca_fw_info), P]),
             "rpca_fw_destroy": (None, [P]),
+            "rpca_fw_profile_enable": (I32, [P, I32]),
+            "rpca_fw_profile_read": (I32, [P, ctypes.POINTER(rpca_fw_profile), I32]),
             "rpca_tune_get": (I32, [I32, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
             "rpca_tune_set": (I32, [I32, I64, I32, I32]),
         }
@@ -254,6 +260,16 @@ def rpca_fw_solve(h, X, L, t, max_iter, tol, power_tol=0.0, stream=0):
 
 def rpca_fw_destroy(h):
     lib().rpca_fw_destroy(h)
+
+
+RPCA_FW_K_UPDATE, RPCA_FW_K_LEFT, RPCA_FW_K_RIGHT, RPCA_FW_K_BILINEAR = 0, 1, 2, 3
+
+
+def rpca_fw_profile_read(h, reset=True):
+    """(status, launches[4], ms[4]) per kernel class."""
+    p = rpca_fw_profile()
+    rc = lib().rpca_fw_profile_read(h, ctypes.byref(p), 1 if reset else 0)
+    return rc, list(p.launches), list(p.ms)
 
 
 def rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream=0):

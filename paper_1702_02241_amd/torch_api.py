@@ -134,6 +134,15 @@ class FrankWolfe:
         except Exception:
             pass
 
+    def profile(self, on):
+        R.lib().rpca_fw_profile_enable(self.h, 1 if on else 0)
+
+    def profile_read(self, reset=True):
+        rc, launches, ms = R.rpca_fw_profile_read(self.h, reset)
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_fw_profile_read failed: {R.rpca_status_string(rc)}")
+        return launches, ms
+
     def solve(self, Xcm, Lcm=None, t=0.0, max_iter=1000, tol=1e-6, power_tol=0.0):
         """Returns (status, Lcm, t, info); Lcm None starts from L = 0, t = 0."""
         if Lcm is None:

@@ -158,3 +158,8 @@ def test_frank_wolfe_info_layout_matches_header_order():
     body = re.search(r"typedef struct rpca_fw_info \{(.*?)\} rpca_fw_info;", text, re.S).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     assert [f for f, _ in R.rpca_fw_info._fields_] == re.findall(r"(\w+)\s*;", body)
+
+
+def test_frank_wolfe_profile_rejects_null():
+    assert R.lib().rpca_fw_profile_enable(None, 1) == R.RPCA_EINVAL
+    assert R.rpca_fw_profile_read(None)[0] == R.RPCA_EINVAL
