@@ -83,13 +83,13 @@ def _terms_efficient(D, U1, V1):
 
 
 def certificate(U, V, X, lam_s, lam_l, mask=None, tau=1e-10, F_best=None,
-                form="exact", rel_tol=1e-3):
+                form="exact", rel_tol=1e-3, mu=0.0):
     """Certificate terms, F(L), F_bound and the gap bound at L = U V^T."""
     U = np.asarray(U, np.float64)
     V = np.asarray(V, np.float64)
     X = np.asarray(X, np.float64)
     L = U @ V.T
-    D = grad_phi(L, X, lam_s, mask) / lam_l
+    D = grad_phi(L, X, lam_s, mask, mu) / lam_l
     U1, sig, V1, sig_all = factor_svd(U, V, tau)
     r = sig.size
     if form == "exact":
@@ -99,9 +99,9 @@ def certificate(U, V, X, lam_s, lam_l, mask=None, tau=1e-10, F_best=None,
         T1, T2, T3, T4, sv, normM2 = _terms_efficient(D, U1, V1)
     trunc = float(np.sqrt(np.sum(sig_all[r:] ** 2))) / lam_l
     E = float(np.sqrt(max(T1 + T2 + T3 + T4, 0.0))) + trunc
-    phiL = phi(L, X, lam_s, mask)
+    phiL = phi(L, X, lam_s, mask, mu)
     F = lam_l * float(np.sum(sig_all)) + phiL
-    phi0 = phi(np.zeros_like(X), X, lam_s, mask)
+    phi0 = phi(np.zeros_like(X), X, lam_s, mask, mu)
     F_bound = min(F, phi0) if F_best is None else min(F, phi0, F_best)
     normL = float(np.sqrt(np.sum(sig_all ** 2)))
     gap = E * (lam_l * normL + F_bound)

@@ -28,14 +28,14 @@ def svt(Z, tau):
     return (U[:, :r] * s[:r]) @ Vt[:r], s[:r]
 
 
-def objective(L, X, lam_s, lam_l, mask=None, sing=None):
+def objective(L, X, lam_s, lam_l, mask=None, sing=None, mu=0.0):
     if sing is None:
         sing = np.linalg.svd(L, compute_uv=False)
-    return lam_l * float(np.sum(sing)) + phi(L, X, lam_s, mask)
+    return lam_l * float(np.sum(sing)) + phi(L, X, lam_s, mask, mu)
 
 
 def fista_svt(X, lam_s, lam_l, mask=None, L0=None, max_iter=20000, tol=1e-13,
-              callback=None):
+              callback=None, mu=0.0):
     """Minimise F(L) by accelerated proximal gradient, step 1.
 
     Stops when ||L_{t+1} - L_t||_F <= tol * max(1, ||L_t||_F).
@@ -45,16 +45,16 @@ def fista_svt(X, lam_s, lam_l, mask=None, L0=None, max_iter=20000, tol=1e-13,
     L = np.zeros_like(X) if L0 is None else np.array(L0, np.float64)
     Yk = L.copy()
     t = 1.0
-    F_prev = objective(L, X, lam_s, lam_l, mask)
+    F_prev = objective(L, X, lam_s, lam_l, mask, mu=mu)
     it = 0
     for it in range(1, max_iter + 1):
-        L_new, s_new = svt(Yk - grad_phi(Yk, X, lam_s, mask), lam_l)
-        F_new = lam_l * float(np.sum(s_new)) + phi(L_new, X, lam_s, mask)
+        L_new, s_new = svt(Yk - grad_phi(Yk, X, lam_s, mask, mu), lam_l)
+        F_new = lam_l * float(np.sum(s_new)) + phi(L_new, X, lam_s, mask, mu)
         if F_new > F_prev:
             # adaptive restart: drop the momentum and take a plain step from L
             t = 1.0
-            L_new, s_new = svt(L - grad_phi(L, X, lam_s, mask), lam_l)
-            F_new = lam_l * float(np.sum(s_new)) + phi(L_new, X, lam_s, mask)
+            L_new, s_new = svt(L - grad_phi(L, X, lam_s, mask, mu), lam_l)
+            F_new = lam_l * float(np.sum(s_new)) + phi(L_new, X, lam_s, mask, mu)
         t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         step = np.linalg.norm(L_new - L)
         Yk = L_new + ((t - 1.0) / t_new) * (L_new - L)
