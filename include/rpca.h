@@ -143,6 +143,19 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
 int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
                       const uint8_t* mask, int32_t target_waves, rpca_ctx** out);
 
+/* Elastic-net regulariser (Sec. 1 lists it among the structures r(S) that
+ * marginalise like the l1 norm): r(S) = lam_S ||S||_1 + mu/2 ||S||_F^2.  The
+ * per-entry marginal keeps rho(r) = r^2/2 for |r| <= lam_S and becomes
+ * lam_S |r| - lam_S^2/2 + kappa/2 (|r| - lam_S)^2 beyond, kappa = mu / (1 + mu), so
+ * grad phi = Omega .* (c + kappa (R - c)), c = clip(R, +-lam_S), still 1-Lipschitz:
+ * the solver, the certificate and the rank-growth step apply unchanged.  Every
+ * later objective, gradient, solve and certificate of the context uses it.
+ * mu = 0 (the default) is the l1 regulariser, bit for bit.  With mu > 0 the
+ * products run in FP32 only: rpca_objgrad_ex and rpca_solve return RPCA_EINVAL
+ * for the BF16 precisions.  mu >= 0 and finite, else RPCA_EINVAL.  Changing mu
+ * forgets the certificate's cached values. */
+int rpca_set_elastic(rpca_ctx* ctx, double mu);
+
 /* Objective and gradient at (U, V) (Sec. 1 eq. PhiDef/eq. smoothNC, Sec. 3.2 eq. diff).
  * X, U, V, gU, gV: device.  f: device pointer to one double receiving f(U,V).
  * Deterministic: the same inputs give bitwise identical outputs. */

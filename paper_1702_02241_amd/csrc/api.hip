@@ -47,6 +47,7 @@ SweepArgs make_sweep_args(const rpca_ctx* c, const float* X) {
   a.mw = c->mw;
   a.lam_s = (float)c->lam_s;
   a.lam_l = (float)c->lam_l;
+  a.kappa = (float)(c->mu / (1.0 + c->mu));
   // vector (buffer) loads: 16-byte aligned columns, lane offsets within 32 bits
   a.xvec = (c->m % 4 == 0) && (((uintptr_t)X & 15u) == 0) && c->m < ((int64_t)1 << 26);
   a.gupart = c->gupart;
@@ -352,6 +353,17 @@ int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_s, double lam_
 }
 
 
+int rpca_set_elastic(rpca_ctx* c, double mu) {
+  if (!c || !(mu >= 0) || !isfinite(mu)) return RPCA_EINVAL;
+  if (mu != c->mu) {  // a different objective: forget what the certificates cached
+    c->mu = mu;
+    c->best_F = INFINITY;
+    c->phi0 = NAN;
+    c->phi0_X = nullptr;
+  }
+  return RPCA_OK;
+}
+
 int rpca_objgrad(rpca_ctx* c, const float* X, const float* U, const float* V, double* f, float* gU,
                  float* gV, void* stream) {
   return rpca_objgrad_ex(c, X, U, V, f, gU, gV, RPCA_PREC_FP32, stream);
@@ -361,6 +373,7 @@ int rpca_objgrad_ex(rpca_ctx* c, const float* X, const float* U, const float* V,
                     float* gU, float* gV, int32_t precision, void* stream) {
   if (!c || !X || !U || !V || !f || !gU || !gV) return RPCA_EINVAL;
   if (precision != RPCA_PREC_FP32 && precision != RPCA_PREC_BF16) return RPCA_EINVAL;
+  if (c->mu != 0 && precision != RPCA_PREC_FP32) return RPCA_EINVAL;  // elastic net: FP32 products only
   SweepArgs sa = make_sweep_args(c, X);
   FinishArgs fa = make_finish_args(c);
   sa.U[0] = sa.U[1] = U;
@@ -386,6 +399,7 @@ CtxView ctx_view(rpca_ctx* c) {
   v.k = c->k;
   v.lam_s = c->lam_s;
   v.lam_l = c->lam_l;
+  v.kappa = c->mu / (1.0 + c->mu);
   v.mask = c->mask;
   v.mw = c->mw;
   v.best_F = &c->best_F;
@@ -725,6 +739,7 @@ extern "C" int rpca_solve(rpca_ctx* c, const float* X, float* U, float* V, const
   if (opts) o = *opts;
   else rpca_default_opts(&o);
   if (!rpca::valid_opts(o)) return RPCA_EINVAL;
+  if (c->mu != 0 && o.precision != RPCA_PREC_FP32) return RPCA_EINVAL;  // elastic net: FP32 products only
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
   rpca::SolvePhase phases[2];

@@ -48,6 +48,7 @@ struct GArgs {
   int64_t m, n;
   int32_t k, mw;
   float lam_s;
+  float kappa;     // elastic-net slope beyond lam_s (0: l1)
   const float* U;  // residual source only
   const float* V;
   const double* W;  // left: n x ldw
@@ -58,6 +59,13 @@ struct GArgs {
   double* part;      // right: [row_groups][n * BP]
   int32_t strips_per_wg, nchunks, row_groups;
 };
+
+// rho'(R): clip(R, +-lam_s), continued with slope kappa beyond the threshold
+// (elastic net; kappa = 0 is the l1 clip).
+__device__ __forceinline__ float grad_rho(float R, float lam_s, float kappa) {
+  const float c = fminf(fmaxf(R, -lam_s), lam_s);
+  return kappa != 0.f ? fmaf(kappa, R - c, c) : c;
+}
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -122,7 +130,7 @@ __device__ __forceinline__ void tile_op(const GArgs& a, const TileIn& t, int64_t
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(acc[r], -a.lam_s), a.lam_s);
+    for (int r = 0; r < 4; ++r) G[r] = grad_rho(acc[r], a.lam_s, a.kappa);
   } else {
 #pragma unroll
     for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -327,7 +335,7 @@ __global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
               }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(r4[r], -a.lam_s), a.lam_s);
+            for (int r = 0; r < 4; ++r) G[r] = grad_rho(r4[r], a.lam_s, a.kappa);
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -460,7 +468,7 @@ __global__ __launch_bounds__(THREADS) void k_right_lds(GArgs a) {
             }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) G[r] = fminf(fmaxf(r4[r], -a.lam_s), a.lam_s);
+          for (int r = 0; r < 4; ++r) G[r] = grad_rho(r4[r], a.lam_s, a.kappa);
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -645,6 +653,7 @@ hipError_t left_product(const rpca::CtxView& cv, const Workspace& w, const float
   a.k = cv.k;
   a.mw = cv.mw;
   a.lam_s = (float)cv.lam_s;
+  a.kappa = (float)cv.kappa;
   a.U = U;
   a.V = V;
   a.W = W;
@@ -690,6 +699,7 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
   a.k = cv.k;
   a.mw = cv.mw;
   a.lam_s = (float)cv.lam_s;
+  a.kappa = (float)cv.kappa;
   a.U = U;
   a.V = V;
   a.Y = Y;

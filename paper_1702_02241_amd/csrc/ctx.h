@@ -12,6 +12,7 @@ struct rpca_ctx {
   int64_t m = 0, n = 0;
   int k = 0;
   double lam_s = 0, lam_l = 0;
+  double mu = 0;             // elastic-net weight of ||S||_F^2 / 2 (0: the l1 regulariser)
   uint32_t* mask = nullptr;  // device bitmask or null
   int mw = 0;
   // sweep configuration

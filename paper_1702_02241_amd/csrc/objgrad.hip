@@ -266,6 +266,7 @@ hipError_t launch_sweep_f32_plain(const SweepArgs&, bool, hipStream_t);
 hipError_t launch_sweep_f32_trial(const SweepArgs&, bool, hipStream_t);
 hipError_t launch_sweep_bf16_plain(const SweepArgs&, bool, hipStream_t);
 hipError_t launch_sweep_bf16_trial(const SweepArgs&, bool, hipStream_t);
+hipError_t launch_sweep_f32_elastic(const SweepArgs&, bool, bool, hipStream_t);
 
 // Sweep decomposition table, keyed by (k bucket, n bucket): the number of
 // waves the strips are spread over and the divisor of the widest chunk.
@@ -336,6 +337,10 @@ int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_p
 
 hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream) {
   const bool masked = sa.mask != nullptr;
+  if (sa.kappa != 0.f) {  // elastic-net marginal: FP32 products only (callers reject BF16 first)
+    if (bf16) return hipErrorInvalidValue;
+    return launch_sweep_f32_elastic(sa, trial, masked, stream);
+  }
   if (bf16)
     return trial ? launch_sweep_bf16_trial(sa, masked, stream) : launch_sweep_bf16_plain(sa, masked, stream);
   return trial ? launch_sweep_f32_trial(sa, masked, stream) : launch_sweep_f32_plain(sa, masked, stream);

@@ -96,6 +96,7 @@ struct SweepArgs {
   int64_t m, n;
   int32_t k, mw;
   float lam_s, lam_l;
+  float kappa;            // slope of rho' beyond lam_s: mu / (1 + mu) (elastic net), 0 for l1
   int32_t xvec;           // 1: X is 16-byte aligned and m % 4 == 0 (vector loads allowed)
   // base point: U[cur], V[cur]; trial point = base + alpha * d
   const float* U[2];
@@ -214,6 +215,7 @@ struct CtxView {
   int64_t m, n;
   int k;
   double lam_s, lam_l;
+  double kappa;          // elastic-net slope (0: l1)
   const uint32_t* mask;
   int mw;
   double* best_F;

@@ -75,15 +75,26 @@ __device__ __forceinline__ s4 pack_bf16(float a, float b, float c, float d) {
 // Huber value and derivative at one entry of the negated residual Rn = -R (the
 // tiles compute X - U V^T).  Returns Gn = clip(Rn, +-lam_s) = -G and adds
 // rho(R) = G (R - G / 2) = Gn (Rn - Gn / 2) to f and Gn^2 to g2; an unobserved
-// entry (observed = 0) contributes nothing.
-__device__ __forceinline__ float huber(float Rn, float lam_s, uint32_t observed, float& f, float& g2) {
-  float gn = __builtin_amdgcn_fmed3f(Rn, -lam_s, lam_s);
-  float h = fmaf(-0.5f, gn, Rn);
+// entry (observed = 0) contributes nothing.  ELASTIC (the elastic-net marginal,
+// kappa = mu / (1 + mu)): the derivative continues with slope kappa beyond the
+// threshold, Gn = c + kappa (Rn - c), and rho gains kappa (Rn - c)^2 / 2, c = clip(Rn).
+template <bool ELASTIC>
+__device__ __forceinline__ float huber(float Rn, float lam_s, float kappa, uint32_t observed, float& f,
+                                       float& g2) {
+  float c = __builtin_amdgcn_fmed3f(Rn, -lam_s, lam_s);
+  float h = fmaf(-0.5f, c, Rn);
+  float d = ELASTIC ? Rn - c : 0.f;
   if (!observed) {  // whatever X holds there (even a NaN) stays out of f and G
-    gn = 0.f;
+    c = 0.f;
     h = 0.f;
+    d = 0.f;
   }
-  f = fmaf(gn, h, f);
+  f = fmaf(c, h, f);
+  float gn = c;
+  if (ELASTIC) {
+    f = fmaf(0.5f * kappa * d, d, f);
+    gn = fmaf(kappa, d, c);
+  }
   g2 = fmaf(gn, gn, g2);
   return gn;
 }
@@ -159,7 +170,7 @@ struct StripOps {
 typedef __attribute__((address_space(4))) SweepArgs ConstSweepArgs;
 
 // `Args` is SweepArgs (a kernel argument) or ConstSweepArgs (a batch table entry).
-template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, typename Args>
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, typename Args, bool ELASTIC = false>
 __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const int ch, float* lds,
                                             double* sRed) {
   constexpr int KMAX = 16 * KB;
@@ -184,7 +195,7 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
   const int c = lane & 15, g = lane >> 4;
   const int64_t m = a.m, n = a.n;
   const int k = a.k;
-  const float lam_s = a.lam_s, lam_l = a.lam_l;
+  const float lam_s = a.lam_s, lam_l = a.lam_l, kappa = a.kappa;
   const float* __restrict__ U = a.U[cur];
   const float* __restrict__ V = a.V[cur];
   const float* __restrict__ X = a.X;
@@ -366,7 +377,7 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
     float G[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float gn = huber(acc[r], lam_s, MASKED ? ((bits >> r) & 1u) : 1u, ftile, gtile);
+      const float gn = huber<ELASTIC>(acc[r], lam_s, kappa, MASKED ? ((bits >> r) & 1u) : 1u, ftile, gtile);
       G[r] = gn;
       myT[(4 * g + r) * LDT + c] = gn;
     }
@@ -441,7 +452,8 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
         float* tT = myT + v * 16 * LDT;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float gn = huber(acc[u][r], lam_s, MASKED ? ((bits >> r) & 1u) : 1u, ftile, gtile);
+          const float gn = huber<ELASTIC>(acc[u][r], lam_s, kappa, MASKED ? ((bits >> r) & 1u) : 1u, ftile,
+                                          gtile);
           G[v][r] = gn;
           tT[(4 * g + r) * LDT + c] = gn;
         }
@@ -658,11 +670,11 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
 }
 
 
-template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, bool ELASTIC>
 __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
   extern __shared__ float lds[];
   __shared__ double sRed[4 * WAVES];
-  sweep_item<KB, TMAX, MASKED, TRIAL, BF16>(a, blockIdx.x, blockIdx.y, lds, sRed);
+  sweep_item<KB, TMAX, MASKED, TRIAL, BF16, SweepArgs, ELASTIC>(a, blockIdx.x, blockIdx.y, lds, sRed);
 }
 
 // Batched sweep: one persistent launch per tile class (k block, tiles per
@@ -738,7 +750,7 @@ int batch_grid(int kb, int tmax, int lds_floats_max) {
   return per_cu * cus;
 }
 
-template <bool MASKED, bool TRIAL, bool BF16>
+template <bool MASKED, bool TRIAL, bool BF16, bool ELASTIC = false>
 hipError_t launch_kb(const SweepArgs& sa, hipStream_t s) {
   const int kb = (sa.k + 15) / 16;
   const int cwp = (int)(((sa.n < sa.chunk_w ? sa.n : sa.chunk_w) + 15) / 16) * 16;
@@ -748,12 +760,12 @@ hipError_t launch_kb(const SweepArgs& sa, hipStream_t s) {
   const dim3 grid(sa.row_groups, sa.nchunks), block(NT);
   const size_t bytes = lds * sizeof(float);
   if (kb == 1) {
-    if (tm == 4) hipLaunchKernelGGL((k_sweep<1, 4, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
-    else if (tm == 8) hipLaunchKernelGGL((k_sweep<1, 8, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
-    else hipLaunchKernelGGL((k_sweep<1, 16, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+    if (tm == 4) hipLaunchKernelGGL((k_sweep<1, 4, MASKED, TRIAL, BF16, ELASTIC>), grid, block, bytes, s, sa);
+    else if (tm == 8) hipLaunchKernelGGL((k_sweep<1, 8, MASKED, TRIAL, BF16, ELASTIC>), grid, block, bytes, s, sa);
+    else hipLaunchKernelGGL((k_sweep<1, 16, MASKED, TRIAL, BF16, ELASTIC>), grid, block, bytes, s, sa);
   } else {
-    if (tm == 4) hipLaunchKernelGGL((k_sweep<2, 4, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
-    else hipLaunchKernelGGL((k_sweep<2, 8, MASKED, TRIAL, BF16>), grid, block, bytes, s, sa);
+    if (tm == 4) hipLaunchKernelGGL((k_sweep<2, 4, MASKED, TRIAL, BF16, ELASTIC>), grid, block, bytes, s, sa);
+    else hipLaunchKernelGGL((k_sweep<2, 8, MASKED, TRIAL, BF16, ELASTIC>), grid, block, bytes, s, sa);
   }
   return hipGetLastError();
 }

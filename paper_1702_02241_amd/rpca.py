@@ -113,6 +113,7 @@ def lib():
             "rpca_create": (I32, [I64, I64, I32, D, D, P, ctypes.POINTER(P)]),
             "rpca_create_waves": (I32, [I64, I64, I32, D, D, P, I32, ctypes.POINTER(P)]),
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
+            "rpca_set_elastic": (I32, [P, D]),
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_certificate": (I32, [P, P, P, P, ctypes.POINTER(rpca_cert), P]),

@@ -27,11 +27,19 @@ def to_device_factor(A, device="cuda"):
 class Context:
     """Owns an rpca_ctx for one problem shape."""
 
-    def __init__(self, m, n, k, lam_s, lam_l, mask=None, waves=None):
+    def __init__(self, m, n, k, lam_s, lam_l, mask=None, waves=None, mu=0.0):
         rc, self.ctx = R.rpca_create(m, n, k, lam_s, lam_l, mask, waves)
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_create failed: {R.rpca_status_string(rc)}")
         self.m, self.n, self.k = m, n, k
+        if mu:
+            self.set_elastic(mu)
+
+    def set_elastic(self, mu):
+        """Elastic-net regulariser lam_s ||S||_1 + mu/2 ||S||_F^2 (mu = 0: l1)."""
+        rc = R.lib().rpca_set_elastic(self.ctx, float(mu))
+        if rc != R.RPCA_OK:
+            raise RuntimeError(f"rpca_set_elastic failed: {R.rpca_status_string(rc)}")
 
     def close(self):
         if self.ctx:

@@ -163,3 +163,8 @@ def test_frank_wolfe_info_layout_matches_header_order():
 def test_frank_wolfe_profile_rejects_null():
     assert R.lib().rpca_fw_profile_enable(None, 1) == R.RPCA_EINVAL
     assert R.rpca_fw_profile_read(None)[0] == R.RPCA_EINVAL
+
+
+def test_set_elastic_rejects_bad_arguments():
+    L = R.lib()
+    assert L.rpca_set_elastic(None, 0.5) == R.RPCA_EINVAL
