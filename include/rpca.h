@@ -218,6 +218,37 @@ int rpca_solve_grow(int64_t m, int64_t n, int32_t k0, int32_t k_max, double lam_
                     const uint8_t* mask, const float* X, float* U, float* V, int32_t* k_out,
                     const rpca_opts* opts, rpca_info* info, void* stream);
 
+/* Convex baseline: accelerated proximal gradient (FISTA with function-value
+ * restart) on F(L) = lam_L ||L||_* + phi(L) (eq. genConvex), the class of solvers
+ * the paper compares against (Sec. 6.1: SVT steps with a randomized SVD).  Each
+ * step takes the singular-value threshold of Z = Y - grad phi(Y) at the
+ * extrapolated point Y from a randomized SVD of Z (sketch of width rank +
+ * oversample, warm-started with the last step's right singular vectors and
+ * widened while every sketched value exceeds lam_L; power_steps subspace
+ * iterations), computed through thin products that form Z tile by tile from Y's
+ * factors and X.  Step size 1 (grad phi is 1-Lipschitz).  Stops when the
+ * relative change of F between steps is at most tol, or after max_iter steps.
+ * ctx: its k bounds the rank of an iterate (momentum needs the ranks of two
+ * iterates to fit in k, else that step is a plain one; a rank above k is
+ * truncated and reported); every entry observed (a context made with a mask:
+ * RPCA_EINVAL).  X: device.  U, V: device outputs (m x k, n x k row-major), the
+ * balanced factors L = U V^T, zero beyond the rank; start L = 0.  1 <= max_iter,
+ * tol >= 0, 0 <= oversample <= 32, 0 <= power_steps <= 8.  Blocks until done.
+ * Returns RPCA_OK (converged) or RPCA_ENOTCONV, RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP. */
+typedef struct rpca_prox_info {
+  int32_t status;           /* RPCA_OK or RPCA_ENOTCONV */
+  int32_t iters;            /* proximal steps accepted */
+  int32_t restarts;         /* momentum restarts */
+  int32_t rank;             /* rank of the returned L */
+  int32_t sketch;           /* last sketch width */
+  int32_t truncated;        /* 1 if some step had more than k values above lam_L */
+  double F;                 /* F(L) of the returned L */
+  double rel_change;        /* last relative change of F */
+  double seconds;           /* wall time of the call */
+} rpca_prox_info;
+int rpca_prox_solve(rpca_ctx* ctx, const float* X, float* U, float* V, int32_t max_iter, double tol,
+                    int32_t oversample, int32_t power_steps, uint64_t seed, rpca_prox_info* info, void* stream);
+
 /* Randomized-SVD start (Sec. 4.2): U0 = U_k S_k^{1/2}, V0 = V_k S_k^{1/2} from
  * the sketch Y = P_Omega(X) Omega_s, q power steps, B = Q^T P_Omega(X).
  * Omega_s: device, n x (k+p) row-major FP32 test matrix (p = oversample);
@@ -233,6 +264,8 @@ enum rpca_kernel_class {
   RPCA_K_UPDATE = 2,      /* L-BFGS history update (FP64 dots) */
   RPCA_K_DIRECTION = 3,   /* L-BFGS direction */
   RPCA_K_TRIAL = 4,       /* the same sweep at line-search trial points */
+  RPCA_K_LEFT = 5,        /* thin product Op W of the certificate, the rSVD and the proximal baseline */
+  RPCA_K_RIGHT = 6,       /* thin product Op^T Y (the same users) */
   RPCA_K_NCLASS = 8
 };
 

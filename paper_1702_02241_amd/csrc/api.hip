@@ -403,9 +403,30 @@ CtxView ctx_view(rpca_ctx* c) {
   v.mask = c->mask;
   v.mw = c->mw;
   v.best_F = &c->best_F;
+  v.ctx = c;
   v.phi0 = &c->phi0;
   v.phi0_X = &c->phi0_X;
   return v;
+}
+
+hipError_t prof_begin(rpca_ctx* c, hipStream_t s, void** token) {
+  *token = nullptr;
+  if (!c->prof_on) return hipSuccess;
+  hipEvent_t a = take_event(c);
+  if (!a) return hipErrorOutOfMemory;
+  *token = (void*)a;
+  return hipEventRecord(a, s);
+}
+
+hipError_t prof_end(rpca_ctx* c, int cls, hipStream_t s, void* token) {
+  if (!token) return hipSuccess;
+  hipEvent_t b = take_event(c);
+  if (!b) return hipErrorOutOfMemory;
+  const hipError_t e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  c->pending.push_back({cls, (hipEvent_t)token, b});
+  if (c->pending.size() >= 4096) prof_collect(c);
+  return hipSuccess;
 }
 
 int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V, double* f_dev,

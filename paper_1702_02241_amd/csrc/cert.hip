@@ -40,7 +40,9 @@ constexpr int BP = 8;      // columns per pass of a thin product
 constexpr int RJT = 4;     // 16-column tiles per chunk of the right sweep
 constexpr size_t LEFT_LDS_MAX = 48 * 1024;  // W and V staged in LDS up to this size
 
-enum { SRC_RESID = 0, SRC_DATA = 1 };
+// Operator sources: the gradient G = Omega .* rho'(U V^T - X) (residual), the data
+// Omega .* X, or the proximal-gradient point Z = U V^T - G (every entry observed).
+enum { SRC_RESID = 0, SRC_DATA = 1, SRC_PROX = 2 };
 
 struct GArgs {
   const float* X;
@@ -65,6 +67,13 @@ struct GArgs {
 __device__ __forceinline__ float grad_rho(float R, float lam_s, float kappa) {
   const float c = fminf(fmaxf(R, -lam_s), lam_s);
   return kappa != 0.f ? fmaf(kappa, R - c, c) : c;
+}
+
+// Operator value of one entry from the residual r = (U V^T - X)_ij and x = X_ij.
+template <int SRC>
+__device__ __forceinline__ float op_value(float r, float x, float lam_s, float kappa) {
+  const float g = grad_rho(r, lam_s, kappa);
+  return SRC == SRC_PROX ? (x + r) - g : g;
 }
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
@@ -100,7 +109,7 @@ __device__ __forceinline__ void tile_load(const GArgs& a, int64_t i0, int64_t j,
   }
   t.bits = 0xFu;
   if (MASKED) t.bits = (a.mask[jc * a.mw + (i0 >> 5)] >> ((int)(i0 & 31) + 4 * g)) & 0xFu;
-  if (SRC == SRC_RESID) {
+  if (SRC != SRC_DATA) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (q < KS) {
@@ -120,7 +129,7 @@ __device__ __forceinline__ void tile_op(const GArgs& a, const TileIn& t, int64_t
   float x[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? t.x[r] : 0.f;
-  if (SRC == SRC_RESID) {
+  if (SRC != SRC_DATA) {
     f4 acc = f4{-x[0], -x[1], -x[2], -x[3]};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -130,7 +139,7 @@ __device__ __forceinline__ void tile_op(const GArgs& a, const TileIn& t, int64_t
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) G[r] = grad_rho(acc[r], a.lam_s, a.kappa);
+    for (int r = 0; r < 4; ++r) G[r] = op_value<SRC>(acc[r], x[r], a.lam_s, a.kappa);
   } else {
 #pragma unroll
     for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -148,8 +157,8 @@ __device__ __forceinline__ void load_ua(const GArgs& a, int64_t i0, int KS, floa
   for (int q = 0; q < 8; ++q) {
     const int kk = 4 * q + g;
     float v = 0.f;
-    if (SRC == SRC_RESID && q < KS) v = a.U[i * a.k + (kk < a.k ? kk : a.k - 1)];
-    ua[q] = (SRC == SRC_RESID && q < KS && kk < a.k && i0 + c < a.m) ? v : 0.f;
+    if (SRC != SRC_DATA && q < KS) v = a.U[i * a.k + (kk < a.k ? kk : a.k - 1)];
+    ua[q] = (SRC != SRC_DATA && q < KS && kk < a.k && i0 + c < a.m) ? v : 0.f;
   }
 }
 
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
         if (idx < nw) sW[(idx / BP) * LW + idx % BP] = v[u];
       }
     }
-    if (SRC == SRC_RESID) {
+    if (SRC != SRC_DATA) {
       const int64_t nv = a.n * a.k;
       for (int64_t base = threadIdx.x; base < nv; base += 4 * THREADS) {
         float v[4];
@@ -325,7 +334,7 @@ __global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
           float x[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? xs[t][r] : 0.f;
-          if (SRC == SRC_RESID) {
+          if (SRC != SRC_DATA) {
             f4 r4 = f4{-x[0], -x[1], -x[2], -x[3]};
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
               }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) G[r] = grad_rho(r4[r], a.lam_s, a.kappa);
+            for (int r = 0; r < 4; ++r) G[r] = op_value<SRC>(r4[r], x[r], a.lam_s, a.kappa);
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -377,7 +386,7 @@ __global__ __launch_bounds__(THREADS) void k_left_lds(GArgs a) {
 
 // LDS bytes of k_left_lds for n columns and rank k (0 residual / 1 data).
 size_t left_lds_bytes(int64_t n, int k, int src) {
-  return (size_t)n * (BP + 1) * 8 + (src == SRC_RESID ? (size_t)n * k * 4 : 0);
+  return (size_t)n * (BP + 1) * 8 + (src != SRC_DATA ? (size_t)n * k * 4 : 0);
 }
 
 // Per-row-group partials of Z[:, col0 + p] = Op^T Y[:, col0 + p] over one chunk of
@@ -398,7 +407,7 @@ __global__ __launch_bounds__(THREADS) void k_right_lds(GArgs a) {
   const int rg = blockIdx.x, ch = blockIdx.y;
   const int64_t j_begin = (int64_t)ch * RJT * 16;
   const int ncols = (int)((a.n - j_begin) < RJT * 16 ? (a.n - j_begin) : RJT * 16);
-  if (SRC == SRC_RESID)
+  if (SRC != SRC_DATA)
     for (int idx = threadIdx.x; idx < ncols * a.k; idx += THREADS) sV[idx] = a.V[j_begin * a.k + idx];
   __syncthreads();
   const int64_t nstrips = (a.m + 15) >> 4;
@@ -458,7 +467,7 @@ __global__ __launch_bounds__(THREADS) void k_right_lds(GArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[r] = (jok && i0 + 4 * g + r < a.m) ? S.x[t][r] : 0.f;
         float G[4];
-        if (SRC == SRC_RESID) {
+        if (SRC != SRC_DATA) {
           f4 r4 = f4{-x[0], -x[1], -x[2], -x[3]};
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -468,7 +477,7 @@ __global__ __launch_bounds__(THREADS) void k_right_lds(GArgs a) {
             }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) G[r] = grad_rho(r4[r], a.lam_s, a.kappa);
+          for (int r = 0; r < 4; ++r) G[r] = op_value<SRC>(r4[r], x[r], a.lam_s, a.kappa);
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r) G[r] = x[r];
@@ -666,7 +675,12 @@ hipError_t left_product(const rpca::CtxView& cv, const Workspace& w, const float
     a.bw = std::min(BP, l - col0);
     const dim3 grid(w.rg_left);
     const size_t lb = left_lds_bytes(cv.n, cv.k, src);
-    if (lb <= LEFT_LDS_MAX) {
+    void* tok = nullptr;
+    if (cv.ctx && rpca::prof_begin(cv.ctx, s, &tok) != hipSuccess) return hipErrorUnknown;
+    if (src == SRC_PROX) {  // every entry observed (the caller checks)
+      if (lb <= LEFT_LDS_MAX) hipLaunchKernelGGL((k_left_lds<SRC_PROX, false>), grid, dim3(THREADS), lb, s, a);
+      else hipLaunchKernelGGL((k_left<SRC_PROX, false>), grid, dim3(THREADS), 0, s, a);
+    } else if (lb <= LEFT_LDS_MAX) {
       if (src == SRC_RESID) {
         if (cv.mask) hipLaunchKernelGGL((k_left_lds<SRC_RESID, true>), grid, dim3(THREADS), lb, s, a);
         else hipLaunchKernelGGL((k_left_lds<SRC_RESID, false>), grid, dim3(THREADS), lb, s, a);
@@ -683,6 +697,7 @@ hipError_t left_product(const rpca::CtxView& cv, const Workspace& w, const float
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (tok && rpca::prof_end(cv.ctx, RPCA_K_LEFT, s, tok) != hipSuccess) return hipErrorUnknown;
   }
   return hipSuccess;
 }
@@ -712,7 +727,11 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
     a.col0 = col0;
     a.bw = std::min(BP, l - col0);
     const dim3 grid(w.rg_right, w.nch_right);
-    if (src == SRC_RESID) {
+    void* tok = nullptr;
+    if (cv.ctx && rpca::prof_begin(cv.ctx, s, &tok) != hipSuccess) return hipErrorUnknown;
+    if (src == SRC_PROX) {  // every entry observed (the caller checks)
+      hipLaunchKernelGGL((k_right_lds<SRC_PROX, false>), grid, dim3(THREADS), 0, s, a);
+    } else if (src == SRC_RESID) {
       if (cv.mask) hipLaunchKernelGGL((k_right_lds<SRC_RESID, true>), grid, dim3(THREADS), 0, s, a);
       else hipLaunchKernelGGL((k_right_lds<SRC_RESID, false>), grid, dim3(THREADS), 0, s, a);
     } else {
@@ -721,6 +740,7 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (tok && rpca::prof_end(cv.ctx, RPCA_K_RIGHT, s, tok) != hipSuccess) return hipErrorUnknown;
     const int64_t outs = cv.n * BP;
     hipLaunchKernelGGL(k_right_reduce, dim3((unsigned)((outs + RR_OUT - 1) / RR_OUT)), dim3(THREADS), 0, s,
                        (const double*)w.part, w.rg_right, cv.n, Z, ldz, col0, a.bw);
@@ -1363,4 +1383,234 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
   if (hipMemcpyAsync(V, V0.data(), V0.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   return RPCA_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Convex baseline: accelerated proximal gradient on F(L) = lam_L ||L||_* + phi(L)
+// (the solver class the paper compares against, Sec. 6.1), with the singular-value
+// threshold computed by a randomized SVD of Z = Y - grad phi(Y) through the
+// thin products (source SRC_PROX: Z is formed tile by tile from Y's factors and
+// X, never stored).  Iterates are kept as balanced factors L = U V^T.
+
+namespace {
+
+// out (rows x k row-major) = [a P(:, 0:rp) | b Q(:, 0:rq) | 0]; P, Q rows x k row-major.
+__global__ void k_pack_factors(const float* P, int rp, float a, const float* Q, int rq, float b, int64_t rows,
+                               int k, float* out) {
+  const int64_t o = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (o >= rows * k) return;
+  const int64_t i = o / k;
+  const int cc = (int)(o % k);
+  float v = 0.f;
+  if (cc < rp) v = a * P[i * k + cc];
+  else if (cc < rp + rq) v = b * Q[i * k + (cc - rp)];
+  out[o] = v;
+}
+
+struct ProxState {
+  rpca::CtxView cv;
+  Workspace ws;
+  const float* X;
+  int oversample, power;
+  uint64_t seed;
+  int ell;                      // current sketch width
+  std::vector<double> warm;     // n x rw right singular vectors of the last step
+  int rw = 0;
+  int truncated = 0;
+  int draws = 0;
+};
+
+// One proximal step: L+ = SVT_{lam_L}(Z), Z = A B^T - grad phi(A B^T), into Uo, Vo
+// (balanced factors, k columns, zero beyond the rank).  Returns F(L+) and its rank.
+int prox_step(rpca_ctx* c, ProxState& P, const float* A, const float* B, float* Uo, float* Vo, int* rank_out,
+              double* F_out, hipStream_t s) {
+  const rpca::CtxView& cv = P.cv;
+  const Workspace& ws = P.ws;
+  const int64_t m = cv.m, n = cv.n;
+  const int k = cv.k;
+  const double lam_l = cv.lam_l;
+  const int lcap = (int)std::min<int64_t>(LMAX, std::min(m, n));
+  int rc;
+  for (;;) {
+    const int l = std::min(P.ell, lcap);
+    // sketch: the last step's right singular vectors, then Gaussian columns
+    std::vector<double> Om((size_t)n * l);
+    const int rw = std::min(P.rw, l);
+    ++P.draws;
+    for (int64_t i = 0; i < n; ++i)
+      for (int j = 0; j < l; ++j)
+        Om[(size_t)i * l + j] = j < rw ? P.warm[(size_t)i * P.rw + j]
+                                       : normal_deviate(P.seed + (uint64_t)P.draws, (uint64_t)(i * l + j));
+    if (hipMemcpyAsync(ws.Wd, Om.data(), Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    if (left_product(cv, ws, P.X, SRC_PROX, A, B, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+    if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;  // (syncs: Om may die)
+    for (int q = 0; q < P.power; ++q) {
+      if (right_product(cv, ws, P.X, SRC_PROX, A, B, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
+      if ((rc = orthonormalize_dev(ws, ws.Zd, ws.Wd, n, l, l, s))) return rc;
+      if (left_product(cv, ws, P.X, SRC_PROX, A, B, ws.Zd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+      if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+    }
+    // Z^T Q (n x l) on the host; Z ~ Q W diag(sig) (Z^T Q W diag(1/sig))^T
+    if (right_product(cv, ws, P.X, SRC_PROX, A, B, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
+    std::vector<double> Zb((size_t)n * l);
+    if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return RPCA_EHIP;
+    std::vector<double> BBt((size_t)l * l), lam(l), W((size_t)l * l);
+    rpca::la::matmul_tn(Zb.data(), Zb.data(), BBt.data(), (int)n, l, l);
+    rpca::la::sym_eig(BBt.data(), l, lam.data(), W.data());
+    int r = 0;
+    while (r < l && sqrt(std::max(lam[r], 0.0)) > lam_l) ++r;
+    if (r == l && l < lcap) {  // the sketch may miss values above the threshold: widen it
+      P.ell = std::min(2 * l, lcap);
+      continue;
+    }
+    if (r > k) {  // more singular values above lam_L than the factors hold
+      r = k;
+      P.truncated = 1;
+    }
+    // U+ = Q W_r diag(sqrt(sig - lam)), V+ = Z^T Q W_r diag(sqrt(sig - lam) / sig)
+    std::vector<double> T((size_t)l * k, 0.0);
+    std::vector<float> Vh((size_t)n * k, 0.f);
+    std::vector<double> warm((size_t)n * std::max(r, 1), 0.0);
+    double nuc = 0.0;
+    for (int j = 0; j < r; ++j) {
+      const double sig = sqrt(std::max(lam[j], 0.0));
+      const double sh = sig - lam_l;
+      nuc += sh;
+      for (int t = 0; t < l; ++t) T[(size_t)t * k + j] = W[(size_t)t * l + j] * sqrt(sh);
+      for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int t = 0; t < l; ++t) d += Zb[(size_t)i * l + t] * W[(size_t)t * l + j];
+        warm[(size_t)i * std::max(r, 1) + j] = d / sig;
+        Vh[(size_t)i * k + j] = (float)(d / sig * sqrt(sh));
+      }
+    }
+    (void)nuc;
+    if (hipMemcpyAsync(ws.T, T.data(), T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((m * k + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
+                       (const double*)ws.Yd, l, l, (const double*)ws.T, k, m, (double*)nullptr, Uo, k);
+    if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+    if (hipMemcpyAsync(Vo, Vh.data(), Vh.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    // F(L+) = phi(L+) + lam_L ||L+||_* = f(U+, V+) for balanced factors
+    if ((rc = rpca::ctx_objgrad_aux(c, P.X, Uo, Vo, ws.scal, ws.scal + 1, ws.gU, ws.gV, s))) return rc;
+    double sc[2];
+    if (hipMemcpyAsync(sc, ws.scal, sizeof(sc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)  // T, Vh and sc are host frames of this call
+      return RPCA_EHIP;
+    *F_out = sc[0];
+    *rank_out = r;
+    P.warm.swap(warm);
+    P.rw = r;
+    P.ell = std::min(std::max(r + P.oversample, 8), lcap);
+    return RPCA_OK;
+  }
+}
+
+}  // namespace
+
+namespace rpca {
+
+int prox_solve_impl(rpca_ctx* c, const float* X, float* U, float* V, int32_t max_iter, double tol,
+                    int32_t oversample, int32_t power, uint64_t seed, rpca_prox_info* info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ProxState P;
+  P.cv = rpca::ctx_view(c);
+  if (P.cv.mask) return RPCA_EINVAL;  // the proximal operator source assumes every entry observed
+  const int64_t m = P.cv.m, n = P.cv.n;
+  const int k = P.cv.k;
+  int rc = get_workspace(c, &P.ws, s);
+  if (rc) return rc;
+  P.X = X;
+  P.oversample = oversample;
+  P.power = power;
+  P.seed = seed;
+  P.ell = (int)std::min<int64_t>(std::min<int64_t>(LMAX, std::min(m, n)), std::max(16, oversample + 8));
+  // iterates: L (current), Lo (previous), Ln (new); A B^T = the extrapolated point
+  float* buf = nullptr;
+  const size_t fm = (size_t)m * k, fn = (size_t)n * k;
+  if (hipMalloc(&buf, (fm + fn) * 4 * 4) != hipSuccess) return RPCA_ENOMEM;
+  float *Uc = buf, *Vc = Uc + fm, *Uo = Vc + fn, *Vo = Uo + fm, *Un = Vo + fn, *Vn = Un + fm;
+  float *A = Vn + fn, *B = A + fm;
+  auto fail = [&](int e) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    return e;
+  };
+  if (hipMemsetAsync(buf, 0, (fm + fn) * 4 * 4, s) != hipSuccess) return fail(RPCA_EHIP);
+  int rk = 0, ro = 0, restarts = 0, it = 0;
+  // F(0) = phi(0)
+  if ((rc = rpca::ctx_objgrad_aux(c, X, Uc, Vc, P.ws.scal, P.ws.scal + 1, P.ws.gU, P.ws.gV, s))) return fail(rc);
+  double sc[2];
+  if (hipMemcpyAsync(sc, P.ws.scal, sizeof(sc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(RPCA_EHIP);
+  double F = sc[0], rel = INFINITY, t = 1.0, beta = 0.0;
+  auto pack = [&](float* out, int64_t rows, const float* Pm, int rp, float a, const float* Qm, int rq, float b) {
+    hipLaunchKernelGGL(k_pack_factors, dim3((unsigned)((rows * k + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
+                       Pm, rp, a, Qm, rq, b, rows, k, out);
+    return hipGetLastError();
+  };
+  bool converged = false;
+  for (it = 0; it < max_iter; ++it) {
+    // extrapolated point Y = (1 + beta) L - beta Lo (plain L when the ranks do not fit)
+    const bool mom = beta > 0.0 && rk + ro <= k;
+    if (pack(A, m, Uc, rk, 1.f, Uo, mom ? ro : 0, 1.f) != hipSuccess ||
+        pack(B, n, Vc, rk, (float)(mom ? 1.0 + beta : 1.0), Vo, mom ? ro : 0, (float)(-beta)) != hipSuccess)
+      return fail(RPCA_EHIP);
+    int rn = 0;
+    double Fn = 0.0;
+    if ((rc = prox_step(c, P, A, B, Un, Vn, &rn, &Fn, s))) return fail(rc);
+    if (Fn > F && mom) {  // adaptive restart: drop the momentum, plain step from L
+      ++restarts;
+      t = 1.0;
+      if (pack(A, m, Uc, rk, 1.f, Uo, 0, 1.f) != hipSuccess || pack(B, n, Vc, rk, 1.f, Vo, 0, 0.f) != hipSuccess)
+        return fail(RPCA_EHIP);
+      if ((rc = prox_step(c, P, A, B, Un, Vn, &rn, &Fn, s))) return fail(rc);
+    }
+    const double t_new = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    beta = (t - 1.0) / t_new;
+    t = t_new;
+    rel = fabs(F - Fn) / std::max(fabs(Fn), 1e-300);
+    F = Fn;
+    // rotate: Lo <- L, L <- Ln
+    std::swap(Uo, Uc);
+    std::swap(Vo, Vc);
+    std::swap(Uc, Un);
+    std::swap(Vc, Vn);
+    ro = rk;
+    rk = rn;
+    if (rel <= tol) {
+      converged = true;
+      ++it;
+      break;
+    }
+  }
+  if (hipMemcpyAsync(U, Uc, fm * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(V, Vc, fn * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(RPCA_EHIP);
+  fail(RPCA_OK);  // synchronise and free the iterates
+  if (info) {
+    info->status = converged ? RPCA_OK : RPCA_ENOTCONV;
+    info->iters = it;
+    info->restarts = restarts;
+    info->rank = rk;
+    info->sketch = P.ell;
+    info->truncated = P.truncated;
+    info->F = F;
+    info->rel_change = rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return converged ? RPCA_OK : RPCA_ENOTCONV;
+}
+
+}  // namespace rpca
+
+extern "C" int rpca_prox_solve(rpca_ctx* c, const float* X, float* U, float* V, int32_t max_iter, double tol,
+                               int32_t oversample, int32_t power_steps, uint64_t seed, rpca_prox_info* info,
+                               void* stream) {
+  if (!c || !X || !U || !V || max_iter < 1 || !(tol >= 0) || oversample < 0 || oversample > 32 ||
+      power_steps < 0 || power_steps > 8)
+    return RPCA_EINVAL;
+  return rpca::prox_solve_impl(c, X, U, V, max_iter, tol, oversample, power_steps, seed, info, (hipStream_t)stream);
 }

@@ -219,10 +219,16 @@ struct CtxView {
   const uint32_t* mask;
   int mw;
   double* best_F;
+  rpca_ctx* ctx;         // for kernel timing (prof_begin / prof_end)
   double* phi0;          // phi(0) of the current solve (NaN: unknown)
   const void** phi0_X;   // the X it belongs to
 };
 CtxView ctx_view(rpca_ctx* c);
+// Event pair around one launch when the context's kernel timing is on: begin
+// records the first event (token null when timing is off), end the second and
+// files the pair under class cls.
+hipError_t prof_begin(rpca_ctx* c, hipStream_t s, void** token);
+hipError_t prof_end(rpca_ctx* c, int cls, hipStream_t s, void* token);
 // Optional outputs of the certificate's power iteration: the top Ritz vector v of
 // M^T M (n values, P_V^perp-projected, unit norm) and the k x r map T_U with
 // U1 = U T_U (the left singular vectors of L).

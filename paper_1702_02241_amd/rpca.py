@@ -73,6 +73,12 @@ class rpca_cert(ctypes.Structure):
     ]
 
 
+class rpca_prox_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rank", ctypes.c_int32), ("sketch", ctypes.c_int32), ("truncated", ctypes.c_int32),
+                ("F", ctypes.c_double), ("rel_change", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 class rpca_fw_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("power_iters", ctypes.c_int32),
                 ("last_step", ctypes.c_int32), ("F", ctypes.c_double), ("phi", ctypes.c_double),
@@ -95,7 +101,7 @@ class rpca_fw_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
 
 
-RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION, RPCA_K_TRIAL = 0, 1, 2, 3, 4
+RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION, RPCA_K_TRIAL, RPCA_K_LEFT, RPCA_K_RIGHT = 0, 1, 2, 3, 4, 5, 6
 
 _lib = None
 
@@ -121,6 +127,7 @@ def lib():
             "rpca_solve_grow": (I32, [I64, I64, I32, I32, D, D, P, P, P, P, ctypes.POINTER(I32),
                                       ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_init_rsvd": (I32, [P, P, P, I32, I32, U64, P, P, P]),
+            "rpca_prox_solve": (I32, [P, P, P, P, I32, D, I32, I32, U64, ctypes.POINTER(rpca_prox_info), P]),
             "rpca_destroy": (None, [P]),
             "rpca_status_string": (ctypes.c_char_p, [I32]),
             "rpca_profile_enable": (I32, [P, I32]),
@@ -271,6 +278,14 @@ def rpca_fw_profile_read(h, reset=True):
     p = rpca_fw_profile()
     rc = lib().rpca_fw_profile_read(h, ctypes.byref(p), 1 if reset else 0)
     return rc, list(p.launches), list(p.ms)
+
+
+def rpca_prox_solve(ctx, X, U, V, max_iter=500, tol=1e-8, oversample=10, power_steps=1, seed=7, stream=0):
+    """Returns (status, info)."""
+    info = rpca_prox_info()
+    rc = lib().rpca_prox_solve(ctx, X, U, V, max_iter, tol, oversample, power_steps, seed, ctypes.byref(info),
+                               stream)
+    return rc, info
 
 
 def rpca_init_rsvd(ctx, X, Omega, oversample, power_steps, seed, U, V, stream=0):

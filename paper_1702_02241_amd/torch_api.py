@@ -77,6 +77,17 @@ class Context:
             raise RuntimeError(f"rpca_certificate failed: {R.rpca_status_string(rc)}")
         return cert
 
+    def prox_solve(self, Xcm, max_iter=500, tol=1e-8, oversample=10, power_steps=1, seed=7):
+        """Convex baseline (accelerated proximal gradient with randomized SVT from L = 0).
+        Returns (status, info, U (m, k), V (n, k)), L = U V^T."""
+        U = torch.empty(self.m, self.k, dtype=torch.float32, device=Xcm.device)
+        V = torch.empty(self.n, self.k, dtype=torch.float32, device=Xcm.device)
+        rc, info = R.rpca_prox_solve(self.ctx, Xcm.data_ptr(), U.data_ptr(), V.data_ptr(), max_iter, tol, oversample,
+                                     power_steps, seed, _stream())
+        if rc < 0:
+            raise RuntimeError(f"rpca_prox_solve failed: {R.rpca_status_string(rc)}")
+        return rc, info, U, V
+
     def rank_direction(self, Xcm, U, V):
         """Growth column pair at L = U V^T: (sigma, t, u_col (m,), v_col (n,))."""
         u_col = torch.empty(self.m, dtype=torch.float32, device=U.device)

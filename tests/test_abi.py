@@ -168,3 +168,19 @@ def test_frank_wolfe_profile_rejects_null():
 def test_set_elastic_rejects_bad_arguments():
     L = R.lib()
     assert L.rpca_set_elastic(None, 0.5) == R.RPCA_EINVAL
+
+
+def test_prox_solve_rejects_bad_arguments_before_hip():
+    assert R.rpca_prox_solve(None, 1, 1, 1)[0] == R.RPCA_EINVAL
+    L = R.lib()
+    info = R.rpca_prox_info()
+    import ctypes as C
+    for args in [(0, 1e-8, 10, 1), (10, -1.0, 10, 1), (10, 1e-8, 33, 1), (10, 1e-8, 10, 9)]:
+        assert L.rpca_prox_solve(C.c_void_p(1), 1, 1, 1, *args, 7, C.byref(info), None) == R.RPCA_EINVAL
+
+
+def test_prox_info_layout_matches_header_order():
+    text = open(R.HEADER_PATH).read()
+    body = re.search(r"typedef struct rpca_prox_info \{(.*?)\} rpca_prox_info;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    assert [f for f, _ in R.rpca_prox_info._fields_] == re.findall(r"(\w+)\s*;", body)
