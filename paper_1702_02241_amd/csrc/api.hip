@@ -335,6 +335,7 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->pc_dev);
   dfree(c->pc_gram);
   dfree(c->cert_ws);
+  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
   if (c->st_host) (void)hipHostFree(c->st_host);
   prof_collect(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
@@ -448,10 +449,23 @@ int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V,
 
 SolverState* ctx_state_host(rpca_ctx* c) { return c->st_host; }
 
+void* ctx_pinned(rpca_ctx* c, size_t bytes) {
+  if (c->cert_pin && c->cert_pin_bytes >= bytes) return c->cert_pin;
+  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
+  c->cert_pin = nullptr;
+  c->cert_pin_bytes = 0;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  c->cert_pin = p;
+  c->cert_pin_bytes = bytes;
+  return p;
+}
+
 void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
   *fresh = 0;
   if (c->cert_ws && c->cert_ws_bytes >= bytes) return c->cert_ws;
   dfree(c->cert_ws);
+  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
   c->cert_ws = nullptr;
   c->cert_ws_bytes = 0;
   void* p = nullptr;

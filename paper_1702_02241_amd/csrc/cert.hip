@@ -750,7 +750,27 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
   return hipSuccess;
 }
 
-// Gram of rows (synchronous; result on the host, w x w row-major).
+// Sum of the per-block Gram partials, one workgroup per entry e: out[e] = sum over
+// b of part[b ww + e] (thread b takes partials b, b + THREADS, ...; then a fixed tree).
+__global__ __launch_bounds__(THREADS) void k_gram_sum(const double* __restrict__ part, int blocks, int ww,
+                                                      double* __restrict__ out) {
+  __shared__ double red[WAVES];
+  const int e = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += THREADS) v += part[(size_t)b * ww + e];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < WAVES; ++w) t += red[w];
+    out[e] = t;
+  }
+}
+
+// Gram of rows (synchronous; result on the host, w x w row-major).  The partials
+// are summed on the device (into ws.T, free here: every user of T uploads it
+// after the Gram it is built from), so only w x w values cross to the host.
 int gram_host(const Workspace& ws, const GramArgs& ga_in, std::vector<double>& out, hipStream_t s) {
   GramArgs ga = ga_in;
   ga.part = ws.gram;
@@ -758,18 +778,18 @@ int gram_host(const Workspace& ws, const GramArgs& ga_in, std::vector<double>& o
   hipLaunchKernelGGL(k_gram, dim3(blocks), dim3(THREADS), 0, s, ga);
   if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
   const int ww = ga.w * ga.w;
-  std::vector<double> h((size_t)blocks * ww);
-  if (hipMemcpyAsync(h.data(), ws.gram, h.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_gram_sum, dim3(ww), dim3(THREADS), 0, s, (const double*)ws.gram, blocks, ww, ws.T);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
   out.assign(ww, 0.0);
-  for (int b = 0; b < blocks; ++b)
-    for (int e = 0; e < ww; ++e) out[e] += h[(size_t)b * ww + e];
+  if (hipMemcpyAsync(out.data(), ws.T, (size_t)ww * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   return RPCA_OK;
 }
 
 // Orthonormalise the columns of an FP64 device matrix (rows x l, ld) in place:
-// Q = Y W Lambda^{-1/2} from the eigen-decomposition of Y^T Y, twice.  Columns
-// in directions with eigenvalue below 1e-13 of the largest become zero.
+// Cholesky QR, twice.  With Y^T Y = L L^T (columns in order), Q = Y L^{-T}; a
+// column whose part outside the span of the previous ones has squared norm at
+// most 1e-13 of the largest squared column norm is dropped (its Q column is zero).
 int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows, int l, int ld,
                        hipStream_t s) {
   for (int pass = 0; pass < 2; ++pass) {
@@ -783,12 +803,35 @@ int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows
     std::vector<double> G;
     int rc = gram_host(ws, ga, G, s);
     if (rc) return rc;
-    std::vector<double> ev(l), W((size_t)l * l), T((size_t)l * l, 0.0);
-    rpca::la::sym_eig(G.data(), l, ev.data(), W.data());
-    const double top = std::max(ev[0], 0.0);
+    std::vector<double> Lc((size_t)l * l, 0.0), T((size_t)l * l, 0.0), x(l);
+    std::vector<char> keep(l, 0);
+    double maxd = 0.0;
+    for (int j = 0; j < l; ++j) maxd = std::max(maxd, G[(size_t)j * l + j]);
     for (int j = 0; j < l; ++j) {
-      const double sc = (ev[j] > 1e-13 * top && ev[j] > 0) ? 1.0 / sqrt(ev[j]) : 0.0;
-      for (int i = 0; i < l; ++i) T[(size_t)i * l + j] = W[(size_t)i * l + j] * sc;
+      double d = G[(size_t)j * l + j];
+      for (int t = 0; t < j; ++t) d -= Lc[(size_t)j * l + t] * Lc[(size_t)j * l + t];
+      if (!(d > 1e-13 * maxd)) continue;  // dependent: column j of L stays zero
+      keep[j] = 1;
+      const double ljj = sqrt(d);
+      Lc[(size_t)j * l + j] = ljj;
+      for (int i = j + 1; i < l; ++i) {
+        double v = G[(size_t)i * l + j];
+        for (int t = 0; t < j; ++t) v -= Lc[(size_t)i * l + t] * Lc[(size_t)j * l + t];
+        Lc[(size_t)i * l + j] = v / ljj;
+      }
+    }
+    // T = L^{-T}: row c of T is column c of L^{-1} (forward substitution over kept rows)
+    for (int c = 0; c < l; ++c) {
+      if (!keep[c]) continue;
+      std::fill(x.begin(), x.end(), 0.0);
+      x[c] = 1.0 / Lc[(size_t)c * l + c];
+      for (int i = c + 1; i < l; ++i) {
+        if (!keep[i]) continue;
+        double v = 0.0;
+        for (int t = c; t < i; ++t) v -= Lc[(size_t)i * l + t] * x[t];
+        x[i] = v / Lc[(size_t)i * l + i];
+      }
+      for (int i = 0; i < l; ++i) T[(size_t)c * l + i] = x[i];
     }
     if (hipMemcpyAsync(ws.T, T.data(), T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     const int64_t outs = rows * l;
@@ -1104,6 +1147,10 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
       }
   };
   std::vector<double> Xb((size_t)n * b), Zb, ritz(b, 0.0);
+  // pinned staging of the block copies (one in, one out per step); the stream is
+  // synchronised every step, so a step never overwrites a copy still in flight
+  double* pin = (double*)rpca::ctx_pinned(c, (size_t)2 * n * bmax * sizeof(double));
+  if (!pin) return RPCA_ENOMEM;
   for (int64_t i = 0; i < n * b; ++i) Xb[i] = normal_deviate(0xC0FFEEull, (uint64_t)i);
   int it_total = 0;
   const int max_it = 300;
@@ -1115,11 +1162,14 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
     Zb.assign((size_t)n * b, 0.0);
     for (int it = 0; it < max_it; ++it) {
       ++it_total;
-      if (hipMemcpyAsync(ws.Wd, Xb.data(), Xb.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+      memcpy(pin, Xb.data(), Xb.size() * 8);
+      if (hipMemcpyAsync(ws.Wd, pin, Xb.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
       if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, b, ws.Yd, b, b, s) != hipSuccess) return RPCA_EHIP;
       if (right_product(cv, ws, X, SRC_RESID, U, V, ws.Yd, b, ws.Zd, b, b, s) != hipSuccess) return RPCA_EHIP;
-      if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+      if (hipMemcpyAsync(pin + (size_t)n * bmax, ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return RPCA_EHIP;
       if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+      memcpy(Zb.data(), pin + (size_t)n * bmax, Zb.size() * 8);
       for (auto& z : Zb) z /= (lam_l * lam_l);
       if (r) {  // Z -= Bn (Bn^T X)
         std::vector<double> coef((size_t)r * b);

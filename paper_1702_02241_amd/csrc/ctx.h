@@ -44,6 +44,8 @@ struct rpca_ctx {
   // certificate / rSVD workspace (allocated on first use)
   void* cert_ws = nullptr;
   size_t cert_ws_bytes = 0;
+  void* cert_pin = nullptr;  // pinned host staging of the certificate's small copies
+  size_t cert_pin_bytes = 0;
   // optional per-launch timing
   struct Pending {
     int cls;
