@@ -384,6 +384,9 @@ struct rpca_fw {
   double* Z = nullptr;          // n x BLK
   double* res = nullptr;        // small device results
   double* res_host = nullptr;   // pinned copy
+  double* zpin = nullptr;       // pinned staging: Z (n x BLK doubles) in, block and v out
+  float* xpin = nullptr;        // n x BLK floats
+  float* vpin = nullptr;        // n floats
   std::vector<double> Xh;       // host copy of the block (FP64)
   int64_t rb_upd = 0, nchunks_left = 0, rc_right = 0, rc_bil = 0;
   bool x_valid = false;
@@ -450,6 +453,9 @@ void fw_free(rpca_fw* h) {
                   (void*)h->part, (void*)h->Z, (void*)h->res})
     if (p) (void)hipFree(p);
   if (h->res_host) (void)hipHostFree(h->res_host);
+  if (h->zpin) (void)hipHostFree(h->zpin);
+  if (h->xpin) (void)hipHostFree(h->xpin);
+  if (h->vpin) (void)hipHostFree(h->vpin);
   delete h;
 }
 
@@ -518,11 +524,11 @@ void orth_block(std::vector<double>& Xh, int64_t n, int b, uint64_t salt) {
     for (int q = b; q < BLK; ++q) Xh[(size_t)j * BLK + q] = 0.0;
 }
 
+// The pinned staging is rewritten only after the stream has been synchronised
+// (every power step ends with a synchronisation), so no copy from it is in flight.
 int upload_block(rpca_fw* h, hipStream_t s) {
-  std::vector<float> xf(h->Xh.size());
-  for (size_t e = 0; e < xf.size(); ++e) xf[e] = (float)h->Xh[e];
-  FWCHK(hipMemcpyAsync(h->Xb, xf.data(), xf.size() * 4, hipMemcpyHostToDevice, s));
-  FWCHK(hipStreamSynchronize(s));  // xf dies with this frame
+  for (size_t e = 0; e < h->Xh.size(); ++e) h->xpin[e] = (float)h->Xh[e];
+  FWCHK(hipMemcpyAsync(h->Xb, h->xpin, h->Xh.size() * 4, hipMemcpyHostToDevice, s));
   return RPCA_OK;
 }
 
@@ -559,8 +565,9 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
     hipLaunchKernelGGL(k_fw_right_finish, dim3((unsigned)((n * BLK + TH - 1) / TH)), dim3(TH), 0, s,
                        (const double*)h->part, h->rc_right, n * BLK, h->Z);
     FWCHK(hipGetLastError());
-    FWCHK(hipMemcpyAsync(Zh.data(), h->Z, Zh.size() * 8, hipMemcpyDeviceToHost, s));
+    FWCHK(hipMemcpyAsync(h->zpin, h->Z, Zh.size() * 8, hipMemcpyDeviceToHost, s));
     FWCHK(hipStreamSynchronize(s));
+    memcpy(Zh.data(), h->zpin, Zh.size() * 8);
     ++*steps;
     // Rayleigh-Ritz: H = Xb^T Z (b x b) = Xb^T G^T G Xb
     for (int a = 0; a < b; ++a)
@@ -588,19 +595,17 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
     const bool done = resid <= ptol || p + 1 == POWER_MAX || th0 == 0.0;
     if (done) {
       // v = Xb w0, y = Y w0 = G v, sigma = sqrt(th0)
-      std::vector<float> vf((size_t)n);
       for (int64_t j = 0; j < n; ++j) {
         double d = 0.0;
         for (int a = 0; a < b; ++a) d += h->Xh[(size_t)j * BLK + a] * W[(size_t)a * b];
-        vf[(size_t)j] = (float)d;
+        h->vpin[j] = (float)d;
       }
       Coef cw;
       for (int a = 0; a < BLK; ++a) cw.w[a] = a < b ? (float)W[(size_t)a * b] : 0.f;
-      FWCHK(hipMemcpyAsync(h->v, vf.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+      FWCHK(hipMemcpyAsync(h->v, h->vpin, (size_t)n * 4, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_fw_combine, dim3((unsigned)((m + TH - 1) / TH)), dim3(TH), 0, s, (const float*)h->Y, cw, m,
                          h->y);
       FWCHK(hipGetLastError());
-      FWCHK(hipStreamSynchronize(s));  // vf dies with this frame
       *sigma = sqrt(th0);
     }
     // next block: the Ritz-rotated Z, orthonormalised
@@ -683,7 +688,10 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_s, double lam_l, const uint8
        hipMalloc(&h->Y, (size_t)(m * BLK) * 4) == hipSuccess && hipMalloc(&h->y, (size_t)m * 4) == hipSuccess &&
        hipMalloc(&h->Xb, (size_t)(n * BLK) * 4) == hipSuccess && hipMalloc(&h->v, (size_t)n * 4) == hipSuccess &&
        hipMalloc(&h->part, (size_t)parts * 8) == hipSuccess && hipMalloc(&h->Z, (size_t)(n * BLK) * 8) == hipSuccess &&
-       hipMalloc(&h->res, 16 * 8) == hipSuccess && hipHostMalloc(&h->res_host, 16 * 8, hipHostMallocDefault) == hipSuccess;
+       hipMalloc(&h->res, 16 * 8) == hipSuccess && hipHostMalloc(&h->res_host, 16 * 8, hipHostMallocDefault) == hipSuccess &&
+       hipHostMalloc(&h->zpin, (size_t)(n * BLK) * 8, hipHostMallocDefault) == hipSuccess &&
+       hipHostMalloc(&h->xpin, (size_t)(n * BLK) * 4, hipHostMallocDefault) == hipSuccess &&
+       hipHostMalloc(&h->vpin, (size_t)n * 4, hipHostMallocDefault) == hipSuccess;
   if (ok && (hipMemset(h->y, 0, (size_t)m * 4) != hipSuccess || hipMemset(h->v, 0, (size_t)n * 4) != hipSuccess))
     ok = false;
   if (ok && mask) {
@@ -795,6 +803,8 @@ int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t ma
     fin.eta = eta;
   }
   *t_io = t;
+  // the warm-start block's upload from the pinned staging may still be in flight
+  FWCHK(hipStreamSynchronize(s));
   fin.status = (fin.gap <= tol * fin.F) ? RPCA_OK : RPCA_ENOTCONV;
   fin.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = fin;
