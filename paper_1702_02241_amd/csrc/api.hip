@@ -230,7 +230,7 @@ int rpca::create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l
   TRY(dalloc(&c->st, 1));
   TRY(dalloc(&c->dscratch, 64));
   TRY(dalloc(&c->pc_dev, (size_t)7 * k * k));
-  TRY(dalloc(&c->pc_gram, (size_t)rpca::PC_GRAM_BLOCKS * k * k));
+  TRY(dalloc(&c->pc_gram, (size_t)(rpca::PC_GRAM_BLOCKS + 1) * k * k));  // partials + their sum
   void* hp = nullptr;
   if (hipHostMalloc(&hp, sizeof(SolverState), hipHostMallocDefault) != hipSuccess) {
     rpca_destroy(c);
@@ -335,8 +335,8 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->pc_dev);
   dfree(c->pc_gram);
   dfree(c->cert_ws);
-  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
-  if (c->st_host) (void)hipHostFree(c->st_host);
+  rpca::host_free(c->cert_pin);
+  rpca::host_free(c->st_host);
   prof_collect(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   delete c;
@@ -449,11 +449,19 @@ int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V,
 
 SolverState* ctx_state_host(rpca_ctx* c) { return c->st_host; }
 
+void host_free(void* p) {
+  // a failed free must not stay pending: the next hipGetLastError would report it
+  if (p && hipHostFree(p) != hipSuccess) (void)hipGetLastError();
+}
+
 void* ctx_pinned(rpca_ctx* c, size_t bytes) {
   if (c->cert_pin && c->cert_pin_bytes >= bytes) return c->cert_pin;
-  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
+  host_free(c->cert_pin);
   c->cert_pin = nullptr;
   c->cert_pin_bytes = 0;
+  // one allocation covers the preconditioner's k x k and the certificate's
+  // 2 n x 32 staging for n up to 512
+  if (bytes < ((size_t)256 << 10)) bytes = (size_t)256 << 10;
   void* p = nullptr;
   if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
   c->cert_pin = p;
@@ -465,7 +473,6 @@ void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
   *fresh = 0;
   if (c->cert_ws && c->cert_ws_bytes >= bytes) return c->cert_ws;
   dfree(c->cert_ws);
-  if (c->cert_pin) (void)hipHostFree(c->cert_pin);
   c->cert_ws = nullptr;
   c->cert_ws_bytes = 0;
   void* p = nullptr;

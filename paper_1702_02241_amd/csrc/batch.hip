@@ -129,7 +129,7 @@ void destroy_batch(rpca_batch* b) {
   dfree(b->d_ld);
   dfree(b->d_states);
   dfree(b->d_phase);
-  if (b->h_phase) (void)hipHostFree(b->h_phase);
+  rpca::host_free(b->h_phase);
   for (int t = 0; t < BATCH_WORKERS; ++t) {
     if (b->ev_aux[t]) (void)hipEventDestroy(b->ev_aux[t]);
     if (b->aux[t]) (void)hipStreamDestroy(b->aux[t]);

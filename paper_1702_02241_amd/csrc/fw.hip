@@ -452,10 +452,9 @@ void fw_free(rpca_fw* h) {
   for (void* p : {(void*)h->mask, (void*)h->G, (void*)h->ypart, (void*)h->Y, (void*)h->y, (void*)h->Xb, (void*)h->v,
                   (void*)h->part, (void*)h->Z, (void*)h->res})
     if (p) (void)hipFree(p);
-  if (h->res_host) (void)hipHostFree(h->res_host);
-  if (h->zpin) (void)hipHostFree(h->zpin);
-  if (h->xpin) (void)hipHostFree(h->xpin);
-  if (h->vpin) (void)hipHostFree(h->vpin);
+  // a failed free must not stay pending: the caller's next error check would see it
+  for (void* p : {(void*)h->res_host, (void*)h->zpin, (void*)h->xpin, (void*)h->vpin})
+    if (p && hipHostFree(p) != hipSuccess) (void)hipGetLastError();
   delete h;
 }
 

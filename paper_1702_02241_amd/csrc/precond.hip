@@ -80,19 +80,43 @@ __global__ __launch_bounds__(TH) void k_rows_times(float* A, int64_t rows, int k
   }
 }
 
+// out[e] = sum over the blocks of part[b kk2 + e], one workgroup per entry
+// (thread-strided, then the wave tree and the waves in order: a fixed order).
+__global__ __launch_bounds__(TH) void k_gram_rows_sum(const double* part, int blocks, int kk2, double* out) {
+  __shared__ double red[TH / 64];
+  const int e = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < blocks; b += TH) v += part[(int64_t)b * kk2 + e];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < TH / 64; ++w) t += red[w];
+    out[e] = t;
+  }
+}
+
+// Gram of the rows of A (k x k, on the host).  The block partials are summed on
+// the device (into the slot after the largest partial set) and the k x k result
+// comes back through the context's pinned staging.
 int gram(rpca_ctx* c, const float* A, int64_t rows, std::vector<double>& out, hipStream_t s) {
   const int k = c->k;
+  const int kk2 = k * k;
   int64_t blocks = (rows + 63) / 64;
   if (blocks > rpca::PC_GRAM_BLOCKS) blocks = rpca::PC_GRAM_BLOCKS;
   hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)blocks), dim3(TH), 0, s, A, rows, k, c->pc_gram);
   if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
-  std::vector<double> h((size_t)blocks * k * k);
-  if (hipMemcpyAsync(h.data(), c->pc_gram, h.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  double* sum = c->pc_gram + (size_t)rpca::PC_GRAM_BLOCKS * kk2;
+  hipLaunchKernelGGL(k_gram_rows_sum, dim3((unsigned)kk2), dim3(TH), 0, s, (const double*)c->pc_gram, (int)blocks,
+                     kk2, sum);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  double* pin = (double*)rpca::ctx_pinned(c, (size_t)kk2 * sizeof(double));
+  if (!pin) return RPCA_ENOMEM;
+  if (hipMemcpyAsync(pin, sum, (size_t)kk2 * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return RPCA_EHIP;
-  out.assign((size_t)k * k, 0.0);
-  for (int64_t b = 0; b < blocks; ++b)
-    for (int e = 0; e < k * k; ++e) out[e] += h[(size_t)b * k * k + e];
+  out.assign(pin, pin + kk2);
   return RPCA_OK;
 }
 

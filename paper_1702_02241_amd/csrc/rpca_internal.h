@@ -246,8 +246,11 @@ int ctx_objgrad_aux(rpca_ctx* c, const float* X, const float* U, const float* V,
                     double* aux_dev, float* gU, float* gV, hipStream_t s);
 // Device workspace owned by the context, grown on demand; *fresh = 1 when newly allocated.
 void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh);
-// Pinned host staging owned by the context (grown on demand; null on failure).
+// Pinned host staging owned by the context (at least 256 KB, grown on demand;
+// null on failure).  Callers synchronise their copies through it before returning.
 void* ctx_pinned(rpca_ctx* c, size_t bytes);
+// hipHostFree that leaves no pending error behind when the free fails.
+void host_free(void* p);
 
 // Solve steps shared by rpca_solve and the batched solver.
 struct SolvePhase {
