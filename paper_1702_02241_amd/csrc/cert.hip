@@ -641,8 +641,13 @@ struct Workspace {
   float* zU;     // zeros m x k
   float* zV;     // zeros n x k
   double* scal;  // 16 doubles
+  // pinned host staging (the context's): [0, PIN_SMALL) Gram results and small
+  // transforms, then n x LMAX doubles (sketches, Z^T Q), then n x 32 floats
+  // (factor uploads); the certificate's power loop uses [0, 2 n x 32) on its own
+  double* pin;
   int rg_left, spw_left, rg_right, spw_right, nch_right, gram_blocks;
 };
+constexpr size_t PIN_SMALL = 4096;
 
 constexpr int LMAX = 48;
 
@@ -780,9 +785,9 @@ int gram_host(const Workspace& ws, const GramArgs& ga_in, std::vector<double>& o
   const int ww = ga.w * ga.w;
   hipLaunchKernelGGL(k_gram_sum, dim3(ww), dim3(THREADS), 0, s, (const double*)ws.gram, blocks, ww, ws.T);
   if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
-  out.assign(ww, 0.0);
-  if (hipMemcpyAsync(out.data(), ws.T, (size_t)ww * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipMemcpyAsync(ws.pin, ws.T, (size_t)ww * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  out.assign(ws.pin, ws.pin + ww);
   return RPCA_OK;
 }
 
@@ -833,14 +838,14 @@ int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows
       }
       for (int i = 0; i < l; ++i) T[(size_t)c * l + i] = x[i];
     }
-    if (hipMemcpyAsync(ws.T, T.data(), T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    memcpy(ws.pin, T.data(), T.size() * 8);
+    if (hipMemcpyAsync(ws.T, ws.pin, T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     const int64_t outs = rows * l;
     hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((outs + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
                        (const double*)Y, ld, l, (const double*)ws.T, l, rows, tmp, (float*)nullptr, ld);
     if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
     if (hipMemcpyAsync(Y, tmp, (size_t)rows * ld * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return RPCA_EHIP;
-    // T is the host source of an asynchronous copy from pageable memory: the
-    // runtime may read it after the call returns, so it must outlive the copy
+    // the pinned source of the T upload is rewritten by the next pass
     if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   }
   return RPCA_OK;
@@ -909,6 +914,8 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   w->gV = (float*)take(sz_gV);
   w->zV = (float*)take(sz_gV);
   w->scal = (double*)take(256);
+  w->pin = (double*)rpca::ctx_pinned(c, (PIN_SMALL + (size_t)n * 64) * sizeof(double));
+  if (!w->pin) return RPCA_ENOMEM;
   if (fresh) {  // zero factors used for phi(0)
     if (hipMemsetAsync(w->zU, 0, sz_gU, s) != hipSuccess) return RPCA_EHIP;
     if (hipMemsetAsync(w->zV, 0, sz_gV, s) != hipSuccess) return RPCA_EHIP;
@@ -1149,8 +1156,7 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   std::vector<double> Xb((size_t)n * b), Zb, ritz(b, 0.0);
   // pinned staging of the block copies (one in, one out per step); the stream is
   // synchronised every step, so a step never overwrites a copy still in flight
-  double* pin = (double*)rpca::ctx_pinned(c, (size_t)2 * n * bmax * sizeof(double));
-  if (!pin) return RPCA_ENOMEM;
+  double* pin = ws.pin;  // capacity PIN_SMALL + 64 n >= 2 n bmax
   for (int64_t i = 0; i < n * b; ++i) Xb[i] = normal_deviate(0xC0FFEEull, (uint64_t)i);
   int it_total = 0;
   const int max_it = 300;
@@ -1390,7 +1396,9 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
   } else {
     for (size_t i = 0; i < Om.size(); ++i) Om[i] = normal_deviate(seed, i);
   }
-  if (hipMemcpyAsync(ws.Wd, Om.data(), Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  double* pinB = ws.pin + PIN_SMALL;  // n x l
+  memcpy(pinB, Om.data(), Om.size() * 8);
+  if (hipMemcpyAsync(ws.Wd, pinB, Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
   // Y = A Omega, Q = orth(Y)
   if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
   if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
@@ -1403,8 +1411,9 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
   // B^T = A^T Q (n x l); B B^T = W Lam W^T
   if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
   std::vector<double> Zb((size_t)n * l);
-  if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipMemcpyAsync(pinB, ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  memcpy(Zb.data(), pinB, Zb.size() * 8);
   std::vector<double> BBt((size_t)l * l), lam(l), W((size_t)l * l);
   rpca::la::matmul_tn(Zb.data(), Zb.data(), BBt.data(), (int)n, l, l);
   rpca::la::sym_eig(BBt.data(), l, lam.data(), W.data());
@@ -1419,7 +1428,8 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
       TV[(size_t)i * k + j] = W[(size_t)i * l + j] * irs;
     }
   }
-  if (hipMemcpyAsync(ws.T, TU.data(), TU.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  memcpy(ws.pin, TU.data(), TU.size() * 8);
+  if (hipMemcpyAsync(ws.T, ws.pin, TU.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
   hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((m * k + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
                      (const double*)ws.Yd, l, l, (const double*)ws.T, k, m, (double*)nullptr, U, k);
   if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
@@ -1430,7 +1440,9 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
       for (int t = 0; t < l; ++t) sacc += Zb[(size_t)i * l + t] * TV[(size_t)t * k + j];
       V0[(size_t)i * k + j] = (float)sacc;
     }
-  if (hipMemcpyAsync(V, V0.data(), V0.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  float* pinC = reinterpret_cast<float*>(ws.pin + PIN_SMALL + (size_t)n * LMAX);  // n x k floats
+  memcpy(pinC, V0.data(), V0.size() * 4);
+  if (hipMemcpyAsync(V, pinC, V0.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   return RPCA_OK;
 }
@@ -1491,7 +1503,9 @@ int prox_step(rpca_ctx* c, ProxState& P, const float* A, const float* B, float* 
       for (int j = 0; j < l; ++j)
         Om[(size_t)i * l + j] = j < rw ? P.warm[(size_t)i * P.rw + j]
                                        : normal_deviate(P.seed + (uint64_t)P.draws, (uint64_t)(i * l + j));
-    if (hipMemcpyAsync(ws.Wd, Om.data(), Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    double* pinB = ws.pin + PIN_SMALL;  // n x l
+    memcpy(pinB, Om.data(), Om.size() * 8);
+    if (hipMemcpyAsync(ws.Wd, pinB, Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     if (left_product(cv, ws, P.X, SRC_PROX, A, B, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
     if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;  // (syncs: Om may die)
     for (int q = 0; q < P.power; ++q) {
@@ -1503,9 +1517,10 @@ int prox_step(rpca_ctx* c, ProxState& P, const float* A, const float* B, float* 
     // Z^T Q (n x l) on the host; Z ~ Q W diag(sig) (Z^T Q W diag(1/sig))^T
     if (right_product(cv, ws, P.X, SRC_PROX, A, B, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
     std::vector<double> Zb((size_t)n * l);
-    if (hipMemcpyAsync(Zb.data(), ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(pinB, ws.Zd, Zb.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return RPCA_EHIP;
+    memcpy(Zb.data(), pinB, Zb.size() * 8);
     std::vector<double> BBt((size_t)l * l), lam(l), W((size_t)l * l);
     rpca::la::matmul_tn(Zb.data(), Zb.data(), BBt.data(), (int)n, l, l);
     rpca::la::sym_eig(BBt.data(), l, lam.data(), W.data());
@@ -1537,11 +1552,14 @@ int prox_step(rpca_ctx* c, ProxState& P, const float* A, const float* B, float* 
       }
     }
     (void)nuc;
-    if (hipMemcpyAsync(ws.T, T.data(), T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    memcpy(ws.pin, T.data(), T.size() * 8);
+    if (hipMemcpyAsync(ws.T, ws.pin, T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((m * k + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
                        (const double*)ws.Yd, l, l, (const double*)ws.T, k, m, (double*)nullptr, Uo, k);
     if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
-    if (hipMemcpyAsync(Vo, Vh.data(), Vh.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+    float* pinC = reinterpret_cast<float*>(ws.pin + PIN_SMALL + (size_t)n * LMAX);  // n x k floats
+    memcpy(pinC, Vh.data(), Vh.size() * 4);
+    if (hipMemcpyAsync(Vo, pinC, Vh.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     // F(L+) = phi(L+) + lam_L ||L+||_* = f(U+, V+) for balanced factors
     if ((rc = rpca::ctx_objgrad_aux(c, P.X, Uo, Vo, ws.scal, ws.scal + 1, ws.gU, ws.gV, s))) return rc;
     double sc[2];
