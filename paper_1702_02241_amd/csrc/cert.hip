@@ -951,8 +951,9 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   rc = rpca::ctx_objgrad_aux(c, X, U, V, ws.scal, ws.scal + 1, ws.gU, ws.gV, s);
   if (rc) return rc;
   double scal[16];
-  if (hipMemcpyAsync(scal, ws.scal, sizeof(scal), hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipMemcpyAsync(ws.pin, ws.scal, sizeof(scal), hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  memcpy(scal, ws.pin, sizeof(scal));
   const double phiL = scal[1], g2 = scal[4];
   const double phi0 = cached ? *cv.phi0 : scal[9];
   if (cv.phi0_X) {
@@ -1112,11 +1113,14 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   int b = std::min(8, bmax);
   std::vector<double> Vh((size_t)n * k), Bh((size_t)n * k);
   {
-    std::vector<float> tmpV((size_t)n * k), tmpB((size_t)n * k);
-    if (hipMemcpyAsync(tmpV.data(), V, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
-    if (hipMemcpyAsync(tmpB.data(), ws.gV, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+    // through the pinned staging (n x LMAX doubles hold both n x k float blocks)
+    const float* tmpV = reinterpret_cast<const float*>(ws.pin + PIN_SMALL);
+    const float* tmpB = tmpV + (size_t)n * k;
+    if (hipMemcpyAsync((void*)tmpV, V, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+    if (hipMemcpyAsync((void*)tmpB, ws.gV, (size_t)n * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RPCA_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
-    for (size_t i = 0; i < tmpV.size(); ++i) {
+    for (size_t i = 0; i < (size_t)n * k; ++i) {
       Vh[i] = tmpV[i];
       Bh[i] = (double)tmpB[i] - lam_l * (double)tmpV[i];  // G^T U
     }

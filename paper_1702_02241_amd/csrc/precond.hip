@@ -187,10 +187,13 @@ int precond_refresh(rpca_ctx* c, int cur, hipStream_t s) {
       h[5 * kk2 + o] = (float)PUi[o];
       h[6 * kk2 + o] = (float)PVi[o];
     }
-  if (hipMemcpyAsync(c->pc_dev, h.data(), h.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  float* pin = (float*)rpca::ctx_pinned(c, h.size() * 4);
+  if (!pin) return RPCA_ENOMEM;
+  memcpy(pin, h.data(), h.size() * 4);
+  if (hipMemcpyAsync(c->pc_dev, pin, h.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
   if ((rc = rows_times(c, U, c->m, c->pc_dev + 5 * kk2, s))) return rc;   // A = U P_U^{-1}
   if ((rc = rows_times(c, V, c->n, c->pc_dev + 6 * kk2, s))) return rc;   // B = V P_V^{-1}
-  // the host vector dies with this frame
+  // the pinned staging is reused by the next copy through it
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   c->pc_on = true;
   return RPCA_OK;
