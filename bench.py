@@ -395,7 +395,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is the single-GPU kernel; "
-              "multi-GPU sharding is described in DESIGN.md and not built", file=sys.stderr)
+              "sharding over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -721,7 +721,7 @@ int finish_status(rpca_ctx* c, const rpca_opts& o, int certified, double rel_gap
     default: status = RPCA_OK;
   }
   if (o.certify && status != RPCA_ENONFINITE) {
-    // the certificate is the judge: a search that stalled at the rounding level of
+    // the certificate decides: a search that stalled at the rounding level of
     // the objective is a normal end when the point is certified
     if (certified) status = RPCA_OK;
     else if (status == RPCA_OK) status = RPCA_ENOTCERT;
