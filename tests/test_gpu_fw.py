@@ -146,3 +146,30 @@ def test_video_shape_one_iteration_matches_oracle():
     assert abs(tg - t4) <= 1e-5 * t4
     assert err <= 1e-4
     solver.close()
+
+
+@pytest.mark.parametrize("m,n,masked", [(90, 5, False), (64, 3, True), (37, 1, False)])
+def test_fewer_columns_than_the_power_block(m, n, masked):
+    """n < 8: the power block shrinks to n columns (zero padding in the kernels);
+    one iteration from the oracle's second iterate against the oracle's third."""
+    if masked:
+        p = synth.partial_rpca(m=m, n=n, r=1, k=1, p_obs=0.8, seed=97 + n)
+    else:
+        p = synth.gaussian_rpca(m=m, n=n, r=1, k=1, seed=97 + n, lam_s=0.3, lam_l=0.5)
+    dev = device()
+    X = f32(p.X)
+    L, t = np.zeros((m, n)), 0.0
+    for _ in range(2):
+        L, t, _ = fw.fw_iteration(L, t, X, p.lam_s, p.lam_l, p.mask)
+    L = f32(L)
+    L3, t3, st = fw.fw_iteration(L, t, X, p.lam_s, p.lam_l, p.mask)
+    solver = T.FrankWolfe(m, n, p.lam_s, p.lam_l, mask=p.mask)
+    rc, Lg, tg, info = solver.solve(_to_dev(X, dev), _to_dev(L, dev), t, max_iter=1, tol=0.0, power_tol=TIGHT)
+    Lgh = _from_dev(Lg)
+    den = max(np.linalg.norm(L3), 1e-30)
+    err = np.linalg.norm(Lgh - L3) / den
+    print(f"[fw small n {m}x{n} mask={masked}] sigma step {st['sigma']:.6f} eta {info.eta:.8f} vs {st['eta']:.8f}; "
+          f"t {tg:.9g} vs {t3:.9g}; rel L err {err:.3e}")
+    assert abs(tg - t3) <= 1e-5 * max(t3, 1e-12) + 1e-12
+    assert err <= 1e-4
+    solver.close()
