@@ -81,3 +81,21 @@ def test_masked_context_is_refused():
     Xcm = T.to_device_X(p.X, dev)
     assert R.rpca_prox_solve(ctx.ctx, Xcm.data_ptr(), U.data_ptr(), V.data_ptr())[0] == R.RPCA_EINVAL
     ctx.close()
+
+
+def test_rank_above_the_factor_capacity_is_truncated_and_reported():
+    """k = 4 factors for an optimum of rank > 4: the steps keep the top k values,
+    report it, and F stays above the convex optimum."""
+    p = synth.gaussian_rpca(m=120, n=80, r=6, k=4, seed=530, lam_s=0.3, lam_l=1.0)
+    X = f32(p.X)
+    dev = device()
+    cvx = cv.fista_svt(X, p.lam_s, p.lam_l, max_iter=20000, tol=1e-12)
+    ctx = T.Context(p.m, p.n, 4, p.lam_s, p.lam_l)
+    rc, info, U, V = ctx.prox_solve(T.to_device_X(X, dev), max_iter=60, tol=1e-9)
+    print(f"[prox truncated] status {rc} iters {info.iters} rank {info.rank} truncated {info.truncated} | F {info.F:.9g} "
+          f"vs F* {cvx['F']:.9g} (rank {cvx['rank']})")
+    assert cvx["rank"] > 4
+    assert rc in (R.RPCA_OK, R.RPCA_ENOTCONV)
+    assert info.truncated == 1 and info.rank <= 4
+    assert info.F >= cvx["F"] * (1 - 1e-9)
+    ctx.close()
