@@ -15,7 +15,12 @@ Layout (shared only as a convention with the GPU kernels, not as code):
     loss = (1/B) sum_b ||U_hat_b V_hat_b^T - T_b||_F^2
 
 Backward is written out by hand.  Adam follows Kingma & Ba with bias
-correction.  Pins: central finite differences of ``loss`` in FP64.
+correction.  Window statistics use the population standard deviation
+(divide by the frame count).  Pins (tests/test_oracle_mlp.py): central finite
+differences of ``loss`` in FP64; Adam against the closed form for a constant
+gradient at steps 1-3 and against the unrolled moment sums for varying
+gradients, with a two-step case worked by hand; the window statistics against
+a 4 x 2 pixel, two-frame case worked by hand and against explicit loops.
 """
 import numpy as np
 

@@ -13,9 +13,10 @@
 // as U1 = U T_U, V1 = V T_V (T from the eigen-decompositions of U^T U, V^T V
 // and the SVD of R_U R_V^T), every term except the last needs only k x k
 // Gram matrices of [U, G V] and [V, G^T U], which one objective sweep provides:
-//   T1 = ||I + U1^T D V1||^2,   T2 = ||D^T U1||^2 - ||U1^T D V1||^2,
-//   T3 = ||D V1||^2 - ||U1^T D V1||^2,
-// and ||P_U^perp D P_V^perp||_F^2 follows from ||G||_F^2.  T4 =
+//   T1 = ||I + U1^T D V1||^2,   T2 = ||D^T U1 - V1 C^T||^2,   T3 = ||D V1 - U1 C||^2
+// (C = U1^T D V1; T2 and T3 summed entry by entry over the n x r and m x r blocks
+// in FP64 by one thin pass each), and ||P_U^perp D P_V^perp||_F^2 follows from
+// ||G||_F^2 and the Gram traces.  T4 =
 // sum (sigma_i(P_U^perp D P_V^perp) - 1)_+^2 replaces the (m-r) x (n-r) SVD of the
 // paper by block power iteration on M^T M with M = P_U^perp D P_V^perp, applied
 // as P_V^perp (D^T D x' - B B^T x'), x' = P_V^perp x, B = D^T U1: one left and one
@@ -773,6 +774,49 @@ __global__ __launch_bounds__(THREADS) void k_gram_sum(const double* __restrict__
   }
 }
 
+// Squared Frobenius norm of a projected thin block, FP64, per-block partials:
+//   sum_i || (B_i - lam A_i) M1 - A_i M2 ||^2,   rows i < rows,
+// with A, B FP32 rows of width k (U and its gradient, or V and its gradient) and
+// M1, M2 k x r FP64 (row-major, in global memory).  B_i - lam A_i is the row of
+// G V (or G^T U) the gradient sweep carries, formed in FP64 before the product, so
+// a block that vanishes at a stationary point is summed entry by entry instead of
+// as a difference of two large traces.
+__global__ __launch_bounds__(THREADS) void k_proj_sq(int64_t rows, int k, int r, float lam, const float* A,
+                                                     const float* B, const double* M1, const double* M2,
+                                                     double* part) {
+  __shared__ double sm[2 * 32 * 32];
+  __shared__ double red[WAVES];
+  for (int idx = threadIdx.x; idx < k * r; idx += THREADS) {
+    sm[idx] = M1[idx];
+    sm[k * r + idx] = M2[idx];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x; i < rows; i += (int64_t)gridDim.x * THREADS) {
+    double a[32], d[32];  // k <= 32; fully unrolled so both stay in registers
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      a[t] = t < k ? (double)A[i * k + t] : 0.0;
+      d[t] = t < k ? (double)B[i * k + t] - (double)lam * a[t] : 0.0;
+    }
+    for (int j = 0; j < r; ++j) {
+      double y = 0.0;
+#pragma unroll
+      for (int t = 0; t < 32; ++t)
+        if (t < k) y = fma(d[t], sm[t * r + j], fma(-a[t], sm[k * r + t * r + j], y));
+      acc = fma(y, y, acc);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < WAVES; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
 // Gram of rows (synchronous; result on the host, w x w row-major).  The partials
 // are summed on the device (into ws.T, free here: every user of T uploads it
 // after the Gram it is built from), so only w x w values cross to the host.
@@ -788,6 +832,56 @@ int gram_host(const Workspace& ws, const GramArgs& ga_in, std::vector<double>& o
   if (hipMemcpyAsync(ws.pin, ws.T, (size_t)ww * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   out.assign(ws.pin, ws.pin + ww);
+  return RPCA_OK;
+}
+
+// The two projected-block norms of the certificate (synchronous):
+//   T2 = || D^T U1 - V1 C^T ||^2 (n x r),  T3 = || D V1 - U1 C ||^2 (m x r),
+// with D^T U1 = (G^T U) T_U / lam_L, D V1 = (G V) T_V / lam_L, U1 = U T_U,
+// V1 = V T_V and C = U1^T D V1 (r x r).  G V and G^T U come from the gradient rows
+// gU = G V + lam_L U, gV = G^T U + lam_L V of one sweep.
+int proj_norms_host(const Workspace& ws, int64_t m, int64_t n, int k, int r, double lam_l, const float* U,
+                    const float* V, const float* gU, const float* gV, const std::vector<double>& TU,
+                    const std::vector<double>& TV, const std::vector<double>& C, double* T2, double* T3,
+                    hipStream_t s) {
+  *T2 = *T3 = 0.0;
+  if (r == 0) return RPCA_OK;
+  const size_t kr = (size_t)k * r;
+  // pinned layout: [M1_2 | M2_2 | M1_3 | M2_3], each k x r
+  double* h = ws.pin;
+  for (int t = 0; t < k; ++t)
+    for (int j = 0; j < r; ++j) {
+      double vc = 0.0, uc = 0.0;  // (T_V C^T)[t][j], (T_U C)[t][j]
+      for (int q = 0; q < r; ++q) {
+        vc += TV[(size_t)t * r + q] * C[(size_t)j * r + q];
+        uc += TU[(size_t)t * r + q] * C[(size_t)q * r + j];
+      }
+      h[t * r + j] = TU[(size_t)t * r + j] / lam_l;
+      h[kr + t * r + j] = vc;
+      h[2 * kr + t * r + j] = TV[(size_t)t * r + j] / lam_l;
+      h[3 * kr + t * r + j] = uc;
+    }
+  double* dM = ws.T;           // 4 k r <= 4096 doubles (k <= 32)
+  double* out = ws.gram;       // two sums, then the partials of each launch
+  double* part = ws.gram + 64;
+  const int blocks = ws.gram_blocks;
+  if (hipMemcpyAsync(dM, h, 4 * kr * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_proj_sq, dim3(blocks), dim3(THREADS), 0, s, n, k, r, (float)lam_l, V, gV,
+                     (const double*)dM, (const double*)(dM + kr), part);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_gram_sum, dim3(1), dim3(THREADS), 0, s, (const double*)part, blocks, 1, out);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_proj_sq, dim3(blocks), dim3(THREADS), 0, s, m, k, r, (float)lam_l, U, gU,
+                     (const double*)(dM + 2 * kr), (const double*)(dM + 3 * kr), part + blocks);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  hipLaunchKernelGGL(k_gram_sum, dim3(1), dim3(THREADS), 0, s, (const double*)(part + blocks), blocks, 1,
+                     out + 1);
+  if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+  // stream order: the upload from h has completed before this download writes h
+  if (hipMemcpyAsync(h, out, 2 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return RPCA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+  *T2 = h[0];
+  *T3 = h[1];
   return RPCA_OK;
 }
 
@@ -1064,8 +1158,12 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
       nDV1 += DV1n[(size_t)i * r + i] / (lam_l * lam_l);
       nDtU1 += DU1n[(size_t)i * r + i] / (lam_l * lam_l);
     }
-    T2 = std::max(nDtU1 - nC, 0.0);
-    T3 = std::max(nDV1 - nC, 0.0);
+    // T2, T3 entry by entry (a difference of the traces above cancels at a
+    // stationary point, where both blocks vanish)
+    std::vector<double> Cn((size_t)r * r);
+    for (size_t e = 0; e < Cn.size(); ++e) Cn[e] = Cm[e] / lam_l;
+    const int prc = proj_norms_host(ws, m, n, k, r, lam_l, U, V, ws.gU, ws.gV, TU, TV, Cn, &T2, &T3, s);
+    if (prc) return prc;
   }
   const double nD2 = g2 / (lam_l * lam_l);
   const double normM2 = std::max(nD2 - nDtU1 - nDV1 + nC, 0.0);

@@ -12,7 +12,10 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import certificate as ce
+from oracle import lbfgs as lb
 from oracle import objective as ob
+from oracle import rsvd as rs
 from paper_1702_02241_amd import synth
 from paper_1702_02241_amd import torch_api as T
 
@@ -97,8 +100,10 @@ def test_batched_solve_bitwise_equals_single(graphs):
 
 def test_batched_solve_certifies_against_oracle():
     """cfg4-style instances (Gaussian low rank + 1-10% outliers, k = r + 5),
-    solved with the cold start and the certificate; the smallest instance's
-    solution is compared with the oracle's objective at it."""
+    solved with the cold start and the certificate.  Every instance's L = U V^T is
+    compared with the oracle's own converged L-BFGS solution (its own rSVD start):
+    ||L - L*||_F / ||L*||_F <= 1e-3, |f_oracle(U, V) - f*| / f* <= 1e-5, and the
+    oracle's exact certificate certifies the GPU's point."""
     dev = device()
     specs = [(1024, 64, 3, 0.01), (2000, 150, 7, 0.05), (1500, 300, 12, 0.1), (1200, 90, 5, 0.03)]
     ps = []
@@ -114,8 +119,21 @@ def test_batched_solve_certifies_against_oracle():
     for j, p in enumerate(ps):
         U, V = Us[j].cpu().numpy().astype(np.float64), Vs[j].cpu().numpy().astype(np.float64)
         fo = ob.objective(U, V, f32(p.X), p.lam_s, p.lam_l)
+        Om = synth.gaussian_matrix(p.n, p.k + 10, 21 + j)
+        U0, V0 = rs.rsvd_factors(p.X, p.k, Om)
+        res = lb.lbfgs(ob.make_fg(p.X, p.lam_s, p.lam_l, p.k), ob.pack(U0, V0))
+        Uo, Vo = ob.unpack(res["x"], p.m, p.n, p.k)
+        fstar = res["f"]
+        f_at = ob.objective(U, V, p.X, p.lam_s, p.lam_l)
+        eL = rel(U @ V.T, Uo @ Vo.T)
+        oc = ce.certificate(U, V, p.X, p.lam_s, p.lam_l, tau=1e-6, form="efficient")
         print(f"[batch certify] {j}: {p.m}x{p.n} k={p.k} iters {infos[j].iters} f_gpu {infos[j].f:.9g} "
-              f"f_oracle {fo:.9g} rel_gap {infos[j].rel_gap:.2e} certified {infos[j].certified}")
+              f"f_oracle(U,V) {fo:.9g} f* {fstar:.9g} rel {abs(f_at - fstar) / fstar:.2e} L rel {eL:.2e} "
+              f"gpu rel_gap {infos[j].rel_gap:.2e} oracle rel_gap {oc['rel_gap']:.2e} "
+              f"certified {infos[j].certified}")
         assert abs(infos[j].f - fo) / abs(fo) <= 1e-5
         assert infos[j].certified == 1
+        assert abs(f_at - fstar) / fstar <= 1e-5
+        assert eL <= 1e-3
+        assert oc["rel_gap"] <= 1e-3
     B.close()
