@@ -46,7 +46,8 @@ enum rpca_status {
   RPCA_EINVAL = -1,       /* bad argument (checked before any HIP call) */
   RPCA_ENOMEM = -2,       /* device or pinned allocation failed */
   RPCA_EHIP = -3,         /* a HIP runtime call failed */
-  RPCA_ENONFINITE = -4    /* objective or gradient became NaN/Inf */
+  RPCA_ENONFINITE = -4,   /* objective or gradient became NaN/Inf */
+  RPCA_ETOOBIG = -5       /* the instance exceeds the fixed scratch of rpca_objgrad_noalloc */
 };
 
 enum rpca_precision {
@@ -167,6 +168,35 @@ int rpca_objgrad(rpca_ctx* ctx, const float* X, const float* U, const float* V,
  * products, FP32 accumulation and residual, FP64 sums). */
 int rpca_objgrad_ex(rpca_ctx* ctx, const float* X, const float* U, const float* V,
                     double* f, float* gU, float* gV, int32_t precision, void* stream);
+
+/* Bytes of the device array behind rpca_objgrad_noalloc (per GPU). */
+#define RPCA_NOALLOC_SCRATCH_MB 64
+
+/* rpca_objgrad for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  No context: the
+ * instance is described by its arguments (the same rules as rpca_create:
+ * 1 <= k <= 32, k <= min(m, n), lam_S, lam_L > 0 and finite), the l1
+ * regulariser and FP32 products.  X, U, V, gU, gV, f: device, as in
+ * rpca_objgrad.  mask_bits: NULL (every entry observed) or a DEVICE bitmask,
+ * column-major: entry (i, j) is observed when bit i % 32 of word
+ * j * ceil(m / 32) + i / 32 is set.  The same kernels and the same sweep
+ * decomposition as a context made by rpca_create for these sizes, so the
+ * outputs are bitwise those of rpca_objgrad on such a context.
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call): the
+ * partial sums live in one library-owned device array of
+ * RPCA_NOALLOC_SCRATCH_MB MiB per GPU, resolved on the first call on each
+ * device and held until the process ends.  Every call on a GPU shares that
+ * GPU's array: calls in stream order are safe, calls that overlap on one GPU
+ * (two streams or two threads at once) race.  Call with the device that holds
+ * the buffers current.  Returns RPCA_EINVAL for bad arguments, RPCA_ETOOBIG when
+ * the instance's partials do not fit the array (they take
+ * 4 R n k + 8 ceil(R / 16) n k bytes for the R <= 256 workgroup rows of the
+ * default decomposition, plus 4 C m k when the n columns span C > 1 chunks of
+ * a few hundred; 2.1 MB at 76,800 x 200, k = 10), RPCA_EHIP when the array's address cannot be
+ * resolved or a launch fails. */
+int rpca_objgrad_noalloc(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
+                         const uint32_t* mask_bits, const float* X, const float* U,
+                         const float* V, double* f, float* gU, float* gV, void* stream);
 
 /* Minimise f from (U, V) with L-BFGS + strong-Wolfe line search (Sec. 5.1).
  * X: device.  U, V: device, in = start (ignored with RPCA_INIT_RSVD), out =

@@ -309,6 +309,7 @@ const char* rpca_status_string(int s) {
     case RPCA_ENOMEM: return "out of memory";
     case RPCA_EHIP: return "HIP runtime error";
     case RPCA_ENONFINITE: return "non-finite objective or gradient";
+    case RPCA_ETOOBIG: return "instance too large for the fixed scratch array";
     default: return "unknown status";
   }
 }

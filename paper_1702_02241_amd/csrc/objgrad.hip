@@ -50,6 +50,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 //     (thread-0 fence + counter over a handful of blocks) forms f and g^T d
 //     and, in solver mode, runs one step of the line search.
 __device__ __forceinline__ void reduce1_body(const FinishArgs& a, int bx, int by) {
+  // arm the second kernel's last-block counter (it also returns to zero after
+  // every completed reduction; this covers memory that starts undefined)
+  if (bx == 0 && by == 0 && threadIdx.x == 0) *a.counter = 0u;
   const int64_t nk = a.n * a.k;
   const int64_t o = (int64_t)bx * FIN_THREADS + threadIdx.x;
   if (o >= nk) return;

@@ -17,7 +17,7 @@ HEADER_PATHS = [HEADER_PATH, os.path.join(os.path.dirname(HEADER_PATH), "rpca_wa
                 os.path.join(os.path.dirname(HEADER_PATH), "rpca_fw.h")]
 
 RPCA_OK, RPCA_ENOTCONV, RPCA_ELINESEARCH, RPCA_ENOTCERT = 0, 1, 2, 3
-RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP, RPCA_ENONFINITE = -1, -2, -3, -4
+RPCA_EINVAL, RPCA_ENOMEM, RPCA_EHIP, RPCA_ENONFINITE, RPCA_ETOOBIG = -1, -2, -3, -4, -5
 RPCA_PREC_FP32, RPCA_PREC_BF16_POLISH, RPCA_PREC_BF16 = 0, 1, 2
 RPCA_INIT_GIVEN, RPCA_INIT_RSVD = 0, 1
 
@@ -121,6 +121,7 @@ def lib():
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
             "rpca_set_elastic": (I32, [P, D]),
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
+            "rpca_objgrad_noalloc": (I32, [I64, I64, I32, D, D, P, P, P, P, P, P, P, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
             "rpca_certificate": (I32, [P, P, P, P, ctypes.POINTER(rpca_cert), P]),
             "rpca_rank_direction": (I32, [P, P, P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D), P]),
@@ -201,6 +202,10 @@ def rpca_objgrad(ctx, X, U, V, f, gU, gV, stream=0):
 
 def rpca_objgrad_ex(ctx, X, U, V, f, gU, gV, precision, stream=0):
     return lib().rpca_objgrad_ex(ctx, X, U, V, f, gU, gV, precision, stream)
+
+
+def rpca_objgrad_noalloc(m, n, k, lam_s, lam_l, mask_bits, X, U, V, f, gU, gV, stream=0):
+    return lib().rpca_objgrad_noalloc(m, n, k, lam_s, lam_l, mask_bits, X, U, V, f, gU, gV, stream)
 
 
 def rpca_solve(ctx, X, U, V, opts=None, stream=0):

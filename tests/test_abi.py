@@ -184,3 +184,17 @@ def test_prox_info_layout_matches_header_order():
     body = re.search(r"typedef struct rpca_prox_info \{(.*?)\} rpca_prox_info;", text, re.S).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     assert [f for f, _ in R.rpca_prox_info._fields_] == re.findall(r"(\w+)\s*;", body)
+
+
+def test_objgrad_noalloc_rejects_bad_arguments_and_oversize_before_hip():
+    d = ctypes.c_void_p(16)
+    call = R.lib().rpca_objgrad_noalloc
+    assert call(100, 50, 0, 0.1, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(100, 50, 33, 0.1, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(10, 50, 11, 0.1, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(100, 50, 5, 0.0, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(100, 50, 5, 0.1, float("inf"), None, d, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(100, 50, 5, 0.1, 1.0, None, None, d, d, d, d, d, None) == R.RPCA_EINVAL
+    assert call(100, 50, 5, 0.1, 1.0, None, d, d, d, d, d, None, None) == R.RPCA_EINVAL
+    # many column chunks of a tall matrix: the G V partials exceed the fixed array
+    assert call(1 << 22, 1 << 14, 32, 0.1, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_ETOOBIG
