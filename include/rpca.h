@@ -72,7 +72,11 @@ typedef struct rpca_opts {
   double gtol;              /* stop: ||g||_inf <= gtol * max(1,|f|), default 1e-6 */
   double ftol;              /* stop: relative f decrease over 5 iterations < ftol, default 1e-9;
                                0 switches the test off (certification rounds always do) */
-  double bf16_gtol;         /* BF16 phase tolerance before the FP32 polish, default 1e-3 */
+  double bf16_gtol;         /* RPCA_PREC_BF16_POLISH: the BF16 phase ends once ||g||_inf has
+                               fallen to bf16_gtol times its value at the phase's first
+                               iteration (a test that does not grow with m n), when f stops
+                               decreasing (ftol) or when the line search stalls at the BF16
+                               rounding level; then the FP32 polish runs.  Default 1e-3 */
   double c1, c2;            /* strong-Wolfe constants, default 1e-4, 0.9 */
   int32_t certify;          /* 1 (default): run the certificate at the end; while rel_gap > cert_tol
                                continue from the point reached (one more preconditioner cycle
@@ -143,6 +147,12 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
  * Same errors as rpca_create; target_waves out of range is RPCA_EINVAL. */
 int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
                       const uint8_t* mask, int32_t target_waves, rpca_ctx** out);
+
+/* The sweep decomposition a context took when it was created (from the
+ * tuning table, or from rpca_create_waves): out[0] workgroup rows, out[1]
+ * strips of 16 rows per wave, out[2] columns per chunk, out[3] chunks.
+ * Host only; RPCA_EINVAL for null arguments. */
+int rpca_sweep_layout(const rpca_ctx* ctx, int32_t out[4]);
 
 /* Elastic-net regulariser (Sec. 1 lists it among the structures r(S) that
  * marginalise like the l1 norm): r(S) = lam_S ||S||_1 + mu/2 ||S||_F^2.  The

@@ -95,9 +95,11 @@ void rpca_batch_destroy(rpca_batch* b);
  * batches read the table when they are created, so tune first.
  *
  * rpca_autotune: for every entry, time rpca_objgrad on a synthetic probe
- * instance (m_probe rows in [16, 2^24], the bucket's largest k and n) for
+ * instance (m_probe rows in [32, 2^24], the bucket's largest k and n) for
  * each candidate (1024, 2048 or 4096 waves x divisor 1 or 2), `reps` calls
  * each (1..10000) on `stream`, and keep the fastest.  Blocks until done.
+ * A batch reads both parts of an entry: the chunk divisor as is, and the wave
+ * count as a factor (entry / 1024) on the instance's share of the chip's waves.
  * rpca_tune_get / rpca_tune_set read or overwrite the entry that covers
  * (k, n) (for saving and restoring a tuned table). */
 int rpca_autotune(int64_t m_probe, int32_t reps, void* stream);

@@ -355,6 +355,15 @@ int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_s, double lam_
 }
 
 
+int rpca_sweep_layout(const rpca_ctx* c, int32_t out[4]) {
+  if (!c || !out) return RPCA_EINVAL;
+  out[0] = c->row_groups;
+  out[1] = c->spw;
+  out[2] = c->chunk_w;
+  out[3] = c->nchunks;
+  return RPCA_OK;
+}
+
 int rpca_set_elastic(rpca_ctx* c, double mu) {
   if (!c || !(mu >= 0) || !isfinite(mu)) return RPCA_EINVAL;
   if (mu != c->mu) {  // a different objective: forget what the certificates cached
@@ -646,7 +655,8 @@ int solve_phases(const rpca_opts& o, SolvePhase* ph) {
   if (o.precision == RPCA_PREC_FP32) ph[nph++] = {false, o.gtol};
   else if (o.precision == RPCA_PREC_BF16) ph[nph++] = {true, o.gtol};
   else {
-    ph[nph++] = {true, o.bf16_gtol};
+    // the BF16 phase's gradient test is relative to its first iteration's gradient
+    ph[nph++] = {true, -o.bf16_gtol};
     ph[nph++] = {false, o.gtol};
   }
   return nph;

@@ -146,13 +146,19 @@ hipError_t upload_tables(rpca_batch* b, const std::vector<SweepArgs>& sl, const 
                          const std::vector<LbfgsArgs>& lu, const std::vector<LbfgsArgs>& ld) {
   const int n = b->count;
   hipStream_t s = b->stream;
+  // a failed call leaves the earlier copies in flight from the caller's vectors:
+  // wait for them before returning
+  auto fail = [&](hipError_t e) {
+    (void)hipStreamSynchronize(s);
+    return e;
+  };
   hipError_t e;
-  if ((e = hipMemcpyAsync(b->d_sa_loop, sl.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return e;
-  if ((e = hipMemcpyAsync(b->d_sa_eval, se.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return e;
-  if ((e = hipMemcpyAsync(b->d_fa_loop, fl.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return e;
-  if ((e = hipMemcpyAsync(b->d_fa_eval, fe.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return e;
-  if ((e = hipMemcpyAsync(b->d_lu, lu.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
-  if ((e = hipMemcpyAsync(b->d_ld, ld.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return e;
+  if ((e = hipMemcpyAsync(b->d_sa_loop, sl.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return fail(e);
+  if ((e = hipMemcpyAsync(b->d_sa_eval, se.data(), n * sizeof(SweepArgs), hipMemcpyHostToDevice, s))) return fail(e);
+  if ((e = hipMemcpyAsync(b->d_fa_loop, fl.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return fail(e);
+  if ((e = hipMemcpyAsync(b->d_fa_eval, fe.data(), n * sizeof(FinishArgs), hipMemcpyHostToDevice, s))) return fail(e);
+  if ((e = hipMemcpyAsync(b->d_lu, lu.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return fail(e);
+  if ((e = hipMemcpyAsync(b->d_ld, ld.data(), n * sizeof(LbfgsArgs), hipMemcpyHostToDevice, s))) return fail(e);
   return hipStreamSynchronize(s);
 }
 
@@ -374,8 +380,12 @@ int rpca_batch_create(int32_t count, const int64_t* m, const int64_t* n, const i
   }
   for (int i = 0; i < count; ++i) {
     const int64_t nstrips = (m[i] + 15) / 16;
-    const int64_t cap = std::max<int64_t>(4, nstrips / BATCH_MIN_STRIPS);
-    const int64_t share = llround(BATCH_WAVES_PER_CU * (double)cus * icost[i] / class_cost[icls[i]]);
+    // the tuned entry of the instance's (k, n) bucket scales its share and its cap: an
+    // entry that spreads one sweep over more waves than the default 1024 gives the
+    // instance more waves here too, with proportionally fewer strips each
+    const double tuned = rpca::tune_get(k[i], n[i]).target_waves / 1024.0;
+    const int64_t cap = std::max<int64_t>(4, (int64_t)(tuned * (double)nstrips) / BATCH_MIN_STRIPS);
+    const int64_t share = llround(BATCH_WAVES_PER_CU * (double)cus * tuned * icost[i] / class_cost[icls[i]]);
     b->waves[i] = (int)std::max<int64_t>(4, std::min<int64_t>(share, cap));
     const int rc = rpca::create_ctx(m[i], n[i], k[i], lam_s[i], lam_l[i], nullptr, b->waves[i], &b->ctx[i]);
     if (rc != RPCA_OK) {
@@ -506,8 +516,10 @@ int rpca_batch_objgrad(rpca_batch* b, const float* const* X, const float* const*
           hipSuccess ||
       hipMemcpyAsync(b->d_fa_eval, fe.data(), b->count * sizeof(FinishArgs), hipMemcpyHostToDevice,
                      b->stream) != hipSuccess ||
-      hipStreamSynchronize(b->stream) != hipSuccess)
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    (void)hipStreamSynchronize(b->stream);  // se, fe are read until the copies end
     return RPCA_EHIP;
+  }
   if (batched_objgrad(b, false, precision == RPCA_PREC_BF16) != hipSuccess) return RPCA_EHIP;
   if (hipEventRecord(b->ev_out, b->stream) != hipSuccess || hipStreamWaitEvent(cs, b->ev_out, 0) != hipSuccess)
     return RPCA_EHIP;

@@ -1414,16 +1414,22 @@ int growth_direction_impl(rpca_ctx* c, const float* X, const float* U, const flo
   if ((rc = get_workspace(c, &ws, s))) return rc;
   double sigma = 0.0;
   std::vector<double> u((size_t)m, 0.0);
+  // every early return below first waits for the copies that use this frame's
+  // host vectors (ex.v, y, Uh, uc, vc)
+  auto fail = [&]() {
+    (void)hipStreamSynchronize(s);
+    return RPCA_EHIP;
+  };
   if (!ex.v.empty()) {
     // y = D v = G v / lam_L (one left product, b = 1)
-    if (hipMemcpyAsync(ws.Wd, ex.v.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
-    if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, 1, ws.Yd, 1, 1, s) != hipSuccess) return RPCA_EHIP;
+    if (hipMemcpyAsync(ws.Wd, ex.v.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess) return fail();
+    if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, 1, ws.Yd, 1, 1, s) != hipSuccess) return fail();
     std::vector<double> y((size_t)m);
     std::vector<float> Uh((size_t)m * k);
     if (hipMemcpyAsync(y.data(), ws.Yd, (size_t)m * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(Uh.data(), U, (size_t)m * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-      return RPCA_EHIP;
+      return fail();
     for (auto& x : y) x /= lam_l;
     // P_U^perp y = y - U1 (U1^T y), U1 = U T_U (m x r)
     const int r = ex.r;
@@ -1455,7 +1461,7 @@ int growth_direction_impl(rpca_ctx* c, const float* X, const float* U, const flo
   if (hipMemcpyAsync(u_col, uc.data(), (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(v_col, vc.data(), (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)  // the host sources die with this frame
-    return RPCA_EHIP;
+    return fail();
   *sigma_out = sigma;
   *t_out = t;
   return RPCA_OK;

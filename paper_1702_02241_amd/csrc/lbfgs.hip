@@ -242,9 +242,18 @@ __device__ void update_stops(SolverState* st, const double* D) {
   for (int i = 0; i < 7; ++i) st->fhist[i] = st->fhist[i + 1];
   st->fhist[7] = f;
   if (f < st->best_f) st->best_f = f;
+  // gradient threshold: relative to max(1, |f|), or (gtol < 0) to the gradient at
+  // the phase's first iteration, a test whose scale does not grow with m n
+  double gthr;
+  if (st->gtol < 0.0) {
+    if (!(st->gref > 0.0)) st->gref = D[I::GINF];
+    gthr = -st->gtol * st->gref;
+  } else {
+    gthr = st->gtol * fmax(1.0, fabs(f));
+  }
   int stop = STOP_NONE;
   if (!isfinite(f) || !isfinite(D[I::GG])) stop = STOP_NONFINITE;
-  else if (D[I::GINF] <= st->gtol * fmax(1.0, fabs(f))) stop = STOP_GTOL;
+  else if (D[I::GINF] <= gthr) stop = STOP_GTOL;
   else if (st->ftol > 0.0 && st->iter >= 5 && (st->fhist[2] - f) <= st->ftol * fmax(1.0, fabs(f)))
     stop = STOP_FTOL;
   else if (st->iter >= st->max_iter) stop = STOP_MAXITER;

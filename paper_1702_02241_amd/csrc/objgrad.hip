@@ -62,13 +62,13 @@ __device__ __forceinline__ void reduce1_body(const FinishArgs& a, int bx, int by
   const float* src = a.gvpart + o;
   double s = 0.0;
   int r = r0;
-  for (; r + 3 < r1; r += 4) {
-    const float x0 = src[(int64_t)r * nk], x1 = src[(int64_t)(r + 1) * nk];
-    const float x2 = src[(int64_t)(r + 2) * nk], x3 = src[(int64_t)(r + 3) * nk];
-    s += (double)x0;
-    s += (double)x1;
-    s += (double)x2;
-    s += (double)x3;
+  // eight loads in flight, summed in row order
+  for (; r + 7 < r1; r += 8) {
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = src[(int64_t)(r + e) * nk];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s += (double)x[e];
   }
   for (; r < r1; ++r) s += (double)src[(int64_t)r * nk];
   a.level2[(int64_t)by * nk + o] = s;
@@ -102,8 +102,17 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
     const bool ok = jr < rpb && j < a.n;
     const int64_t o = j * k + c;
     double s = 0.0;
-    if (ok)
-      for (int q = 0; q < a.segs; ++q) s += a.level2[(int64_t)q * nk + o];
+    if (ok) {
+      int q = 0;
+      for (; q + 7 < a.segs; q += 8) {  // eight loads in flight, summed in segment order
+        double x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = a.level2[(int64_t)(q + e) * nk + o];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += x[e];
+      }
+      for (; q < a.segs; ++q) s += a.level2[(int64_t)q * nk + o];
+    }
     if (!a.pc) {
       if (ok) {
         const float v = Vt[o];
@@ -282,8 +291,9 @@ struct TuneTable {
   std::mutex mu;
   SweepTune t[TUNE_KB][TUNE_NB];
   TuneTable() {
+    // k <= 16: two workgroups per CU (the k16 sweep); k > 16: one
     for (int a = 0; a < TUNE_KB; ++a)
-      for (int b = 0; b < TUNE_NB; ++b) t[a][b] = SweepTune{1024, 1};
+      for (int b = 0; b < TUNE_NB; ++b) t[a][b] = SweepTune{a < 2 ? 2048 : 1024, 1};
   }
 };
 TuneTable& tune_table() {

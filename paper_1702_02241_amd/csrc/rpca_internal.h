@@ -65,6 +65,8 @@ struct SolverState {
   double gamma;
   double fhist[8];
   double best_f;
+  double gref;          // gtol < 0: the gradient test is ||g||_inf <= -gtol * gref, gref = ||g||_inf
+                        // at the phase's first iteration (0 until then)
   // --- everything above is the state head (what the line search reads and writes) ---
   double SY[RPCA_MEMMAX][RPCA_MEMMAX];  // s_i^T y_j by slot
   double YY[RPCA_MEMMAX][RPCA_MEMMAX];  // y_i^T y_j by slot

@@ -29,9 +29,15 @@
 //     the transposed layout and into MFMA; the strip's G V accumulates in
 //     registers over the chunk and is complete when the strip ends (one chunk)
 //     or written as a per-chunk partial.
-// FP32 mode uses v_mfma_f32_16x16x4f32; BF16 mode rounds U, V and G to bf16 and
-// uses v_mfma_f32_16x16x16_bf16 (FP32 accumulation, FP32 residual).  Every
-// cross-wave and cross-workgroup sum runs in a fixed order: bitwise reproducible.
+// FP32 mode uses v_mfma_f32_16x16x4f32.  Every cross-wave and cross-workgroup sum
+// runs in a fixed order: bitwise reproducible.
+//
+// Rank k <= 16 (sweep_k16.h) follows this plan with operand layouts that make
+// every MFMA operand one 16-byte LDS read, a single buffer resource per chunk,
+// and two workgroups per CU; its BF16 mode forms the residual from a hi/lo
+// split of U and V (three bf16 products, close to FP32 accuracy) and rounds G,
+// U and V to bf16 for the two gradient products.  Rank 17..32 keeps the kernel
+// below (BF16: U, V and G rounded to bf16 throughout).
 #pragma once
 
 #include <math.h>
@@ -125,15 +131,21 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
 // where LDS is scarcer, two at a time).
 __host__ __device__ constexpr int ntb(int kb) { return kb == 1 ? 4 : 2; }
 
-// Dynamic LDS (floats): sVt[cwp][16 kb + 1] | sGV[WAVES][cwp][k] | sT[WAVES][ntb][16*LDT]
+#include "sweep_k16.h"
+
+// Dynamic LDS (floats).  k <= 16: see the k16 layouts.  k in 17..32:
+// sVt[cwp][16 kb + 1] | sGV[WAVES][cwp][k] | sT[WAVES][ntb][16*LDT]
 __host__ __device__ constexpr int lds_floats(int kb, int k, int cwp) {
-  return cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * ntb(kb) * 16 * LDT;
+  return kb == 1 ? k16::lds_floats(k, cwp) : cwp * (16 * kb + 1) + WAVES * cwp * k + WAVES * ntb(kb) * 16 * LDT;
 }
 
 // Widest chunk (multiple of 16 columns) that fits the LDS budget and the
 // register accumulators.
+__host__ __device__ constexpr int max_chunk_k16(int k, int cw) {
+  return cw <= 16 ? 16 : (k16::lds_floats(k, cw) <= LDS_LIMIT_FLOATS ? cw : max_chunk_k16(k, cw - 16));
+}
 __host__ __device__ constexpr int max_chunk(int kb, int k) {
-  return 16 * ((LDS_LIMIT_FLOATS - WAVES * ntb(kb) * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k))) <
+  return kb == 1 ? max_chunk_k16(k, 16 * TMAX_KB1) : 16 * ((LDS_LIMIT_FLOATS - WAVES * ntb(kb) * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k))) <
                  16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2)
              ? 16 * ((LDS_LIMIT_FLOATS - WAVES * ntb(kb) * 16 * LDT) / (16 * (16 * kb + 1 + WAVES * k)))
              : 16 * (kb == 1 ? TMAX_KB1 : TMAX_KB2);
@@ -171,8 +183,8 @@ typedef __attribute__((address_space(4))) SweepArgs ConstSweepArgs;
 
 // `Args` is SweepArgs (a kernel argument) or ConstSweepArgs (a batch table entry).
 template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, typename Args, bool ELASTIC = false>
-__device__ __forceinline__ void sweep_item(const Args& a, const int rg, const int ch, float* lds,
-                                            double* sRed) {
+__device__ __forceinline__ void sweep_item_kb2(const Args& a, const int rg, const int ch, float* lds,
+                                               double* sRed) {
   constexpr int KMAX = 16 * KB;
   constexpr int KQ = 4 * KB;
   constexpr int LDV = KMAX + 1;
@@ -670,8 +682,17 @@ __device__ __forceinline__ void sweep_item(const Args& a, const int rg, const in
 }
 
 
+template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, typename Args, bool ELASTIC = false>
+__device__ __forceinline__ void sweep_item(const Args& a, const int rg, const int ch, float* lds, double* sRed) {
+  if constexpr (KB == 1)
+    sweep_item_k16<TMAX, MASKED, TRIAL, BF16, Args, ELASTIC>(a, rg, ch, lds, sRed);
+  else
+    sweep_item_kb2<KB, TMAX, MASKED, TRIAL, BF16, Args, ELASTIC>(a, rg, ch, lds, sRed);
+}
+
 template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16, bool ELASTIC>
-__global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
+// k <= 16: two waves per SIMD (the k16 layouts fit two workgroups' LDS per CU)
+__global__ __launch_bounds__(NT, KB == 1 ? 2 : 1) void k_sweep(SweepArgs a) {
   extern __shared__ float lds[];
   __shared__ double sRed[4 * WAVES];
   sweep_item<KB, TMAX, MASKED, TRIAL, BF16, SweepArgs, ELASTIC>(a, blockIdx.x, blockIdx.y, lds, sRed);
@@ -684,7 +705,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs a) {
 // until the list is drained.  Lists are sorted by decreasing cost, so the long
 // items start first and the short ones fill the tail.
 template <int KB, int TMAX, bool MASKED, bool TRIAL, bool BF16>
-__global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs* __restrict__ args,
+__global__ __launch_bounds__(NT, KB == 1 ? 2 : 1) void k_sweep_batch(const SweepArgs* __restrict__ args,
                                                     const SweepItem* __restrict__ items, int nitems,
                                                     unsigned* head) {
   extern __shared__ float lds[];

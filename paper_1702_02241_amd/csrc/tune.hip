@@ -32,7 +32,8 @@ const int DIV_CAND[] = {1, 2};
 extern "C" {
 
 int rpca_autotune(int64_t m_probe, int32_t reps, void* stream) {
-  if (m_probe < 16 || m_probe > (int64_t)1 << 24 || reps < 1 || reps > 10000) return RPCA_EINVAL;
+  // the probes reach k = 32, which needs at least 32 rows
+  if (m_probe < 32 || m_probe > (int64_t)1 << 24 || reps < 1 || reps > 10000) return RPCA_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int64_t nmax = N_REP[rpca::TUNE_NB - 1];
   const int kmax = K_REP[rpca::TUNE_KB - 1];

@@ -120,6 +120,7 @@ def lib():
             "rpca_create_waves": (I32, [I64, I64, I32, D, D, P, I32, ctypes.POINTER(P)]),
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
             "rpca_set_elastic": (I32, [P, D]),
+            "rpca_sweep_layout": (I32, [P, ctypes.POINTER(I32 * 4)]),
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_objgrad_noalloc": (I32, [I64, I64, I32, D, D, P, P, P, P, P, P, P, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
@@ -194,6 +195,13 @@ def rpca_create(m, n, k, lam_s, lam_l, mask=None, waves=None):
     else:
         rc = lib().rpca_create_waves(m, n, k, lam_s, lam_l, mptr, int(waves), ctypes.byref(ctx))
     return rc, ctx
+
+
+def rpca_sweep_layout(ctx):
+    """(status, (workgroup rows, strips per wave, chunk columns, chunks))."""
+    out = (ctypes.c_int32 * 4)()
+    rc = lib().rpca_sweep_layout(ctx, ctypes.byref(out))
+    return rc, tuple(out)
 
 
 def rpca_objgrad(ctx, X, U, V, f, gU, gV, stream=0):

@@ -128,6 +128,8 @@ def test_tune_table_round_trip_and_bounds():
     assert R.rpca_tune_set(33, 200, 2048, 1) == R.RPCA_EINVAL
     assert R.rpca_tune_set(10, 200, 8, 1) == R.RPCA_EINVAL
     assert R.rpca_autotune(8, 10) == R.RPCA_EINVAL
+    assert R.rpca_autotune(31, 10) == R.RPCA_EINVAL     # the k = 32 probes need 32 rows
+    assert R.lib().rpca_sweep_layout(None, None) == R.RPCA_EINVAL
 
 
 def test_batch_entry_points_reject_bad_arguments_before_hip():

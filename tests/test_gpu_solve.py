@@ -60,17 +60,24 @@ def test_bf16_polish_solve_matches_oracle(small):
     ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
     Xcm = T.to_device_X(p.X, dev)
     U, V = T.to_device_factor(U0, dev), T.to_device_factor(V0, dev)
-    rc, info = ctx.solve(Xcm, U, V, precision=1, certify=1)
-    torch.cuda.synchronize()
-    Ug, Vg = U.cpu().numpy().astype(np.float64), V.cpu().numpy().astype(np.float64)
-    eL = rel(Ug @ Vg.T, Us @ Vs.T)
-    f_at = ob.objective(Ug, Vg, p.X, p.lam_s, p.lam_l)
-    print(f"[solve bf16+polish] rc={rc} iters={info.iters} (bf16 {info.iters_bf16}) evals={info.evals} "
-          f"L rel={eL:.2e} f rel={abs(f_at - fstar) / fstar:.2e} rel_gap={info.rel_gap:.2e}")
-    assert rc >= 0 and info.certified == 1
-    assert info.iters_bf16 > 0
-    assert eL <= 1e-4
-    assert abs(f_at - fstar) / fstar <= 1e-5
+    runs = []
+    for bf16_gtol in (1e-2, 1e-3, 0.0):   # the default relative test; BF16 until the phase stalls
+        U.copy_(T.to_device_factor(U0, dev))
+        V.copy_(T.to_device_factor(V0, dev))
+        rc, info = ctx.solve(Xcm, U, V, precision=1, certify=1, bf16_gtol=bf16_gtol)
+        torch.cuda.synchronize()
+        Ug, Vg = U.cpu().numpy().astype(np.float64), V.cpu().numpy().astype(np.float64)
+        eL = rel(Ug @ Vg.T, Us @ Vs.T)
+        f_at = ob.objective(Ug, Vg, p.X, p.lam_s, p.lam_l)
+        print(f"[solve bf16+polish bf16_gtol={bf16_gtol:g}] rc={rc} iters={info.iters} "
+              f"(bf16 {info.iters_bf16}) evals={info.evals} L rel={eL:.2e} "
+              f"f rel={abs(f_at - fstar) / fstar:.2e} rel_gap={info.rel_gap:.2e}", flush=True)
+        runs.append((bf16_gtol, rc, info.certified, info.iters, info.iters_bf16, eL, abs(f_at - fstar) / fstar))
+    for bf16_gtol, rc, cert, iters, iters_bf16, eL, ef in runs:
+        assert rc >= 0 and cert == 1
+        assert eL <= 1e-4 and ef <= 1e-5
+    # run to its own stall, the BF16 phase carries at least half of the iterations
+    assert runs[-1][4] >= 0.5 * runs[-1][3]
 
 
 def fp32_floor(p, U, V, r):
@@ -81,8 +88,12 @@ def fp32_floor(p, U, V, r):
     its operands: delta ~ 4 * 2^-24 * x_rms, x_rms the RMS of X over those entries.  D V1
     sums such errors against unit columns, so each of its m r entries moves by about
     delta / lam_L, and likewise the n r entries of D^T U1: the two blocks' squared norms
-    grow by about (m + n) r delta^2 / lam_L^2 and E by its square root.  Returns
-    (E floor, per-term floor), each doubled for margin."""
+    grow by about (m + n) r delta^2 / lam_L^2 and E by its square root.  The FP32
+    accumulation of the products G V and G^T U over their n (resp. m) terms adds
+    rounding of the same order, whose constant depends on the sweep's decomposition
+    (measured at a 76,800 x 200 optimum: a T3 difference of 1.75 times the
+    residual-only estimate).  Returns (E floor, per-term floor), each four times
+    the residual-only estimate."""
     L = np.asarray(U, np.float64) @ np.asarray(V, np.float64).T
     R = L - p.X
     inl = np.abs(R) <= p.lam_s
@@ -91,7 +102,7 @@ def fp32_floor(p, U, V, r):
     x_rms = float(np.sqrt(np.mean(p.X[inl] ** 2))) if inl.any() else 0.0
     delta = 4.0 * 2.0 ** -24 * x_rms
     t = (p.m + p.n) * max(r, 1) * (delta / p.lam_l) ** 2
-    return 2.0 * np.sqrt(t), 2.0 * t
+    return 4.0 * np.sqrt(t), 4.0 * t
 
 
 def test_certificate_matches_oracle_exact(small):
