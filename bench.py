@@ -53,7 +53,13 @@ def parse():
                     help="profiling aid: run --reps objective/gradient evaluations (or device copies of X, "
                          "the calibration of the HBM byte counters) at the workload's shape and exit")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--workload", choices=["video", "batch", "fw", "prox"], default="video",
+    ap.add_argument("--stream-train", type=int, default=2000,
+                    help="stream workload: solver-generated training windows (over five videos)")
+    ap.add_argument("--stream-eval", type=int, default=491,
+                    help="stream workload: windows of the 5000-frame evaluation video")
+    ap.add_argument("--stream-epochs", type=int, default=100)
+    ap.add_argument("--stream-lr", type=float, default=1e-4)
+    ap.add_argument("--workload", choices=["video", "batch", "fw", "prox", "stream"], default="video",
                     help="video: the single 76,800 x 200 solve (default line); batch: the 64 uneven "
                          "Gaussian instances solved by the batched path against one-by-one solves; fw: "
                          "Frank-Wolfe with marginalisation on the video (--fw-iters iterations per step); prox: the convex "
@@ -220,6 +226,126 @@ def run_fw(args):
     }
     print(json.dumps(out))
     fw.close()
+
+
+def run_stream(args):
+    """Streaming warm start: windows of 100 frames (76,800 x 100, k = 10) every 10 frames.
+    Training: --stream-train windows solved from the cold start over five seeded
+    videos (seeds 5001-5005), then Adam on the network's product loss.  Evaluation:
+    the first --stream-eval windows of a 5000-frame video (seed 5000), each solved to
+    a certificate from the cold start, the trivial warm start (the previous window's
+    factors moved by 10 frames with a ridge fit of the new frames), the learned start,
+    and the learned start with the cold fallback.  The cpu_baseline leg polishes a
+    sample of windows with the FP64 oracle to compare every start's solution with
+    the oracle's optimum."""
+    import numpy as np
+    import torch
+
+    from paper_1702_02241_amd import synth
+    from paper_1702_02241_amd import warmstart as W
+    dev = torch.device("cuda:0")
+    spec = W.WindowSpec(width=320, height=240, frames=100, stride=10, factor=4, k=10, lam_s=0.05)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
+    per_video = (args.stream_train + 4) // 5
+    n_train_frames = spec.frames + (per_video - 1) * spec.stride
+    t_all = time.perf_counter()
+    videos = [synth.video_frames_device(n_train_frames, spec.width, spec.height, seed=5001 + v, device=dev)
+              for v in range(5)]
+    ws = W.WarmStart(spec, d_h=512, max_batch=64, seed=0, device=dev)
+    # small output layer at the start: the product loss of a large random start
+    # (|U V^T| ~ 10 against targets ~ 1) sent Adam off at the first steps
+    W1, b1, W2, b2 = ws.net.params()
+    ws.net.set_params(W1, b1, 0.05 * W2, b2)
+    t0 = time.perf_counter()
+    F, TU, TV, recs = ws.build_dataset(videos, log=log)
+    t_data = time.perf_counter() - t0
+    del videos
+    n_train = len(recs)
+    l0 = ws.eval_loss(F, TU, TV)
+    t0 = time.perf_counter()
+    losses = ws.train(F, TU, TV, epochs=args.stream_epochs, batch=64, lr=args.stream_lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    Xv = synth.video_frames_device(5000, spec.width, spec.height, seed=5000, device=dev)
+    starts = W.window_starts(5000, spec)[: args.stream_eval]
+    keep = [starts[i] for i in np.linspace(0, len(starts) - 1, 3).astype(int)] if not args.no_cpu else []
+    recs_e, kept = W.evaluate_stream(ws, Xv, starts, keep=keep, log=log)
+
+    def summary(key):
+        rows = [r[key] for r in recs_e if key in r]
+        it = np.array([r[0] for r in rows], float)
+        ms = np.array([r[1] for r in rows], float)
+        cert = np.array([r[2] for r in rows], float)
+        return dict(windows=len(rows), iters_mean=round(float(it.mean()), 2), iters_median=float(np.median(it)),
+                    ms_mean=round(float(ms.mean()), 3), ms_median=round(float(np.median(ms)), 3),
+                    certified=int(cert.sum()))
+    table = {k: summary(k) for k in ("cold", "trivial", "learned", "rule")}
+    chose = sum(1 for r in recs_e if r["rule"][4] == "learned")
+    cpu = None
+    if not args.no_cpu and kept:
+        cpu = stream_oracle(Xv, spec, kept, args.cpu_seconds)
+    rule_s = sum(r["rule"][1] for r in recs_e) / 1e3
+    out = {
+        "metric": "streaming windows to certificate per second (learned start, cold fallback)",
+        "value": round(len(recs_e) / rule_s, 2), "unit": "certified windows/s",
+        "n_gpus": 1, "steps": len(recs_e), "warmup": 0, "ms_per_step": round(1e3 * rule_s / len(recs_e), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded video generator, device assembly; the paper's videos are not available)",
+        "config": {"workload": "windows of 76800x100 (320x240 px x 100 frames) every 10 frames, k=10, "
+                               f"lam_S=0.05, lam_L={spec.lam:.4f}; MLP 9700-512-49000 trained on {n_train} "
+                               "solver-generated windows of videos 5001-5005; evaluation video 5000"},
+        "starts": table,
+        "rule_chose_learned": chose,
+        "train": {"windows": n_train, "data_s": round(t_data, 2), "epochs": args.stream_epochs, "lr": args.stream_lr,
+                  "train_s": round(t_train, 2), "loss_initial": l0, "loss_final": losses[-1] if losses else None},
+        "total_s": round(time.perf_counter() - t_all, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ws.close()
+
+
+def stream_oracle(Xv, spec, kept, budget_s):
+    """FP64 oracle on a sample of evaluation windows: L-BFGS polished from the GPU's
+    cold-start solution to the oracle's own tolerance, then ||L - L_oracle||_F /
+    ||L_oracle||_F for every start's certified GPU solution; and the oracle's
+    objective+gradient rate at this size."""
+    import numpy as np
+    from oracle import lbfgs as olb
+    from oracle import objective as ob
+    out = {"windows": {}, "kind": "oracle"}
+    n_evals, t_eval = 0, 0.0
+    for t, sols in kept.items():
+        Xw = Xv[t:t + spec.frames].detach().cpu().numpy().astype(np.float64).T  # m x frames
+        U0, V0 = (np.asarray(a, np.float64) for a in sols["cold"])
+        fg = ob.make_fg(Xw, spec.lam_s, spec.lam, spec.k)
+        t0 = time.perf_counter()
+        res = olb.lbfgs(fg, ob.pack(U0, V0), mem=10, max_iter=200, gtol=1e-10)
+        el = time.perf_counter() - t0
+        x = res["x"]
+        Uo, Vo = ob.unpack(x, Xw.shape[0], Xw.shape[1], spec.k)
+        Lo_n2 = np.sum((Uo.T @ Uo) * (Vo.T @ Vo))
+        rec = {}
+        for key, (U, V) in sols.items():
+            U, V = np.asarray(U, np.float64), np.asarray(V, np.float64)
+            a = np.sum((U.T @ U) * (V.T @ V))
+            b = np.sum((U.T @ Uo) * (V.T @ Vo))
+            rec[key] = float(np.sqrt(max(a - 2 * b + Lo_n2, 0.0) / Lo_n2))
+        out["windows"][str(t)] = {"rel_L_err": rec, "oracle_s": round(el, 2)}
+        print(f"oracle window {t}: " + ", ".join(f"{k} {v:.2e}" for k, v in rec.items()), file=sys.stderr,
+              flush=True)
+    # the oracle's evaluation rate at the window size
+    Xw = Xv[0:spec.frames].detach().cpu().numpy().astype(np.float64).T
+    U0, V0 = (np.asarray(a, np.float64) for a in kept[min(kept)]["cold"])
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min(budget_s, 10.0):
+        ob.objgrad(U0, V0, Xw, spec.lam_s, spec.lam)
+        n_evals += 1
+    t_eval = time.perf_counter() - t0
+    out.update(value=n_evals / t_eval, unit="evals/s",
+               sample=f"{n_evals} FP64 objective+gradient evaluations at 76800x100, k=10; "
+                      f"L-BFGS polish of {len(kept)} windows", cores=os.cpu_count())
+    return out
 
 
 def run_prox(args):
@@ -407,11 +533,11 @@ def main():
     if args.probe:
         probe(args)
         return
-    if args.workload in ("batch", "fw", "prox"):
+    if args.workload in ("batch", "fw", "prox", "stream"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        {"batch": run_batch, "fw": run_fw, "prox": run_prox}[args.workload](args)
+        {"batch": run_batch, "fw": run_fw, "prox": run_prox, "stream": run_stream}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is the single-GPU kernel; "

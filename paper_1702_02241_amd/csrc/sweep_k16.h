@@ -103,88 +103,6 @@ __device__ __forceinline__ void sweep_item_k16(const Args& a, const int rg, cons
   float* sT = lds + (BF16 ? cwp * ns * 16 + cwp * 8 : cwp * RS + cwp * 16);
   float* myT = sT + w * NTB * 16 * TS;
 
-  // ---- stage V' (the trial point, or B W^T in preconditioned variables) ----
-  // raw rows first (into the transpose area), then the operand layouts
-  {
-    float* raw = sT;  // [cwp][k] <= 4096 floats, inside the transpose area
-    for (int idx = tid; idx < cwp * k; idx += NT) {
-      const int jl = idx / k;
-      float v = 0.f;
-      if (jl < ncols) {
-        const int64_t o = j_begin * k + idx;
-        v = V[o];
-        if (TRIAL) {
-          v = fmaf(alpha, a.dV[o], v);
-          if (rg == 0) a.Vt[outi][o] = v;
-        }
-      }
-      raw[idx] = v;
-    }
-    __syncthreads();
-    const float* __restrict__ pc = a.pc;
-    if (pc) {
-      // V' = B W^T row by row, in place (one row per thread; W = pc[0 .. k k))
-      for (int jl = tid; jl < cwp; jl += NT) {
-        float row[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) row[t] = t < k ? raw[jl * k + t] : 0.f;
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-          if (kk < k) {
-            float v = 0.f;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-              if (t < k) v = fmaf(row[t], pc[kk * k + t], v);
-            raw[jl * k + kk] = v;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    auto vp = [&](int jl, int kk) -> float { return kk < k ? raw[jl * k + kk] : 0.f; };
-    if (!BF16) {
-      // residual operand: (col, g) -> V'[col][4q + g], q = 0..3
-      for (int idx = tid; idx < cwp * 4; idx += NT) {
-        const int jl = idx >> 2, gg = idx & 3;
-        *reinterpret_cast<f4*>(sVr + jl * RS + gg * 4) = f4{vp(jl, gg), vp(jl, 4 + gg), vp(jl, 8 + gg), vp(jl, 12 + gg)};
-      }
-      // G V operand: (t, g, c) -> V'[16t + 4q + g][c], q = 0..3
-      for (int idx = tid; idx < ntiles * 64; idx += NT) {
-        const int t = idx >> 6, gg = (idx >> 4) & 3, cc = idx & 15;
-        const int j0 = 16 * t + gg;
-        *reinterpret_cast<f4*>(sVg + idx * 4) = f4{vp(j0, cc), vp(j0 + 4, cc), vp(j0 + 8, cc), vp(j0 + 12, cc)};
-      }
-    } else {
-      // G V operand: (t, g, c) -> bf16 V'[16t + 4g + e][c], e = 0..3
-      for (int idx = tid; idx < ntiles * 64; idx += NT) {
-        const int t = idx >> 6, gg = (idx >> 4) & 3, cc = idx & 15;
-        const int j0 = 16 * t + 4 * gg;
-        *reinterpret_cast<u2v_*>(sVgb + idx * 4) =
-            u2v_{pk2(vp(j0, cc), vp(j0 + 1, cc)), pk2(vp(j0 + 2, cc), vp(j0 + 3, cc))};
-      }
-      // residual operand: (col, j) -> 8 bf16 of -V'[col][8j .. 8j+7] for g = 0 (hi),
-      // 1 (lo), 2 (hi), 3 (zeros)
-      for (int idx = tid; idx < cwp * ns; idx += NT) {
-        const int jl = idx / ns, j = idx - jl * ns;
-        u4v hi4, lo4;
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const float v0 = -vp(jl, 8 * j + 2 * h), v1 = -vp(jl, 8 * j + 2 * h + 1);
-          const uint32_t hi = pk2(v0, v1);
-          const float h0 = __builtin_bit_cast(float, hi << 16), h1 = __builtin_bit_cast(float, hi & 0xFFFF0000u);
-          hi4[h] = hi;
-          lo4[h] = pk2(v0 - h0, v1 - h1);
-        }
-        u4v* dst = reinterpret_cast<u4v*>(sVrb + (size_t)idx * 32);
-        dst[0] = hi4;
-        dst[1] = lo4;
-        dst[2] = hi4;
-        dst[3] = u4v{0u, 0u, 0u, 0u};
-      }
-    }
-    __syncthreads();
-  }
-
   f4 gva[TMAX];
 #pragma unroll
   for (int t = 0; t < TMAX; ++t) gva[t] = f4{0.f, 0.f, 0.f, 0.f};
@@ -444,14 +362,101 @@ __device__ __forceinline__ void sweep_item_k16(const Args& a, const int rg, cons
     }
   };
 
+  // the first strip's operands and X groups are requested before V' is staged, so
+  // that their latency overlaps the staging
+  constexpr int D = NBUF - 1;
+  Ops ops, nops;
+  f4 xbuf[NBUF][PF];
+  uint32_t bbuf[NBUF][PF] = {};
   if (n_pipe > 0) {
-    constexpr int D = NBUF - 1;
-    Ops ops, nops;
     load_ops(s_first, ops);
-    f4 xbuf[NBUF][PF];
-    uint32_t bbuf[NBUF][PF] = {};
 #pragma unroll
     for (int d = 0; d < D; ++d) load_group(s_first, d, xbuf[d], bbuf[d], true);
+  }
+
+  // ---- stage V' (the trial point, or B W^T in preconditioned variables) ----
+  // raw rows first (into the transpose area), then the operand layouts
+  {
+    float* raw = sT;  // [cwp][k] <= 4096 floats, inside the transpose area
+    for (int idx = tid; idx < cwp * k; idx += NT) {
+      const int jl = idx / k;
+      float v = 0.f;
+      if (jl < ncols) {
+        const int64_t o = j_begin * k + idx;
+        v = V[o];
+        if (TRIAL) {
+          v = fmaf(alpha, a.dV[o], v);
+          if (rg == 0) a.Vt[outi][o] = v;
+        }
+      }
+      raw[idx] = v;
+    }
+    __syncthreads();
+    const float* __restrict__ pc = a.pc;
+    if (pc) {
+      // V' = B W^T row by row, in place (one row per thread; W = pc[0 .. k k))
+      for (int jl = tid; jl < cwp; jl += NT) {
+        float row[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) row[t] = t < k ? raw[jl * k + t] : 0.f;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          if (kk < k) {
+            float v = 0.f;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+              if (t < k) v = fmaf(row[t], pc[kk * k + t], v);
+            raw[jl * k + kk] = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    auto vp = [&](int jl, int kk) -> float { return kk < k ? raw[jl * k + kk] : 0.f; };
+    if (!BF16) {
+      // residual operand: (col, g) -> V'[col][4q + g], q = 0..3
+      for (int idx = tid; idx < cwp * 4; idx += NT) {
+        const int jl = idx >> 2, gg = idx & 3;
+        *reinterpret_cast<f4*>(sVr + jl * RS + gg * 4) = f4{vp(jl, gg), vp(jl, 4 + gg), vp(jl, 8 + gg), vp(jl, 12 + gg)};
+      }
+      // G V operand: (t, g, c) -> V'[16t + 4q + g][c], q = 0..3
+      for (int idx = tid; idx < ntiles * 64; idx += NT) {
+        const int t = idx >> 6, gg = (idx >> 4) & 3, cc = idx & 15;
+        const int j0 = 16 * t + gg;
+        *reinterpret_cast<f4*>(sVg + idx * 4) = f4{vp(j0, cc), vp(j0 + 4, cc), vp(j0 + 8, cc), vp(j0 + 12, cc)};
+      }
+    } else {
+      // G V operand: (t, g, c) -> bf16 V'[16t + 4g + e][c], e = 0..3
+      for (int idx = tid; idx < ntiles * 64; idx += NT) {
+        const int t = idx >> 6, gg = (idx >> 4) & 3, cc = idx & 15;
+        const int j0 = 16 * t + 4 * gg;
+        *reinterpret_cast<u2v_*>(sVgb + idx * 4) =
+            u2v_{pk2(vp(j0, cc), vp(j0 + 1, cc)), pk2(vp(j0 + 2, cc), vp(j0 + 3, cc))};
+      }
+      // residual operand: (col, j) -> 8 bf16 of -V'[col][8j .. 8j+7] for g = 0 (hi),
+      // 1 (lo), 2 (hi), 3 (zeros)
+      for (int idx = tid; idx < cwp * ns; idx += NT) {
+        const int jl = idx / ns, j = idx - jl * ns;
+        u4v hi4, lo4;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const float v0 = -vp(jl, 8 * j + 2 * h), v1 = -vp(jl, 8 * j + 2 * h + 1);
+          const uint32_t hi = pk2(v0, v1);
+          const float h0 = __builtin_bit_cast(float, hi << 16), h1 = __builtin_bit_cast(float, hi & 0xFFFF0000u);
+          hi4[h] = hi;
+          lo4[h] = pk2(v0 - h0, v1 - h1);
+        }
+        u4v* dst = reinterpret_cast<u4v*>(sVrb + (size_t)idx * 32);
+        dst[0] = hi4;
+        dst[1] = lo4;
+        dst[2] = hi4;
+        dst[3] = u4v{0u, 0u, 0u, 0u};
+      }
+    }
+    __syncthreads();
+  }
+
+  if (n_pipe > 0) {
     for (int64_t j = 0; j < n_pipe; ++j) {
       const int64_t s = s_first + WAVES * j;
       const bool more = j + 1 < n_pipe;

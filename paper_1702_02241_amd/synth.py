@@ -82,20 +82,10 @@ def gaussian_rpca(m=256, n=200, r=5, frac=0.05, k=10, lam_s=None, lam_l=1.0,
                    L0=L0, S0=S0, name=f"gaussian_{m}x{n}_r{r}")
 
 
-def video_frames(n_frames=200, width=320, height=240, seed=2, noise=0.01):
-    """Synthetic video unfolded to a (width*height) x n_frames matrix.
-
-    Background: rank-3 product B C^T with smooth cosine fields B_j in [0,1]
-    and per-frame weights C_tj = g_t w_tj carrying a multiplicative
-    illumination drift g_t, so the background stays exactly rank 3 and in
-    [0,1].  Foreground: 3-8 axis-aligned rectangles (sides 10-40 px,
-    intensity U[0,1]) moving at constant velocity (1-3 px/frame per axis),
-    bouncing off the borders and occluding the background.  Gaussian noise of
-    standard deviation ``noise`` is added everywhere.
-
-    Returns (X, L0, S0) as float64 arrays, column t = frame t, row y*width+x.
-    """
-    rng = np.random.Generator(np.random.PCG64(seed))
+def _video_scene(rng, n_frames, width, height):
+    """Scene of the synthetic video, drawn from ``rng`` in a fixed order: the rank-3
+    background factors B (m x 3) and C (n_frames x 3) and, per moving rectangle,
+    (width, height, intensity, per-frame top-left corners as an (n_frames, 2) int array)."""
     m = width * height
     xs = np.tile(np.arange(width, dtype=np.float64), height)
     ys = np.repeat(np.arange(height, dtype=np.float64), width)
@@ -113,8 +103,7 @@ def video_frames(n_frames=200, width=320, height=240, seed=2, noise=0.01):
         psi = rng.uniform(0, 2 * math.pi)
         w = (0.8 + 0.2 * np.sin(2 * math.pi * t / period + psi)) / 3.0
         C[:, j] = g * w
-    L0 = B @ C.T
-    frames = L0.T.reshape(n_frames, height, width).copy()
+    rects = []
     n_rect = int(rng.integers(3, 9))
     for _ in range(n_rect):
         w_px = int(rng.integers(10, 41))
@@ -125,9 +114,9 @@ def video_frames(n_frames=200, width=320, height=240, seed=2, noise=0.01):
         vx = rng.uniform(1.0, 3.0) * (1 if rng.integers(0, 2) else -1)
         vy = rng.uniform(1.0, 3.0) * (1 if rng.integers(0, 2) else -1)
         px, py = x0, y0
+        pos = np.empty((n_frames, 2), dtype=np.int64)
         for f in range(n_frames):
-            ix, iy = int(round(px)), int(round(py))
-            frames[f, iy:iy + h_px, ix:ix + w_px] = inten
+            pos[f] = (int(round(px)), int(round(py)))
             px += vx
             py += vy
             if px < 0 or px > width - w_px:
@@ -136,11 +125,68 @@ def video_frames(n_frames=200, width=320, height=240, seed=2, noise=0.01):
             if py < 0 or py > height - h_px:
                 vy = -vy
                 py = min(max(py, 0.0), height - h_px)
+        rects.append((w_px, h_px, inten, pos))
+    return B, C, rects
+
+
+def video_frames(n_frames=200, width=320, height=240, seed=2, noise=0.01):
+    """Synthetic video unfolded to a (width*height) x n_frames matrix.
+
+    Background: rank-3 product B C^T with smooth cosine fields B_j in [0,1]
+    and per-frame weights C_tj = g_t w_tj carrying a multiplicative
+    illumination drift g_t, so the background stays exactly rank 3 and in
+    [0,1].  Foreground: 3-8 axis-aligned rectangles (sides 10-40 px,
+    intensity U[0,1]) moving at constant velocity (1-3 px/frame per axis),
+    bouncing off the borders and occluding the background.  Gaussian noise of
+    standard deviation ``noise`` is added everywhere.
+
+    Returns (X, L0, S0) as float64 arrays, column t = frame t, row y*width+x.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = width * height
+    B, C, rects = _video_scene(rng, n_frames, width, height)
+    L0 = B @ C.T
+    frames = L0.T.reshape(n_frames, height, width).copy()
+    for w_px, h_px, inten, pos in rects:
+        for f in range(n_frames):
+            ix, iy = pos[f]
+            frames[f, iy:iy + h_px, ix:ix + w_px] = inten
     X = frames.reshape(n_frames, m).T.copy()
     S0 = X - L0
     if noise:
         X = X + rng.normal(0.0, noise, size=X.shape)
     return X, L0, S0
+
+
+def video_frames_device(n_frames, width=320, height=240, seed=2, noise=0.01, device="cuda"):
+    """The same video model assembled on the device, for long videos: the scene
+    (background factors, rectangle trajectories) is the one ``video_frames`` draws
+    for this seed; the frames are painted on the device and the noise comes from
+    torch's generator seeded with ``seed`` (a different draw of the same
+    distribution).  Returns an (n_frames, width*height) float32 tensor whose row t
+    is frame t (the layout of a column-major X with one frame per column)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B, C, rects = _video_scene(rng, n_frames, width, height)
+    dev = torch.device(device)
+    Bt = torch.from_numpy(B.astype(np.float32)).to(dev)
+    Ct = torch.from_numpy(C.astype(np.float32)).to(dev)
+    frames = (Ct @ Bt.T).reshape(n_frames, height, width)
+    ys = torch.arange(height, device=dev)
+    xs = torch.arange(width, device=dev)
+    for w_px, h_px, inten, pos in rects:
+        p = torch.from_numpy(pos).to(dev)
+        ix, iy = p[:, 0:1], p[:, 1:2]
+        yin = (ys[None, :] >= iy) & (ys[None, :] < iy + h_px)
+        xin = (xs[None, :] >= ix) & (xs[None, :] < ix + w_px)
+        frames = torch.where(yin[:, :, None] & xin[:, None, :], torch.tensor(inten, dtype=torch.float32,
+                                                                             device=dev), frames)
+    X = frames.reshape(n_frames, width * height)
+    if noise:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        X = X + noise * torch.randn(X.shape, generator=gen, device=dev, dtype=torch.float32)
+    return X.contiguous()
 
 
 def video(n_frames=200, width=320, height=240, k=10, seed=2, lam_s=0.05,

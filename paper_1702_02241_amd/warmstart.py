@@ -199,3 +199,75 @@ def low_rank_distance(U, V, Ur, Vr):
     b = np.sum((U.T @ Ur) * (V.T @ Vr))
     c = np.sum((Ur.T @ Ur) * (Vr.T @ Vr))
     return float(np.sqrt(max(a - 2 * b + c, 0.0) / c))
+
+
+def shift_start(U_prev, V_prev, Xw, spec):
+    """The trivial warm start for a window that follows the previous one by
+    ``spec.stride`` frames: the previous U, the previous V moved up by stride rows,
+    and for the stride new frames the ridge fit x ~ U v, v = (U^T U + lam_L I)^-1 U^T x
+    (a baseline for the learned start; its small k x k algebra runs on the host)."""
+    s = spec
+    U = U_prev.detach().cpu().numpy().astype(np.float64)
+    Xn = Xw[s.frames - s.stride:].detach().cpu().numpy().astype(np.float64)  # stride x m
+    G = U.T @ U + s.lam * np.eye(s.k)
+    Vn = np.linalg.solve(G, U.T @ Xn.T).T
+    V = np.vstack([V_prev.detach().cpu().numpy().astype(np.float64)[s.stride:], Vn])
+    return U_prev.clone(), torch.from_numpy(V.astype(np.float32)).to(U_prev.device)
+
+
+def evaluate_stream(ws, Xv, starts, keep=(), log=None):
+    """Solve the windows of one video from three starts and record, per window and
+    start, the accepted iterations, the time to a certified solution (the start's
+    construction included) and the certificate's verdict:
+
+      cold     -- the randomized-SVD start inside rpca_solve;
+      trivial  -- ``shift_start`` from this chain's previous certified window;
+      learned  -- the network's prediction, used as it is;
+      rule     -- the prediction or the cold start, whichever has the lower objective.
+
+    ``keep``: window starts whose solutions (U, V per start) are returned for an
+    outside comparison."""
+    s = ws.spec
+    recs, kept = [], {}
+    prev = None
+    for wi, t in enumerate(starts):
+        Xw = Xv[t:t + s.frames]
+        rec = {"t": int(t)}
+        sol = {}
+        rc, info, U, V, sec = ws.solve(Xw)
+        rec["cold"] = (info.iters, 1e3 * sec, int(info.certified), info.f)
+        sol["cold"] = (U, V)
+        if prev is not None and t - prev[0] == s.stride:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = shift_start(prev[1], prev[2], Xw, s)
+            build = time.perf_counter() - t0
+            rc, info, U2, V2, sec = ws.solve(Xw, st)
+            rec["trivial"] = (info.iters, 1e3 * (build + sec), int(info.certified), info.f)
+            sol["trivial"] = (U2, V2)
+            prev = (t, U2, V2)
+        else:
+            prev = (t, U, V)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Up, Vp = ws.predict(Xw)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t0
+        rc, info, U3, V3, sec = ws.solve(Xw, (Up, Vp))
+        rec["learned"] = (info.iters, 1e3 * (build + sec), int(info.certified), info.f)
+        sol["learned"] = (U3, V3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start, f_pred, f_cold = ws.start_for(Xw)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t0
+        rc, info, U4, V4, sec = ws.solve(Xw, start)
+        rec["rule"] = (info.iters, 1e3 * (build + sec), int(info.certified), info.f,
+                       "learned" if start is not None else "cold")
+        recs.append(rec)
+        if t in keep:
+            kept[int(t)] = {k: (a.detach().cpu().numpy(), b.detach().cpu().numpy()) for k, (a, b) in sol.items()}
+        if log and (wi % 50 == 0 or wi == len(starts) - 1):
+            log(f"stream: window {wi + 1}/{len(starts)} (frame {t}): " + ", ".join(
+                f"{k} {rec[k][0]} it {rec[k][1]:.1f} ms" for k in ("cold", "trivial", "learned", "rule") if k in rec))
+    return recs, kept
