@@ -42,7 +42,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp32", "bf16_polish"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16_polish"], default="fp32",
+                    help="fp32 (default): FP32 products throughout; bf16_polish: BF16 products until the "
+                         "BF16 phase stalls, then the FP32 polish and the certificate.  The line also "
+                         "times the other precision on the same seeds")
     ap.add_argument("--precond", type=int, choices=[0, 1], default=1,
                     help="1 (default): L-BFGS in preconditioned variables with certification rounds; "
                          "0: the paper's plain L-BFGS (memory 10)")
@@ -59,7 +62,7 @@ def parse():
                     help="stream workload: windows of the 5000-frame evaluation video")
     ap.add_argument("--stream-epochs", type=int, default=100)
     ap.add_argument("--stream-lr", type=float, default=1e-4)
-    ap.add_argument("--workload", choices=["video", "batch", "fw", "prox", "stream"], default="video",
+    ap.add_argument("--workload", choices=["video", "batch", "fw", "prox", "stream", "partial"], default="video",
                     help="video: the single 76,800 x 200 solve (default line); batch: the 64 uneven "
                          "Gaussian instances solved by the batched path against one-by-one solves; fw: "
                          "Frank-Wolfe with marginalisation on the video (--fw-iters iterations per step); prox: the convex "
@@ -132,8 +135,43 @@ def run_batch(args):
         "one_by_one_certified": int(sum(i.certified for i in seq)),
         "speedup_vs_one_by_one": round(t_seq / t_batch, 3),
         "sweep_items": lay.sweep_items, "sweep_classes": lay.sweep_classes, "graphs": lay.graphs,
+        "cpu_baseline": None if args.no_cpu else batch_oracle(specs, infos, args.cpu_seconds),
     }
     print(json.dumps(out))
+
+
+def batch_oracle(specs, infos, budget_s):
+    """FP64 oracle on a sample of the batch: seconds per objective+gradient evaluation
+    of four instances spread over the sizes, fitted as seconds per matrix entry and
+    extrapolated to the whole batch with each instance's GPU evaluation count."""
+    import numpy as np
+    from oracle import objective as ob
+    from paper_1702_02241_amd import synth
+    order = sorted(range(len(specs)), key=lambda i: specs[i][0] * specs[i][1])
+    pick = [order[int(q * (len(order) - 1))] for q in (0.0, 0.33, 0.67, 1.0)]
+    per_entry, sample = [], []
+    t_all = time.perf_counter()
+    for i in pick:
+        m, n, r, k, frac, seed = specs[i]
+        p = synth.gaussian_rpca(m=m, n=n, r=r, frac=frac, k=k, seed=seed, lam_s=1.0 / np.sqrt(max(m, n)), lam_l=1.0)
+        U, V = synth.random_factors(m, n, k, 5, scale=0.3)
+        ob.objgrad(U, V, p.X, p.lam_s, p.lam_l)
+        reps, t0 = 0, time.perf_counter()
+        while reps < 3 or (time.perf_counter() - t0 < budget_s / 8 and reps < 50):
+            ob.objgrad(U, V, p.X, p.lam_s, p.lam_l)
+            reps += 1
+        sec = (time.perf_counter() - t0) / reps
+        per_entry.append(sec / (m * n))
+        sample.append(f"{m}x{n} k={k}: {1e3 * sec:.1f} ms")
+    spe = float(np.median(per_entry))
+    total = sum(info.evals * spe * specs[i][0] * specs[i][1] for i, info in enumerate(infos))
+    return dict(kind="oracle", value=round(1.0 / (spe * sum(s[0] * s[1] for s in specs)), 4),
+                unit="batch objective+gradient passes/s", cores=os.cpu_count(),
+                sample="FP64 objective+gradient per evaluation: " + "; ".join(sample)
+                       + f" ({time.perf_counter() - t_all:.1f} s)",
+                time_to_certificate_s_extrapolated=round(total, 1),
+                extrapolation="each instance's GPU evaluation count x the oracle's seconds per entry (median of "
+                              "the sample) x its m n")
 
 
 def run_fw(args):
@@ -222,6 +260,8 @@ def run_fw(args):
         "kernel_ms_per_step": per,
         "roofline": roofline,
         "mfma": mfma,
+        "roofline_bf16": roofline_bf16,
+        "other_precision": comparison,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -348,6 +388,109 @@ def stream_oracle(Xv, spec, kept, budget_s):
     return out
 
 
+def run_partial(args):
+    """Partially observed stable PCA at full size: m = n = 8192, rank 20, 5 % outliers,
+    noise 1e-3, Bernoulli(0.3) observation mask, k = 25, lam_S = 1/sqrt(8192), lam_L = 1.
+    Steps: objective/gradient rate (FP32 and BF16 products), certified solves from the
+    rSVD start (FP32 and BF16 + polish), the FP64 oracle's objective/gradient at one
+    point against the GPU's (parity at full size) and its time per evaluation, with the
+    oracle's time to a certificate extrapolated from the GPU solve's evaluation count."""
+    import numpy as np
+    import torch
+
+    from paper_1702_02241_amd import rpca as R
+    from paper_1702_02241_amd import synth
+    from paper_1702_02241_amd import torch_api as T
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    p = synth.partial_rpca()
+    t_gen = time.perf_counter() - t0
+    print(f"partial: generated {p.m}x{p.n} in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    Xcm = T.to_device_X(p.X, dev)
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l, p.mask)
+    U = torch.empty(p.m, p.k, dtype=torch.float32, device=dev)
+    V = torch.empty(p.n, p.k, dtype=torch.float32, device=dev)
+    rates = {}
+    U0, V0 = ctx.init_rsvd(Xcm)
+    for name, prec in (("fp32", R.RPCA_PREC_FP32), ("bf16", R.RPCA_PREC_BF16)):
+        R.rpca_profile_enable(ctx.ctx, True)
+        R.rpca_profile_read(ctx.ctx, reset=True)
+        for _ in range(20):
+            ctx.objgrad(Xcm, U0, V0, prec)
+        torch.cuda.synchronize()
+        _, pr = R.rpca_profile_read(ctx.ctx, reset=True)
+        R.rpca_profile_enable(ctx.ctx, False)
+        rates[name] = dict(sweep_us=round(1e3 * pr.ms[R.RPCA_K_SWEEP] / max(pr.launches[R.RPCA_K_SWEEP], 1), 2),
+                           finish_us=round(1e3 * pr.ms[R.RPCA_K_FINISH] / max(pr.launches[R.RPCA_K_FINISH], 1), 2))
+    solves = {}
+    for name, prec in (("fp32", R.RPCA_PREC_FP32), ("bf16_polish", R.RPCA_PREC_BF16_POLISH)):
+        ctx.solve(Xcm, U, V, init=R.RPCA_INIT_RSVD, seed=99, precision=prec)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = ctx.solve(Xcm, U, V, init=R.RPCA_INIT_RSVD, seed=1, precision=prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        solves[name] = dict(status=rc, ms=round(1e3 * el, 2), iters=info.iters, iters_bf16=info.iters_bf16,
+                            evals=info.evals, cert_rounds=info.cert_rounds, certified=info.certified,
+                            rel_gap=info.rel_gap, f=info.f)
+        print(f"partial: {name} solve {solves[name]}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        cpu = partial_oracle(p, ctx, Xcm, U0, V0, solves["fp32"]["evals"])
+    # algorithmic bytes of one evaluation in the dense layout: X, the mask bits, U, V, gU
+    alg_bytes = 4 * p.m * p.n + p.m * p.n / 8 + 4 * (2 * p.m * p.k + p.n * p.k)
+    sw = rates["fp32"]["sweep_us"]
+    out = {
+        "metric": "time to certified solution, partially observed 8192x8192 (p=0.3), k=25",
+        "value": round(1e3 / solves["fp32"]["ms"], 3), "unit": "certified solutions/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": solves["fp32"]["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator)",
+        "config": {"workload": "m=n=8192, rank-20 Gaussian L0, 5% outliers U[-10,10], noise 1e-3, "
+                               "Bernoulli(0.3) mask, k=25, lam_S=1/sqrt(8192), lam_L=1, rSVD start"},
+        "objgrad": rates, "solves": solves,
+        "roofline": dict(bound="hbm", kernel="k_sweep (masked, k=25)", kernel_ms=sw / 1e3,
+                         achieved=round(alg_bytes / (sw * 1e-6) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(alg_bytes / (sw * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), traffic=None,
+                         alg_bytes_per_launch=alg_bytes),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def partial_oracle(p, ctx, Xcm, U0, V0, gpu_evals):
+    """FP64 oracle at full size: objective/gradient at the rSVD start against the GPU's
+    (relative errors), seconds per evaluation, and 20 L-BFGS iterations timed; the
+    oracle's time to certificate is extrapolated from the GPU solve's evaluations."""
+    import numpy as np
+    import torch
+    from oracle import lbfgs as olb
+    from oracle import objective as ob
+    f, gU, gV = ctx.objgrad(Xcm, U0, V0)
+    torch.cuda.synchronize()
+    Uh = U0.cpu().numpy().astype(np.float64)
+    Vh = V0.cpu().numpy().astype(np.float64)
+    X32 = np.asarray(p.X, np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    fr, gUr, gVr = ob.objgrad(Uh, Vh, X32, p.lam_s, p.lam_l, p.mask)
+    t_eval = time.perf_counter() - t0
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
+    parity = dict(f_rel=abs(float(f.item()) - fr) / abs(fr), gU_rel=rel(gU.cpu().numpy(), gUr),
+                  gV_rel=rel(gV.cpu().numpy(), gVr))
+    print(f"partial: oracle parity {parity}, {t_eval:.2f} s per evaluation", file=sys.stderr, flush=True)
+    fg = ob.make_fg(X32, p.lam_s, p.lam_l, p.k, p.mask)
+    t0 = time.perf_counter()
+    res = olb.lbfgs(fg, ob.pack(Uh, Vh), mem=10, max_iter=20, gtol=0.0, ftol=0.0)
+    t20 = time.perf_counter() - t0
+    return dict(kind="oracle", value=1.0 / t_eval, unit="evals/s", cores=os.cpu_count(),
+                sample=f"one FP64 objective+gradient at 8192x8192 (mask 0.3), then 20 L-BFGS iterations "
+                       f"({res['evals']} evaluations, {t20:.1f} s)",
+                parity_at_rsvd_start=parity, lbfgs_20_iters_s=round(t20, 2),
+                time_to_certificate_s_extrapolated=round(gpu_evals * t20 / max(res["evals"], 1), 1),
+                extrapolation=f"{gpu_evals} evaluations (the GPU FP32 solve's count) x the oracle's seconds "
+                              "per evaluation inside its 20 L-BFGS iterations")
+
+
 def run_prox(args):
     """Convex baseline on the 76,800 x 200 video: accelerated proximal gradient with
     a randomized singular-value threshold from L = 0 (k = 32 factor capacity), then
@@ -466,21 +609,30 @@ def probe(args):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_video76800x200_hbm_traffic.md")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_1702_02241_amd", "csrc", "sweep_kernel.h")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_1702_02241_amd", "csrc", f) for f in ("sweep_kernel.h", "sweep_k16.h")]
+
+
+def sweep_source_hash():
+    """SHA-256 over the sweep's source files, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     or None when the sweep source changed since the counters were taken."""
-    import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+        src = sweep_source_hash()
     except OSError:
         return None
     vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
-                                                                           "sweep_kernel_h_sha256:")))
-    if vals.get("sweep_kernel_h_sha256", "").strip() != src:
+                                                                           "sweep_sources_sha256:")))
+    if vals.get("sweep_sources_sha256", "").strip() != src:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -533,11 +685,12 @@ def main():
     if args.probe:
         probe(args)
         return
-    if args.workload in ("batch", "fw", "prox", "stream"):
+    if args.workload in ("batch", "fw", "prox", "stream", "partial"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        {"batch": run_batch, "fw": run_fw, "prox": run_prox, "stream": run_stream}[args.workload](args)
+        {"batch": run_batch, "fw": run_fw, "prox": run_prox, "stream": run_stream,
+         "partial": run_partial}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path here is the single-GPU kernel; "
@@ -577,6 +730,21 @@ def main():
     evals = sum(i.evals for _, i in infos)
     ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
     last_rc, last = infos[-1]
+    # the other precision on the same seeds, for comparison
+    other = "fp32" if args.precision != "fp32" else "bf16_polish"
+    oopts = dict(opts, precision=R.RPCA_PREC_FP32 if other == "fp32" else R.RPCA_PREC_BF16_POLISH)
+    ctx.solve(Xcm, U, V, seed=1000, **oopts)
+    torch.cuda.synchronize()
+    oinfos = []
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        oinfos.append(ctx.solve(Xcm, U, V, seed=1 + st, **oopts)[1])
+    torch.cuda.synchronize()
+    other_ms = 1000.0 * (time.perf_counter() - t0) / max(args.steps, 1)
+    comparison = {other: dict(ms_per_step=round(other_ms, 3), iters_per_solve=[i.iters for i in oinfos],
+                              iters_bf16_per_solve=[i.iters_bf16 for i in oinfos],
+                              cert_rounds_per_solve=[i.cert_rounds for i in oinfos],
+                              certified=int(all(i.certified for i in oinfos)))}
 
     # The same solves again with the library's per-launch HIP events (recorded on the
     # stream each kernel is launched on): device time per kernel class and step.
@@ -608,7 +776,7 @@ def main():
     achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                    kernel="k_sweep (objective/gradient evaluation)", kernel_ms=round(sweep_ms, 5),
+                    kernel="k_sweep (objective/gradient evaluation, FP32 products)", kernel_ms=round(sweep_ms, 5),
                     launches=int(prof.launches[R.RPCA_K_SWEEP]), finish_ms=round(finish_ms, 5),
                     alg_bytes_per_launch=alg_bytes)
     # MFMA share of the same launches: the algorithmic flops of the three products
@@ -619,6 +787,21 @@ def main():
     mfma = dict(achieved=round(mfma_tflops, 2), peak=MFMA_PEAK_TFLOPS["fp32"], unit="TFLOP/s",
                 frac=round(mfma_tflops / MFMA_PEAK_TFLOPS["fp32"], 4), product_dtype="fp32",
                 alg_flops_per_launch=alg_flops)
+    # the same sweep with BF16 products (the BF16 phase of the default precision)
+    R.rpca_profile_enable(ctx.ctx, True)
+    R.rpca_profile_read(ctx.ctx, reset=True)
+    for _ in range(args.objgrad_reps):
+        ctx.objgrad(Xcm, U, V, R.RPCA_PREC_BF16)
+    torch.cuda.synchronize()
+    _, prof_b = R.rpca_profile_read(ctx.ctx, reset=True)
+    R.rpca_profile_enable(ctx.ctx, False)
+    sweep_b = prof_b.ms[R.RPCA_K_SWEEP] / max(prof_b.launches[R.RPCA_K_SWEEP], 1)
+    ach_b = alg_bytes / (sweep_b * 1e-3) / 1e9
+    roofline_bf16 = dict(bound="hbm", achieved=round(ach_b, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach_b / HBM_PEAK_GBS, 4), kernel="k_sweep (BF16 products)",
+                         kernel_ms=round(sweep_b, 5), mfma_tflops=round(alg_flops / (sweep_b * 1e-3) / 1e12, 2),
+                         mfma_peak=MFMA_PEAK_TFLOPS["bf16"],
+                         mfma_frac=round(alg_flops / (sweep_b * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"], 5))
     # objective+gradient rate without the events
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -672,6 +855,8 @@ def main():
         "objgrad_evals_per_s": round(og_rate, 1),
         "roofline": roofline,
         "mfma": mfma,
+        "roofline_bf16": roofline_bf16,
+        "other_precision": comparison,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

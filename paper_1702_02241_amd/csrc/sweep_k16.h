@@ -110,7 +110,13 @@ __device__ __forceinline__ void sweep_item_k16(const Args& a, const int rg, cons
   double f_acc = 0.0, uu_acc = 0.0, gud_acc = 0.0, gg_acc = 0.0;
   const int64_t nstrips = (m + 15) >> 4;
   const int64_t R = a.row_groups;
-  const int64_t s_lo = (int64_t)rg * nstrips / R, s_hi = ((int64_t)rg + 1) * nstrips / R;
+  // workgroup rows split whole pairs of strips (a 128-byte line of a column holds two
+  // strips' rows), so that the two halves of every line are read by the same
+  // workgroup at about the same time
+  const int64_t npairs = (nstrips + 1) >> 1;
+  const int64_t s_lo = 2 * ((int64_t)rg * npairs / R);
+  const int64_t s_hi_p = 2 * (((int64_t)rg + 1) * npairs / R);
+  const int64_t s_hi = s_hi_p < nstrips ? s_hi_p : nstrips;
   const int64_t s_first = s_lo + w;
   int64_t n_all = 0;
   if (s_first < s_hi) n_all = (s_hi - s_first + WAVES - 1) / WAVES;
