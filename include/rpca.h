@@ -148,6 +148,18 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
 int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
                       const uint8_t* mask, int32_t target_waves, rpca_ctx** out);
 
+/* Solver slots replayed from captured HIP graphs (on) or launched one by one
+ * (off, the default: on the 76,800 x 200 video the graphs took 15.85 ms per
+ * solve against 15.57 ms eager, the launch queue already running ahead of the
+ * GPU).  With graphs, rpca_solve replays a captured group of
+ * slots_per_sync slots (direction, trial sweep, finishing reduction, pair
+ * update) on a stream the context owns, ordered after the caller's stream; the
+ * graphs are kept per (X, preconditioner, regulariser, memory, group size,
+ * precision) and freed by rpca_destroy.  Results are bitwise the same either
+ * way.  With kernel timing on (rpca_profile_enable) the slots are launched one
+ * by one.  RPCA_EINVAL for a null context. */
+int rpca_set_graphs(rpca_ctx* ctx, int32_t on);
+
 /* The sweep decomposition a context took when it was created (from the
  * tuning table, or from rpca_create_waves): out[0] workgroup rows, out[1]
  * strips of 16 rows per wave, out[2] columns per chunk, out[3] chunks.

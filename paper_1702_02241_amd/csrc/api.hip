@@ -336,6 +336,9 @@ void rpca_destroy(rpca_ctx* c) {
   dfree(c->pc_dev);
   dfree(c->pc_gram);
   dfree(c->cert_ws);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->gev) (void)hipEventDestroy(c->gev);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   rpca::host_free(c->cert_pin);
   rpca::host_free(c->st_host);
   prof_collect(c);
@@ -354,6 +357,12 @@ int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_s, double lam_
   return rpca::create_ctx(m, n, k, lam_s, lam_l, mask, target_waves, out);
 }
 
+
+int rpca_set_graphs(rpca_ctx* c, int32_t on) {
+  if (!c) return RPCA_EINVAL;
+  c->use_graphs = on != 0;
+  return RPCA_OK;
+}
 
 int rpca_sweep_layout(const rpca_ctx* c, int32_t out[4]) {
   if (!c || !out) return RPCA_EINVAL;
@@ -493,8 +502,60 @@ void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
   return p;
 }
 
+// One solver slot: direction, trial sweep, finishing reduction, pair update.
+hipError_t launch_slot(const SweepArgs& sa, const FinishArgs& fa, const LbfgsArgs& lu, const LbfgsArgs& ld, int mem,
+                       bool bf16, hipStream_t s) {
+  hipError_t e = launch_lbfgs_direction(ld, mem, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_sweep(sa, true, bf16, s)) != hipSuccess) return e;
+  if ((e = launch_finish(fa, true, s)) != hipSuccess) return e;
+  return launch_lbfgs_update(lu, mem, s);
+}
+
+// The captured group of `slots` slots for these arguments (built on first use, on
+// the context's own stream: a caller's stream may be the null stream, which cannot
+// be captured).  The launches of a group read only buffers the context owns, X,
+// the preconditioner and the mask, so the key is X, the preconditioner pointer,
+// the regulariser's slope, the memory, the group size and the product precision.
+hipError_t slot_graph(rpca_ctx* c, const SweepArgs& sa, const FinishArgs& fa, const LbfgsArgs& lu,
+                      const LbfgsArgs& ld, int mem, bool bf16, int slots, hipGraphExec_t* out) {
+  for (auto& g : c->graphs)
+    if (g.X == sa.X && g.pc == sa.pc && g.kappa == sa.kappa && g.mem == mem && g.slots == slots &&
+        g.bf16 == bf16) {
+      *out = g.exec;
+      return hipSuccess;
+    }
+  hipError_t e;
+  if (!c->gstream) {
+    if ((e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&c->gev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int q = 0; q < slots && le == hipSuccess; ++q) le = launch_slot(sa, fa, lu, ld, mem, bf16, c->gstream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(c->gstream, &graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le != hipSuccess ? le : e;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  if (c->graphs.size() >= 8) {  // keep the cache small: drop the oldest
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({sa.X, sa.pc, sa.kappa, mem, slots, bf16, exec});
+  *out = exec;
+  return hipSuccess;
+}
+
 // Run the device-resident L-BFGS from x[cur] (whose f and g are valid) until the
-// device reports PH_DONE.  Returns an rpca_status.
+// device reports PH_DONE.  Returns an rpca_status.  Groups of slots are replayed
+// from a captured graph on the context's stream (ordered after the caller's), or,
+// with kernel timing on, launched one by one on the caller's stream.
 int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStream_t s) {
   SweepArgs sa = make_sweep_args(c, X);
   FinishArgs fa = make_finish_args(c);
@@ -504,6 +565,19 @@ int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStr
   lu.counter = c->counters + 1;
   ld.counter = c->counters + 2;
   const int slots = o->slots_per_sync > 0 ? o->slots_per_sync : 16;
+  if (c->use_graphs && !c->prof_on) {
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(slot_graph(c, sa, fa, lu, ld, o->mem, bf16, slots, &exec));
+    for (int guard = 0; guard < 1000000; ++guard) {
+      HIPCHK(hipEventRecord(c->gev, s));
+      HIPCHK(hipStreamWaitEvent(c->gstream, c->gev, 0));
+      HIPCHK(hipGraphLaunch(exec, c->gstream));
+      HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, c->gstream));
+      HIPCHK(hipStreamSynchronize(c->gstream));
+      if (c->st_host->phase == PH_DONE) break;
+    }
+    return RPCA_OK;
+  }
   for (int guard = 0; guard < 1000000; ++guard) {
     for (int q = 0; q < slots; ++q) {
       HIPCHK(timed(c, RPCA_K_DIRECTION, s, [&] { return launch_lbfgs_direction(ld, o->mem, s); }));

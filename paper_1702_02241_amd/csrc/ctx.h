@@ -46,6 +46,19 @@ struct rpca_ctx {
   size_t cert_ws_bytes = 0;
   void* cert_pin = nullptr;  // pinned host staging of the certificate's small copies
   size_t cert_pin_bytes = 0;
+  // captured groups of solver slots (see run_lbfgs), keyed by what the launches read
+  struct SlotGraph {
+    const float* X;
+    const float* pc;
+    float kappa;
+    int mem, slots;
+    bool bf16;
+    hipGraphExec_t exec;
+  };
+  std::vector<SlotGraph> graphs;
+  hipStream_t gstream = nullptr;   // the graphs' stream (non-blocking, default priority)
+  hipEvent_t gev = nullptr;        // orders gstream after the caller's stream
+  bool use_graphs = false;        // off by default: measured no faster (see rpca_set_graphs)
   // optional per-launch timing
   struct Pending {
     int cls;

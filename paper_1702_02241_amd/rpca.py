@@ -121,6 +121,7 @@ def lib():
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
             "rpca_set_elastic": (I32, [P, D]),
             "rpca_sweep_layout": (I32, [P, ctypes.POINTER(I32 * 4)]),
+            "rpca_set_graphs": (I32, [P, I32]),
             "rpca_objgrad_ex": (I32, [P, P, P, P, P, P, P, I32, P]),
             "rpca_objgrad_noalloc": (I32, [I64, I64, I32, D, D, P, P, P, P, P, P, P, P]),
             "rpca_solve": (I32, [P, P, P, P, ctypes.POINTER(rpca_opts), ctypes.POINTER(rpca_info), P]),
@@ -195,6 +196,10 @@ def rpca_create(m, n, k, lam_s, lam_l, mask=None, waves=None):
     else:
         rc = lib().rpca_create_waves(m, n, k, lam_s, lam_l, mptr, int(waves), ctypes.byref(ctx))
     return rc, ctx
+
+
+def rpca_set_graphs(ctx, on):
+    return lib().rpca_set_graphs(ctx, int(on))
 
 
 def rpca_sweep_layout(ctx):

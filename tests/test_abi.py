@@ -200,3 +200,7 @@ def test_objgrad_noalloc_rejects_bad_arguments_and_oversize_before_hip():
     assert call(100, 50, 5, 0.1, 1.0, None, d, d, d, d, d, None, None) == R.RPCA_EINVAL
     # many column chunks of a tall matrix: the G V partials exceed the fixed array
     assert call(1 << 22, 1 << 14, 32, 0.1, 1.0, None, d, d, d, d, d, d, None) == R.RPCA_ETOOBIG
+
+
+def test_set_graphs_rejects_null_context():
+    assert R.lib().rpca_set_graphs(None, 1) == R.RPCA_EINVAL

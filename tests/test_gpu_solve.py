@@ -13,6 +13,7 @@ from oracle import certificate as ce
 from oracle import lbfgs as lb
 from oracle import objective as ob
 from oracle import rsvd as rs
+from paper_1702_02241_amd import rpca as R
 from paper_1702_02241_amd import synth
 from paper_1702_02241_amd import torch_api as T
 
@@ -284,4 +285,30 @@ def test_plain_lbfgs_solve_matches_oracle(masked):
     assert eL <= 1e-3
     assert o["rel_gap"] <= 1e-3
     assert info.certified == 1
+    ctx.close()
+
+
+def test_solve_graph_replays_bitwise_equal_to_eager(small):
+    """Slot groups replayed from captured graphs give the eager launches' results
+    bit for bit, over several solves in a row (each replays the graph many times,
+    with the host's own synchronisations and copies between replays)."""
+    p, U0, V0, Om, fstar, Us, Vs = small
+    dev = device()
+    ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    Xcm = T.to_device_X(p.X, dev)
+    results = {}
+    for graphs in (0, 1):
+        assert R.rpca_set_graphs(ctx.ctx, graphs) == R.RPCA_OK
+        outs = []
+        for seed in (1, 2, 3):
+            U, V = T.to_device_factor(U0, dev), T.to_device_factor(V0, dev)
+            rc, info = ctx.solve(Xcm, U, V, init=R.RPCA_INIT_RSVD, seed=seed, certify=1)
+            torch.cuda.synchronize()
+            outs.append((rc, info.iters, info.evals, info.f, U.cpu().numpy().copy(), V.cpu().numpy().copy()))
+        results[graphs] = outs
+    for a, b in zip(results[0], results[1]):
+        print(f"[graphs] eager rc={a[0]} iters={a[1]} evals={a[2]} f={a[3]:.10g} | graph rc={b[0]} "
+              f"iters={b[1]} evals={b[2]} f={b[3]:.10g}", flush=True)
+        assert a[:4] == b[:4]
+        assert np.array_equal(a[4], b[4]) and np.array_equal(a[5], b[5])
     ctx.close()
