@@ -68,7 +68,9 @@ int rpca_batch_objgrad(rpca_batch* b, const float* const* X, const float* const*
  * that synchronise with the host (rSVD start, preconditioner refresh and
  * restart between cycles, certificates) run on up to 16 host worker threads,
  * each with its own stream of the batch, so a batch must not be used from
- * two host threads at once. */
+ * two host threads at once.  The worker count is the host's hardware thread
+ * count capped at 16; RPCA_BATCH_WORKERS=1..16 in the environment (read at the
+ * first batched solve) sets it. */
 int rpca_batch_solve(rpca_batch* b, const float* const* X, float* const* U, float* const* V,
                      const rpca_opts* opts, rpca_info* info, void* stream);
 

@@ -10,6 +10,7 @@
 // the phase test.  A group of slots is captured once in a hipGraph and
 // replayed until every instance reports done.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -28,8 +29,13 @@ namespace {
 // 64-instance batch: 4 workers 686 ms, 8 573 ms, 16 540 ms per solve.
 constexpr int BATCH_WORKERS = 16;
 
+// RPCA_BATCH_WORKERS (1..16) in the environment overrides the host's count.
 int worker_count() {
   static const int w = [] {
+    if (const char* e = getenv("RPCA_BATCH_WORKERS")) {
+      const int v = atoi(e);
+      if (v >= 1 && v <= BATCH_WORKERS) return v;
+    }
     const unsigned hw = std::thread::hardware_concurrency();
     return (int)std::max(1u, std::min((unsigned)BATCH_WORKERS, hw ? hw : 1u));
   }();
