@@ -52,9 +52,10 @@ def parse():
     ap.add_argument("--objgrad-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--probe", choices=["objgrad", "solve", "copy"], default=None,
+    ap.add_argument("--probe", choices=["objgrad", "solve", "copy", "certified"], default=None,
                     help="profiling aid: run --reps objective/gradient evaluations (or device copies of X, "
-                         "the calibration of the HBM byte counters) at the workload's shape and exit")
+                         "the calibration of the HBM byte counters; or --reps certified solves from the "
+                         "sketch seeds 1..reps, as timed by the bench) at the workload's shape and exit")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--stream-train", type=int, default=2000,
                     help="stream workload: solver-generated training windows (over five videos)")
@@ -594,6 +595,21 @@ def probe(args):
         print(f"probe copy: {args.reps} x (read {Xcm.numel() * 4} B + write {Y.numel() * 4} B)")
         return
     ctx = T.Context(p.m, p.n, p.k, p.lam_s, p.lam_l)
+    if args.probe == "certified":
+        from paper_1702_02241_amd import rpca as R
+        U = torch.empty(p.m, p.k, dtype=torch.float32, device=dev)
+        V = torch.empty(p.n, p.k, dtype=torch.float32, device=dev)
+        opts = dict(init=R.RPCA_INIT_RSVD, certify=1, precond=args.precond)
+        ctx.solve(Xcm, U, V, seed=1000, **opts)  # warm-up
+        torch.cuda.synchronize()
+        for st in range(args.reps):
+            t0 = time.perf_counter()
+            rc, info = ctx.solve(Xcm, U, V, seed=1 + st, **opts)
+            torch.cuda.synchronize()
+            print(f"probe certified: seed {1 + st} {1e3 * (time.perf_counter() - t0):.2f} ms, "
+                  f"iters {info.iters}, evals {info.evals}, cert rounds {info.cert_rounds}", flush=True)
+        ctx.close()
+        return
     U, V = ctx.init_rsvd(Xcm)
     if args.probe == "solve":
         # line-search trial sweeps: --reps L-BFGS iterations from the cold start, no certificate

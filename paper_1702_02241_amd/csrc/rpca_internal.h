@@ -49,7 +49,7 @@ struct SolverState {
   int ls_stage;         // 0 = bracketing, 1 = zoom
   int ls_trials;        // trials in the current search
   int restarted;        // memory already reset once in this search
-  int first_iter;
+  int first_iter;       // the next direction's first trial step is min(1, 1/||g||_1), not 1
   int mode_bf16;        // products in BF16 for the current phase
   int pad0;
   double c1, c2, gtol, ftol;
@@ -295,4 +295,26 @@ int finish_status(rpca_ctx* c, const rpca_opts& o, int certified, double rel_gap
 int solve_finish(rpca_ctx* c, const float* X, float* U, float* V, const rpca_opts& o, bool final_bf16,
                  double gtol, int iters_bf16, std::chrono::steady_clock::time_point t0, rpca_info* info,
                  hipStream_t s);
+// Fused thin Gram product Z = Op^T (Op W) in one pass over X (gram_apply.hip):
+// Op = Omega .* rho'(U V^T - X) (resid) or Omega .* X; rank k <= 16, n <= 256.
+struct GramApplyArgs {
+  const float* X;
+  const uint32_t* mask;   // column-major bitmask (word j*mw + i/32) or null
+  int64_t m, n;
+  int32_t k, mw;
+  float lam_s, kappa;
+  const float* U;         // m x k row-major (residual source)
+  const float* V;         // n x k row-major (residual source)
+  const float* W;         // n x 16 row-major FP32, columns past the block zero
+  float* part;            // [row_groups][n * 16] per-workgroup sums
+  int32_t row_groups;     // workgroups (grid)
+  int32_t xvec;           // 1: X is 16-byte aligned and m % 4 == 0
+};
+bool gram_apply_fits(int64_t n, int k);
+size_t gram_apply_lds_bytes(int64_t n);
+int gram_apply_segments(int row_groups);
+// Z[j * ldz + col0 + p] = scale * (Op^T Op W)[j][p] for p < b (FP64 output; level2:
+// gram_apply_segments(row_groups) * n * 16 doubles of scratch).
+hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* level2, double* Z, int ldz, int col0,
+                             int b, double scale, hipStream_t s);
 }  // namespace rpca

@@ -102,6 +102,7 @@ class rpca_fw_profile(ctypes.Structure):
 
 
 RPCA_K_SWEEP, RPCA_K_FINISH, RPCA_K_UPDATE, RPCA_K_DIRECTION, RPCA_K_TRIAL, RPCA_K_LEFT, RPCA_K_RIGHT = 0, 1, 2, 3, 4, 5, 6
+RPCA_K_GRAM = 7
 
 _lib = None
 
