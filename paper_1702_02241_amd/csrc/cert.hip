@@ -762,10 +762,19 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
   return hipSuccess;
 }
 
+// Wf (n x 16 FP32) = columns [col0, col0 + bw) of the FP64 block W (ld ldw), zero beyond
+__global__ void k_pack_w16(const double* W, int ldw, int col0, int bw, int64_t n, float* Wf) {
+  const int64_t idx = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (idx >= n * 16) return;
+  const int64_t j = idx >> 4;
+  const int p = (int)(idx & 15);
+  Wf[idx] = p < bw ? (float)W[j * ldw + col0 + p] : 0.f;
+}
+
 // Z (n x b, ld ldz, FP64) = Op^T Op W for the FP32 block W in w.Wf (n x 16), one
 // fused pass over X (the workspace has it when n <= 256 and k <= 16).
 hipError_t gram_product(const rpca::CtxView& cv, const Workspace& w, const float* X, int src, const float* U,
-                        const float* V, double* Z, int ldz, int b, hipStream_t s) {
+                        const float* V, double* Z, int ldz, int b, hipStream_t s, int col0 = 0) {
   if (!w.gpart || src == SRC_PROX) return hipErrorInvalidValue;
   rpca::GramApplyArgs a;
   memset(&a, 0, sizeof(a));
@@ -785,7 +794,7 @@ hipError_t gram_product(const rpca::CtxView& cv, const Workspace& w, const float
   a.xvec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0 && cv.m % 4 == 0) ? 1 : 0;
   void* tok = nullptr;
   if (cv.ctx && rpca::prof_begin(cv.ctx, s, &tok) != hipSuccess) return hipErrorUnknown;
-  const hipError_t e = rpca::launch_gram_apply(a, src == SRC_RESID, w.glvl, Z, ldz, 0, b, 1.0, s);
+  const hipError_t e = rpca::launch_gram_apply(a, src == SRC_RESID, w.glvl, Z, ldz, col0, b, 1.0, s);
   if (e != hipSuccess) return e;
   if (tok && rpca::prof_end(cv.ctx, RPCA_K_GRAM, s, tok) != hipSuccess) return hipErrorUnknown;
   return hipSuccess;
@@ -1571,14 +1580,37 @@ extern "C" int rpca_init_rsvd(rpca_ctx* c, const float* X, const float* Omega_s,
   double* pinB = ws.pin + PIN_SMALL;  // n x l
   memcpy(pinB, Om.data(), Om.size() * 8);
   if (hipMemcpyAsync(ws.Wd, pinB, Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
-  // Y = A Omega, Q = orth(Y)
-  if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
-  if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
-  for (int q = 0; q < power_steps; ++q) {
-    if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
-    if ((rc = orthonormalize_dev(ws, ws.Zd, ws.Wd, n, l, l, s))) return rc;
-    if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Zd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+  if (ws.gpart) {
+    // the same subspace, span A (A^T A)^q Omega, with the power steps on the n side:
+    // W <- orth(A^T A W) in fused passes over X (16 columns each), then Y = A W
+    double* Wcur = ws.Wd;
+    double* Wnext = ws.Zd;
+    for (int q = 0; q < power_steps; ++q) {
+      for (int col0 = 0; col0 < l; col0 += 16) {
+        const int bw = std::min(16, l - col0);
+        hipLaunchKernelGGL(k_pack_w16, dim3((unsigned)((n * 16 + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
+                           (const double*)Wcur, l, col0, bw, n, ws.Wf);
+        if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+        if (gram_product(cv, ws, X, SRC_DATA, nullptr, nullptr, Wnext, l, bw, s, col0) != hipSuccess)
+          return RPCA_EHIP;
+      }
+      if ((rc = orthonormalize_dev(ws, Wnext, ws.Y2, n, l, l, s))) return rc;
+      std::swap(Wcur, Wnext);
+    }
+    if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, Wcur, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
     if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+  } else {
+    // Y = A Omega, Q = orth(Y), then q steps Q <- orth(A orth(A^T Q))
+    if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
+    if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+    for (int q = 0; q < power_steps; ++q) {
+      if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess)
+        return RPCA_EHIP;
+      if ((rc = orthonormalize_dev(ws, ws.Zd, ws.Wd, n, l, l, s))) return rc;
+      if (left_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Zd, l, ws.Yd, l, l, s) != hipSuccess)
+        return RPCA_EHIP;
+      if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+    }
   }
   // B^T = A^T Q (n x l); B B^T = W Lam W^T
   if (right_product(cv, ws, X, SRC_DATA, nullptr, nullptr, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
