@@ -628,6 +628,7 @@ int restart_state(rpca_ctx* c, double gtol, double ftol, int max_iter, bool rese
   HIPCHK(hipMemcpyAsync(h, c->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   h->phase = PH_DIRECTION;
+  h->dir_pending = 0;
   h->stop = STOP_NONE;
   h->gtol = gtol;
   h->ftol = ftol;

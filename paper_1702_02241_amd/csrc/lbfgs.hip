@@ -10,10 +10,15 @@
 //
 // where R is the upper triangle of S^T Y and Dg its diagonal.  One pass over
 // the history ("update") computes every inner product the small matrices need
-// in FP64; a second pass ("direction") forms d = -H g.  Both passes end in a
-// one-block kernel that combines the block partials and runs the small
-// (mem x mem) algebra (one wave), so the whole iteration stays on the device.
+// in FP64; its finishing kernel combines the block partials (one block per
+// value, the last to arrive runs the mem x mem algebra in one wave) and, since
+// g^T d = -(gamma g^T g + p^T a - gamma u^T b) follows from the same inner
+// products, also sets up the line search.  A second pass ("direction") then
+// only forms d = -H g.  Only after a restart (no pairs, d = -g) does the
+// direction pass end in a one-block kernel that sums g^T d itself.  The whole
+// iteration stays on the device.
 #include "rpca_internal.h"
+#include "linesearch.h"
 
 #include <math.h>
 
@@ -22,6 +27,7 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / 64;
+constexpr int LBFGS_MAX_BLOCKS = 512;  // blocks of a streaming pass; the combined dots follow their partials
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -127,8 +133,10 @@ __device__ __forceinline__ int bcast_int(int v, int src) { return __builtin_amdg
 // Both substitutions run column by column: the solved entry is broadcast from
 // its lane through the scalar unit and every lane updates its own entry, so a
 // step costs one broadcast and one FMA.
+// Returns g^T d for the next direction d = -(gamma g + S coef_s + Y coef_y):
+//   g^T d = -(gamma g^T g + sum_i coef_s_i a_i + coef_y_i b_i)   (every lane).
 template <int MEM>
-__device__ void update_wave(SolverState* st, const double* D) {
+__device__ double update_wave(SolverState* st, const double* D) {
   using I = DotIdx<MEM>;
   const int lane = threadIdx.x & 63;
   const int cnt = st->count;
@@ -187,7 +195,7 @@ __device__ void update_wave(SolverState* st, const double* D) {
       st->gamma = sy / yy;
     }
   }
-  if (h == 0) return;
+  if (h == 0) return -D[I::GG];  // steepest descent (gamma 1 without pairs)
   const double gamma = keep ? sy / yy : st->gamma;
   // this lane's row and column of R and row of Q (ordered pairs)
   double rowR[MEM], colR[MEM], rowQ[MEM];
@@ -232,11 +240,13 @@ __device__ void update_wave(SolverState* st, const double* D) {
     st->coef_s[ord] = p;
     st->coef_y[ord] = -gamma * u;
   }
+  const double gdl = (lane < h) ? p * av - gamma * u * bv : 0.0;
+  return -(gamma * D[I::GG] + wave_sum(gdl));
 }
 
 // Stopping tests after an update (one thread).
 template <int MEM>
-__device__ void update_stops(SolverState* st, const double* D) {
+__device__ void update_stops(SolverState* st, const double* D, double gd) {
   using I = DotIdx<MEM>;
   const double f = st->f;
   for (int i = 0; i < 7; ++i) st->fhist[i] = st->fhist[i + 1];
@@ -258,7 +268,13 @@ __device__ void update_stops(SolverState* st, const double* D) {
     stop = STOP_FTOL;
   else if (st->iter >= st->max_iter) stop = STOP_MAXITER;
   st->stop = stop;
-  st->phase = (stop == STOP_NONE) ? PH_DIRECTION : PH_DONE;
+  if (stop == STOP_NONE) {
+    // the next direction's slope is known from the inner products: the line search
+    // starts now and the direction pass of the next slot only forms d
+    rpca_ls::setup_trial(st, gd, D[I::G1], 1);
+  } else {
+    st->phase = PH_DONE;
+  }
 }
 
 template <int MEM>
@@ -343,22 +359,67 @@ __device__ __forceinline__ void lbfgs_update_final_body(const LbfgsArgs& a, int 
   copy_state_block(&sst, st);
   __syncthreads();
   if (threadIdx.x < 64) {
-    update_wave<MEM>(&sst, D);
-    if (threadIdx.x == 0) update_stops<MEM>(&sst, D);
+    const double gd = update_wave<MEM>(&sst, D);
+    if (threadIdx.x == 0) update_stops<MEM>(&sst, D, gd);
   }
   __syncthreads();
   copy_state_block(st, &sst);
 }
 
+// The same with the combine spread over one block per value: block v sums value v
+// of the nb partials in a fixed order into dots[v]; the last block to arrive
+// (thread-0 fence + counter over NV blocks) runs the algebra.
 template <int MEM>
-__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final(LbfgsArgs a, int nb) {
-  lbfgs_update_final_body<MEM>(a, nb);
+__global__ __launch_bounds__(THREADS) void k_lbfgs_update_final_mb(LbfgsArgs a, int nb) {
+  using I = DotIdx<MEM>;
+  constexpr int NV = I::NV;
+  SolverState* st = a.st;
+  if (st->phase != PH_UPDATE) return;
+  const int v = blockIdx.x;
+  const bool is_max = v == I::GINF;
+  double* dots = a.part + (int64_t)RPCA_NDOT * LBFGS_MAX_BLOCKS;
+  __shared__ double sh[WAVES];
+  __shared__ int s_last;
+  double r = 0.0;
+  for (int b = threadIdx.x; b < nb; b += THREADS) {
+    const double x = a.part[(int64_t)v * nb + b];
+    r = is_max ? fmax(r, x) : r + x;
+  }
+  r = is_max ? wave_max(r) : wave_sum(r);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double q = sh[0];
+    for (int w = 1; w < WAVES; ++w) q = is_max ? fmax(q, sh[w]) : q + sh[w];
+    dots[v] = q;
+    __threadfence();
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    s_last = prev == (unsigned)NV - 1u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  __shared__ double D[NV];
+  for (int t = threadIdx.x; t < NV; t += THREADS) D[t] = dots[t];
+  __shared__ SolverState sst;
+  copy_state_block(&sst, st);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const double gd = update_wave<MEM>(&sst, D);
+    if (threadIdx.x == 0) {
+      update_stops<MEM>(&sst, D, gd);
+      *a.counter = 0u;
+    }
+  }
+  __syncthreads();
+  copy_state_block(st, &sst);
 }
+
 
 template <int MEM>
 __device__ __forceinline__ void lbfgs_direction_body(const LbfgsArgs& a, int bx, int nb) {
   SolverState* st = a.st;
-  if (st->phase != PH_DIRECTION) return;
+  if (st->phase != PH_DIRECTION && !(st->phase == PH_TRIAL && st->dir_pending)) return;
   const int cur = st->cur;
   const int64_t n4 = a.N >> 2;
   const f4* g = reinterpret_cast<const f4*>(a.g[cur]);
@@ -410,29 +471,8 @@ __device__ __forceinline__ void lbfgs_direction_final_body(const LbfgsArgs& a, i
   __shared__ double D[3];
   combine_partials<3, -1>(a.part, nb, D);
   if (threadIdx.x == 0) {
-    const double gd = D[0];
     st->dd = D[1];
-    if (!(gd < 0.0) || !isfinite(gd)) {
-      if (st->count > 0) {
-        // not a descent direction: drop the memory, steepest descent next slot
-        st->count = 0;
-        st->spare = 0;
-        st->newest = -1;
-      } else {
-        st->stop = isfinite(gd) ? STOP_GTOL : STOP_NONFINITE;
-        st->phase = PH_DONE;
-      }
-      return;
-    }
-    st->dphi0 = gd;
-    st->alpha = st->first_iter ? fmin(1.0, 1.0 / D[2]) : 1.0;
-    st->first_iter = 0;
-    st->ls_stage = 0;
-    st->ls_trials = 0;
-    st->a_prev = 0.0;
-    st->f_prev = st->f;
-    st->d_prev = gd;
-    st->phase = PH_TRIAL;
+    rpca_ls::setup_trial(st, D[0], D[2], 0);
   }
 }
 
@@ -486,7 +526,7 @@ int lbfgs_blocks(int64_t N) {
   // mean fewer partials for the one-block combine that follows
   int64_t b = (N / 4 + THREADS - 1) / THREADS;
   if (b < 1) b = 1;
-  if (b > 512) b = 512;
+  if (b > LBFGS_MAX_BLOCKS) b = LBFGS_MAX_BLOCKS;
   return (int)b;
 }
 
@@ -501,7 +541,7 @@ hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream) 
   case M:                                                                                    \
     hipLaunchKernelGGL((k_lbfgs_update<M>), grid, dim3(THREADS), 0, stream, a);             \
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                      \
-    hipLaunchKernelGGL((k_lbfgs_update_final<M>), dim3(1), dim3(THREADS), 0, stream, a, nb); \
+    hipLaunchKernelGGL((k_lbfgs_update_final_mb<M>), dim3(DotIdx<M>::NV), dim3(THREADS), 0, stream, a, nb); \
     break;
     RPCA_MEM_CASES(CASE)
 #undef CASE

@@ -47,6 +47,37 @@ __device__ inline void search_failed(SolverState* st) {
   }
 }
 
+// Set up the line search along the direction d = -H g whose slope g^T d = gd is
+// known (from the update's inner products, or from the direction pass).  g1 =
+// ||g||_1 scales the very first step of a solve.  A non-descent direction drops
+// the memory (steepest descent next) or, without memory, ends the solve.
+// dir_pending: d still has to be formed by the direction pass of the next slot.
+__device__ inline void setup_trial(SolverState* st, double gd, double g1, int dir_pending) {
+  if (!(gd < 0.0) || !isfinite(gd)) {
+    if (st->count > 0) {
+      st->count = 0;
+      st->spare = 0;
+      st->newest = -1;
+      st->phase = PH_DIRECTION;
+    } else {
+      st->stop = isfinite(gd) ? STOP_GTOL : STOP_NONFINITE;
+      st->phase = PH_DONE;
+    }
+    st->dir_pending = 0;
+    return;
+  }
+  st->dphi0 = gd;
+  st->alpha = st->first_iter ? fmin(1.0, 1.0 / g1) : 1.0;
+  st->first_iter = 0;
+  st->ls_stage = 0;
+  st->ls_trials = 0;
+  st->a_prev = 0.0;
+  st->f_prev = st->f;
+  st->d_prev = gd;
+  st->dir_pending = dir_pending;
+  st->phase = PH_TRIAL;
+}
+
 __device__ inline void accept_trial(SolverState* st, double ft) {
   st->cur = 1 - st->cur;
   st->f = ft;

@@ -228,6 +228,7 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
   copy_state_head(&sst, st);
   __syncthreads();
   if (tid == 0) {
+    sst.dir_pending = 0;  // this trial's direction has been formed
     rpca_ls::line_search_step(&sst, fd + 0.5 * (double)lam_l * (uu + p0), gd1 + p1 + p2);
     *a.counter = 0u;
   }

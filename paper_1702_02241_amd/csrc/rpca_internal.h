@@ -51,7 +51,7 @@ struct SolverState {
   int restarted;        // memory already reset once in this search
   int first_iter;       // the next direction's first trial step is min(1, 1/||g||_1), not 1
   int mode_bf16;        // products in BF16 for the current phase
-  int pad0;
+  int dir_pending;      // PH_TRIAL set up by the update (g^T d known): the direction pass still has to form d
   double c1, c2, gtol, ftol;
   double eps_f;         // relative rounding level of f for the approximate-Wolfe test
   double f;             // objective at the current iterate
