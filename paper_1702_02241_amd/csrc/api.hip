@@ -226,7 +226,7 @@ int rpca::create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l
   TRY(dalloc(&c->d, c->N));
   TRY(dalloc(&c->S, (size_t)RPCA_MEMMAX * c->N));
   TRY(dalloc(&c->Y, (size_t)RPCA_MEMMAX * c->N));
-  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * 1024));
+  TRY(dalloc(&c->lpart, (size_t)RPCA_NDOT * (RPCA_LBFGS_MAX_BLOCKS + 1)));  // partials, then the combined dots
   TRY(dalloc(&c->st, 1));
   TRY(dalloc(&c->dscratch, 64));
   TRY(dalloc(&c->pc_dev, (size_t)7 * k * k));
@@ -502,10 +502,12 @@ void* ctx_workspace(rpca_ctx* c, size_t bytes, int* fresh) {
   return p;
 }
 
-// One solver slot: direction, trial sweep, finishing reduction, pair update.
+// One solver slot: direction, trial sweep, finishing reduction, pair update.  The
+// direction pass's own finish (needed only when the state enters PH_DIRECTION: a
+// restart, or a dropped memory) runs in the first slot of a group.
 hipError_t launch_slot(const SweepArgs& sa, const FinishArgs& fa, const LbfgsArgs& lu, const LbfgsArgs& ld, int mem,
-                       bool bf16, hipStream_t s) {
-  hipError_t e = launch_lbfgs_direction(ld, mem, s);
+                       bool bf16, hipStream_t s, bool first) {
+  hipError_t e = launch_lbfgs_direction(ld, mem, s, first);
   if (e != hipSuccess) return e;
   if ((e = launch_sweep(sa, true, bf16, s)) != hipSuccess) return e;
   if ((e = launch_finish(fa, true, s)) != hipSuccess) return e;
@@ -532,7 +534,7 @@ hipError_t slot_graph(rpca_ctx* c, const SweepArgs& sa, const FinishArgs& fa, co
   }
   if ((e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
   hipError_t le = hipSuccess;
-  for (int q = 0; q < slots && le == hipSuccess; ++q) le = launch_slot(sa, fa, lu, ld, mem, bf16, c->gstream);
+  for (int q = 0; q < slots && le == hipSuccess; ++q) le = launch_slot(sa, fa, lu, ld, mem, bf16, c->gstream, q == 0);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(c->gstream, &graph);
   if (le != hipSuccess || e != hipSuccess) {
@@ -580,7 +582,7 @@ int run_lbfgs(rpca_ctx* c, const float* X, const rpca_opts* o, bool bf16, hipStr
   }
   for (int guard = 0; guard < 1000000; ++guard) {
     for (int q = 0; q < slots; ++q) {
-      HIPCHK(timed(c, RPCA_K_DIRECTION, s, [&] { return launch_lbfgs_direction(ld, o->mem, s); }));
+      HIPCHK(timed(c, RPCA_K_DIRECTION, s, [&] { return launch_lbfgs_direction(ld, o->mem, s, q == 0); }));
       HIPCHK(objgrad_launch(c, sa, fa, true, bf16, s));
       HIPCHK(timed(c, RPCA_K_UPDATE, s, [&] { return launch_lbfgs_update(lu, o->mem, s); }));
     }

@@ -185,9 +185,11 @@ hipError_t batched_objgrad(rpca_batch* b, bool trial, bool bf16) {
                                    s);
 }
 
-hipError_t batched_slot(rpca_batch* b, int mem, bool bf16) {
+// One batched solver slot; the direction pass's own finish (states entering
+// PH_DIRECTION only) runs in the first slot of a group.
+hipError_t batched_slot(rpca_batch* b, int mem, bool bf16, bool first) {
   hipStream_t s = b->stream;
-  hipError_t e = rpca::launch_lbfgs_direction_batch(b->d_ld, b->d_off_lb, b->count, b->tot_lb, mem, s);
+  hipError_t e = rpca::launch_lbfgs_direction_batch(b->d_ld, b->d_off_lb, b->count, b->tot_lb, mem, s, first);
   if (e != hipSuccess) return e;
   if ((e = batched_objgrad(b, true, bf16)) != hipSuccess) return e;
   return rpca::launch_lbfgs_update_batch(b->d_lu, b->d_off_lb, b->count, b->tot_lb, mem, s);
@@ -203,7 +205,7 @@ hipError_t slot_graph(rpca_batch* b, int mem, bool bf16, int slots, hipGraphExec
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   hipError_t le = hipSuccess;
-  for (int q = 0; q < slots && le == hipSuccess; ++q) le = batched_slot(b, mem, bf16);
+  for (int q = 0; q < slots && le == hipSuccess; ++q) le = batched_slot(b, mem, bf16, q == 0);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(b->stream, &graph);
   if (le != hipSuccess || e != hipSuccess) {
@@ -230,7 +232,7 @@ int batched_run(rpca_batch* b, const rpca_opts& o, bool bf16, bool use_graph) {
       if (hipGraphLaunch(exec, b->stream) != hipSuccess) return RPCA_EHIP;
     } else {
       for (int q = 0; q < slots; ++q)
-        if (batched_slot(b, o.mem, bf16) != hipSuccess) return RPCA_EHIP;
+        if (batched_slot(b, o.mem, bf16, q == 0) != hipSuccess) return RPCA_EHIP;
     }
     hipLaunchKernelGGL(k_gather_phase, dim3(nb), dim3(256), 0, b->stream, b->d_states, b->count, b->d_phase);
     if (hipMemcpyAsync(b->h_phase, b->d_phase, b->count * sizeof(int), hipMemcpyDeviceToHost, b->stream) !=

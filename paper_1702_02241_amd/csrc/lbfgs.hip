@@ -27,7 +27,7 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int THREADS = 256;
 constexpr int WAVES = THREADS / 64;
-constexpr int LBFGS_MAX_BLOCKS = 512;  // blocks of a streaming pass; the combined dots follow their partials
+constexpr int LBFGS_MAX_BLOCKS = RPCA_LBFGS_MAX_BLOCKS;  // blocks of a streaming pass; the combined dots follow their partials
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -279,10 +279,16 @@ __device__ void update_stops(SolverState* st, const double* D, double gd) {
 
 template <int MEM>
 __device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, int nb) {
+  // The block's four waves walk the same elements (lane l: bx*64 + l, then every
+  // nb*64-th); wave w owns the stored pairs w, w + 4, w + 8, ... and wave 0 also
+  // the new pair (its store and scalars).  Every value is summed by one wave, so
+  // the block partial is that wave's sum and few accumulators stay live.
   using I = DotIdx<MEM>;
-  constexpr int NV = I::NV;
+  constexpr int PW = (MEM + WAVES - 1) / WAVES;
   SolverState* st = a.st;
   if (st->phase != PH_UPDATE) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cur = st->cur;
   const int64_t n4 = a.N >> 2;
   const f4* gn = reinterpret_cast<const f4*>(a.g[cur]);
@@ -290,54 +296,80 @@ __device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, in
   const f4* dd = reinterpret_cast<const f4*>(a.d);
   const float alpha = (float)st->alpha;
   const int cnt = st->count;
-  const f4* Sp[MEM];
-  const f4* Yp[MEM];
+  const f4* Sp[PW];
+  const f4* Yp[PW];
 #pragma unroll
-  for (int i = 0; i < MEM; ++i) {
-    const int slot = (i < cnt) ? st->order[i] : 0;
-    Sp[i] = reinterpret_cast<const f4*>(a.S + (int64_t)slot * a.N);
-    Yp[i] = reinterpret_cast<const f4*>(a.Y + (int64_t)slot * a.N);
+  for (int j = 0; j < PW; ++j) {
+    const int i = w + WAVES * j;
+    const int slot = (i < cnt) ? st->order[i] : 0;  // unused pairs read slot 0 (ignored)
+    Sp[j] = reinterpret_cast<const f4*>(a.S + (int64_t)slot * a.N);
+    Yp[j] = reinterpret_cast<const f4*>(a.Y + (int64_t)slot * a.N);
   }
   f4* Ssp = reinterpret_cast<f4*>(a.S + (int64_t)st->spare * a.N);
   f4* Ysp = reinterpret_cast<f4*>(a.Y + (int64_t)st->spare * a.N);
-  double acc[NV];
+  double acc[4 * PW], nw[8];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  const int64_t stride = (int64_t)nb * THREADS;
-  for (int64_t e = (int64_t)bx * THREADS + threadIdx.x; e < n4; e += stride) {
-    // every slot is read (unused ones point at slot 0 and their dots are ignored),
-    // and all loads are issued before the new pair is stored (the spare slot may
+  for (int v = 0; v < 4 * PW; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) nw[v] = 0.0;
+  const int64_t stride = (int64_t)nb * 64;
+  for (int64_t e = (int64_t)bx * 64 + lane; e < n4; e += stride) {
+    // the pair loads are issued before the new pair is stored (the spare slot may
     // alias a stored one as far as the compiler knows), so they are in flight together
-    f4 Sv[MEM], Yv[MEM];
+    f4 Sv[PW], Yv[PW];
 #pragma unroll
-    for (int i = 0; i < MEM; ++i) {
-      Sv[i] = __builtin_nontemporal_load(&Sp[i][e]);
-      Yv[i] = __builtin_nontemporal_load(&Yp[i][e]);
+    for (int j = 0; j < PW; ++j) {
+      if (w + WAVES * j < MEM) {
+        Sv[j] = __builtin_nontemporal_load(&Sp[j][e]);
+        Yv[j] = __builtin_nontemporal_load(&Yp[j][e]);
+      }
     }
     const f4 g1 = gn[e];
     const f4 y = g1 - go[e];
-    const f4 s = alpha * dd[e];
-    Ssp[e] = s;
-    Ysp[e] = y;
-#pragma unroll
-    for (int i = 0; i < MEM; ++i) {
-      acc[4 * i + 0] += dot4(Sv[i], g1);
-      acc[4 * i + 1] += dot4(Yv[i], g1);
-      acc[4 * i + 2] += dot4(Sv[i], y);
-      acc[4 * i + 3] += dot4(Yv[i], y);
+    if (w == 0) {
+      const f4 sv = alpha * dd[e];
+      Ssp[e] = sv;
+      Ysp[e] = y;
+      nw[0] += dot4(sv, y);
+      nw[1] += dot4(y, y);
+      nw[2] += dot4(sv, g1);
+      nw[3] += dot4(y, g1);
+      nw[4] += dot4(g1, g1);
+      const double m4 = fmax(fmax(fabs((double)g1[0]), fabs((double)g1[1])),
+                             fmax(fabs((double)g1[2]), fabs((double)g1[3])));
+      nw[5] = fmax(nw[5], m4);
+      nw[6] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
+      nw[7] += dot4(sv, sv);
     }
-    acc[I::SY] += dot4(s, y);
-    acc[I::YY] += dot4(y, y);
-    acc[I::SG] += dot4(s, g1);
-    acc[I::YG] += dot4(y, g1);
-    acc[I::GG] += dot4(g1, g1);
-    acc[I::SS] += dot4(s, s);
-    const double m4 = fmax(fmax(fabs((double)g1[0]), fabs((double)g1[1])),
-                           fmax(fabs((double)g1[2]), fabs((double)g1[3])));
-    acc[I::GINF] = fmax(acc[I::GINF], m4);
-    acc[I::G1] += fabs((double)g1[0]) + fabs((double)g1[1]) + fabs((double)g1[2]) + fabs((double)g1[3]);
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      if (w + WAVES * j < MEM) {
+        acc[4 * j + 0] += dot4(Sv[j], g1);
+        acc[4 * j + 1] += dot4(Yv[j], g1);
+        acc[4 * j + 2] += dot4(Sv[j], y);
+        acc[4 * j + 3] += dot4(Yv[j], y);
+      }
+    }
   }
-  block_partials<NV, I::GINF>(acc, a.part, bx, nb);
+#pragma unroll
+  for (int j = 0; j < PW; ++j) {
+    const int i = w + WAVES * j;
+    if (i < MEM) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double r = wave_sum(acc[4 * j + q]);
+        if (lane == 0) a.part[(int64_t)(4 * i + q) * nb + bx] = r;
+      }
+    }
+  }
+  if (w == 0) {
+    static_assert(I::SY + 5 == I::GINF && I::SY + 7 == I::SS, "new-pair value order");
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double r = (v == 5) ? wave_max(nw[v]) : wave_sum(nw[v]);
+      if (lane == 0) a.part[(int64_t)(I::SY + v) * nb + bx] = r;
+    }
+  }
 }
 
 template <int MEM>
@@ -522,8 +554,8 @@ __global__ __launch_bounds__(THREADS) void k_lbfgs_direction_final_batch(const L
 namespace rpca {
 
 int lbfgs_blocks(int64_t N) {
-  // about one float4 per thread, at most 512 blocks (two per CU): fewer blocks
-  // mean fewer partials for the one-block combine that follows
+  // about one float4 per thread of the direction pass (four per lane of the update
+  // pass, whose waves split the pairs), at most RPCA_LBFGS_MAX_BLOCKS
   int64_t b = (N / 4 + THREADS - 1) / THREADS;
   if (b < 1) b = 1;
   if (b > LBFGS_MAX_BLOCKS) b = LBFGS_MAX_BLOCKS;
@@ -570,7 +602,7 @@ hipError_t launch_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int co
 }
 
 hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
-                                       int mem, hipStream_t stream) {
+                                       int mem, hipStream_t stream, bool with_final) {
   switch (mem) {
 #define CASE(M)                                                                                            \
   case M:                                                                                                  \
@@ -583,11 +615,11 @@ hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int
       return hipErrorInvalidValue;
   }
   if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-  hipLaunchKernelGGL(k_lbfgs_direction_final_batch, dim3(count), dim3(THREADS), 0, stream, la, off);
+  if (with_final) hipLaunchKernelGGL(k_lbfgs_direction_final_batch, dim3(count), dim3(THREADS), 0, stream, la, off);
   return hipGetLastError();
 }
 
-hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream) {
+hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream, bool with_final) {
   const int nb = lbfgs_blocks(a.N);
   const dim3 grid(nb);
   switch (mem) {
@@ -601,7 +633,7 @@ hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t strea
       return hipErrorInvalidValue;
   }
   if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-  hipLaunchKernelGGL(k_lbfgs_direction_final, dim3(1), dim3(THREADS), 0, stream, a, nb);
+  if (with_final) hipLaunchKernelGGL(k_lbfgs_direction_final, dim3(1), dim3(THREADS), 0, stream, a, nb);
   return hipGetLastError();
 }
 

@@ -165,6 +165,7 @@ struct LbfgsArgs {
 };
 
 #define RPCA_NDOT (4 * RPCA_MEMMAX + 8)
+#define RPCA_LBFGS_MAX_BLOCKS 1024  // blocks of an L-BFGS pass; its partials take RPCA_NDOT each
 
 // Host-side launchers (defined in the .hip files).
 namespace rpca {
@@ -191,7 +192,7 @@ hipError_t launch_objgrad(const SweepArgs& sa, const FinishArgs& fa, bool trial,
 hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream);
 hipError_t launch_finish(const FinishArgs& fa, bool trial, hipStream_t stream);
 hipError_t launch_lbfgs_update(const LbfgsArgs& a, int mem, hipStream_t stream);
-hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream);
+hipError_t launch_lbfgs_direction(const LbfgsArgs& a, int mem, hipStream_t stream, bool with_final = true);
 int lbfgs_blocks(int64_t N);
 // Batched launches: arrays of per-instance arguments in device memory, block
 // offsets off[0..count] (device) of each instance in the flattened grid.
@@ -206,7 +207,7 @@ hipError_t launch_finish_batch(const FinishArgs* fa, const int* off1, int total1
 hipError_t launch_lbfgs_update_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks, int mem,
                                     hipStream_t s);
 hipError_t launch_lbfgs_direction_batch(const LbfgsArgs* la, const int* off, int count, int total_blocks,
-                                       int mem, hipStream_t s);
+                                       int mem, hipStream_t s, bool with_final = true);
 int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks);
 }  // namespace rpca
 
