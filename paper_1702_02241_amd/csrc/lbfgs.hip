@@ -320,8 +320,8 @@ __device__ __forceinline__ void lbfgs_update_body(const LbfgsArgs& a, int bx, in
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
       if (w + WAVES * j < MEM) {
-        Sv[j] = __builtin_nontemporal_load(&Sp[j][e]);
-        Yv[j] = __builtin_nontemporal_load(&Yp[j][e]);
+        Sv[j] = Sp[j][e];
+        Yv[j] = Yp[j][e];
       }
     }
     const f4 g1 = gn[e];
@@ -474,8 +474,8 @@ __device__ __forceinline__ void lbfgs_direction_body(const LbfgsArgs& a, int bx,
     f4 Sv[MEM], Yv[MEM];
 #pragma unroll
     for (int i = 0; i < MEM; ++i) {
-      Sv[i] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N) + e);
-      Yv[i] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N) + e);
+      Sv[i] = *(reinterpret_cast<const f4*>(a.S + (int64_t)slot[i] * a.N) + e);
+      Yv[i] = *(reinterpret_cast<const f4*>(a.Y + (int64_t)slot[i] * a.N) + e);
     }
     const f4 gv = g[e];
     __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
