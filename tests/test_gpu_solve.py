@@ -181,8 +181,9 @@ def test_certificate_precise_where_it_decides(small, iters):
 def test_certificate_other_paths_match_oracle(m, n, k, p_obs):
     """The certificate at a near-optimal point (a few oracle L-BFGS iterations from
     the rSVD start) on shapes that take the other code paths of the thin products;
-    same bars as the exact-certificate test (T1..T3 to 1e-3, the leading Ritz
-    value to 1e-3, ||M||_F^2 to 1e-4)."""
+    T1..T3 to 1e-3, T4 to 1e-3, ||M||_F^2 to 1e-4, the leading Ritz value a lower
+    bound of the oracle's top singular value and within 1e-3 of it (1e-2 when that
+    value is below 0.9, where the iteration may stop before the Ritz values settle)."""
     dev = device()
     if p_obs is None:
         p = synth.gaussian_rpca(m=m, n=n, r=max(1, k - 4), k=k, seed=600 + m, lam_s=1.0 / np.sqrt(max(m, n)))
@@ -204,7 +205,14 @@ def test_certificate_other_paths_match_oracle(m, n, k, p_obs):
     for key in ("T1", "T2", "T3"):
         a, b = getattr(c, key), o[key]
         assert abs(a - b) <= 1e-3 * max(b, 1.0) + 1e-5, key
-    assert abs(c.theta[0] - o["sv_perp"][0]) <= 1e-3 * o["sv_perp"][0] + 1e-5
+    # theta are Ritz values, lower bounds of the singular values.  When the leading one
+    # is far below 1 the iteration may stop once a singular value above 1 has negligible
+    # probability (the random-start bound), before the Ritz values have converged: then
+    # theta0 is within 1e-2 of sv0, and T4 is 0 as the oracle's
+    sv0 = o["sv_perp"][0]
+    assert c.theta[0] <= sv0 * (1 + 1e-6) + 1e-9
+    assert abs(c.theta[0] - sv0) <= (1e-2 if sv0 < 0.9 else 1e-3) * sv0 + 1e-5
+    assert abs(c.T4 - o["T4"]) <= 1e-3 * max(o["T4"], 1.0) + 1e-9
     assert abs(c.normM2 - o["normM2"]) <= 1e-4 * max(o["normM2"], 1.0)
     ctx.close()
 
