@@ -145,7 +145,15 @@ __device__ __forceinline__ void reduce2_body(const FinishArgs& a, const int bx, 
     const int64_t stride = (int64_t)(nblk - a.gv_blocks) * FIN_THREADS;
     for (int64_t o = (int64_t)(bx - a.gv_blocks) * FIN_THREADS + tid; o < mk; o += stride) {
       double s = 0.0;
-      for (int cc = 0; cc < a.nchunks; ++cc) s += (double)a.gupart[(int64_t)cc * mk + o];
+      int cc = 0;
+      for (; cc + 7 < a.nchunks; cc += 8) {  // eight loads in flight, summed in chunk order
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = a.gupart[(int64_t)(cc + e) * mk + o];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += (double)x[e];
+      }
+      for (; cc < a.nchunks; ++cc) s += (double)a.gupart[(int64_t)cc * mk + o];
       double reg = Ut[o];
       if (MU) {  // A M_U
         const int64_t i = o / k;
@@ -283,7 +291,7 @@ hipError_t launch_sweep_f32_elastic(const SweepArgs&, bool, bool, hipStream_t);
 
 // Sweep decomposition table, keyed by (k bucket, n bucket): the number of
 // waves the strips are spread over and the divisor of the widest chunk.
-// Defaults are what the cfg-sized measurements favoured; rpca_autotune
+// Defaults are what measurements at the benchmark shapes favoured; rpca_autotune
 // replaces entries by timing the candidates on the device.
 // The table is process-wide: reads and writes hold its mutex (contexts of a
 // batch are set up from several host threads).
@@ -292,9 +300,12 @@ struct TuneTable {
   std::mutex mu;
   SweepTune t[TUNE_KB][TUNE_NB];
   TuneTable() {
-    // k <= 16: two workgroups per CU (the k16 sweep); k > 16: one
+    // k <= 16: two workgroups per CU (the k16 sweep); k > 16: one, and for more
+    // than 512 columns (many chunks, few rows each) four times as many row groups
+    // (8192 x 8192, k = 25, Bernoulli(0.3) mask: 444 -> 369 us)
     for (int a = 0; a < TUNE_KB; ++a)
-      for (int b = 0; b < TUNE_NB; ++b) t[a][b] = SweepTune{a < 2 ? 2048 : 1024, 1};
+      for (int b = 0; b < TUNE_NB; ++b)
+        t[a][b] = SweepTune{a < 2 ? 2048 : (b == TUNE_NB - 1 ? 4096 : 1024), 1};
   }
 };
 TuneTable& tune_table() {
@@ -365,8 +376,9 @@ int finish_blocks(int64_t m, int64_t n, int k, int nchunks, int* gv_blocks) {
   const int gvb = (int)((n + rpb - 1) / rpb);
   int gub = 0;
   if (nchunks > 1) {
-    gub = (int)((m * k + FIN_THREADS * 8 - 1) / (FIN_THREADS * 8));
-    if (gub > 1024) gub = 1024;
+    // one output per thread (all chunks' partials of it in flight eight at a time)
+    gub = (int)((m * k + FIN_THREADS - 1) / FIN_THREADS);
+    if (gub > 4096) gub = 4096;
   }
   if (gv_blocks) *gv_blocks = gvb;
   return gvb + gub;
