@@ -148,6 +148,15 @@ int rpca_create(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
 int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
                       const uint8_t* mask, int32_t target_waves, rpca_ctx** out);
 
+/* rpca_create_waves with the observation mask P_Omega (Sec. 6.2) given as a
+ * DEVICE bitmask, the layout rpca_objgrad_noalloc reads: column-major, entry
+ * (i, j) observed when bit i % 32 of word j * ceil(m / 32) + i / 32 is set (bits
+ * past row m - 1 are cleared in the copy).  The context copies it (device to
+ * device, on the null stream, synchronously) and the caller keeps ownership.  mask_bits NULL is RPCA_EINVAL (use rpca_create for
+ * full observation); otherwise the errors of rpca_create_waves. */
+int rpca_create_device_mask(int64_t m, int64_t n, int32_t k, double lam_S, double lam_L,
+                            const uint32_t* mask_bits, int32_t target_waves, rpca_ctx** out);
+
 /* Solver slots replayed from captured HIP graphs (on) or launched one by one
  * (off, the default: on the 76,800 x 200 video the graphs took 15.85 ms per
  * solve against 15.57 ms eager, the launch queue already running ahead of the

@@ -166,8 +166,16 @@ hipError_t objgrad_launch(rpca_ctx* c, const SweepArgs& sa, const FinishArgs& fa
 
 }  // namespace
 
+namespace {
+// word mw - 1 of every column of a packed mask &= keep
+__global__ void k_clear_tail_bits(uint32_t* mask, int64_t n, int mw, uint32_t keep) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n) mask[j * mw + mw - 1] &= keep;
+}
+}  // namespace
+
 int rpca::create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
-                     int target_waves, rpca_ctx** out) {
+                     int target_waves, rpca_ctx** out, const uint32_t* mask_bits_dev) {
   if (!out) return RPCA_EINVAL;
   if (m < 1 || n < 1 || k < 1 || k > 32 || k > m || k > n) return RPCA_EINVAL;
   if (!(lam_s > 0) || !(lam_l > 0) || !isfinite(lam_s) || !isfinite(lam_l)) return RPCA_EINVAL;
@@ -201,6 +209,23 @@ int rpca::create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l
     if (hipMemcpy(c->mask, bits.data(), bits.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
       rpca_destroy(c);
       return RPCA_EHIP;
+    }
+  } else if (mask_bits_dev) {
+    // already packed on the device: the context keeps its own copy
+    c->mw = (int)((m + 31) / 32);
+    const size_t words = (size_t)c->mw * (size_t)n;
+    TRY(dalloc(&c->mask, words));
+    if (hipMemcpy(c->mask, mask_bits_dev, words * 4, hipMemcpyDeviceToDevice) != hipSuccess) {
+      rpca_destroy(c);
+      return RPCA_EHIP;
+    }
+    if (m % 32) {  // clear the bits past row m - 1 (as the host packing leaves them)
+      hipLaunchKernelGGL(k_clear_tail_bits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, c->mask, n, c->mw,
+                         (uint32_t)((1u << (m % 32)) - 1u));
+      if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        rpca_destroy(c);
+        return RPCA_EHIP;
+      }
     }
   }
   c->sweep_wgs =
@@ -355,6 +380,12 @@ int rpca_create_waves(int64_t m, int64_t n, int32_t k, double lam_s, double lam_
                       int32_t target_waves, rpca_ctx** out) {
   if (target_waves < 0 || target_waves > (1 << 20)) return RPCA_EINVAL;
   return rpca::create_ctx(m, n, k, lam_s, lam_l, mask, target_waves, out);
+}
+
+int rpca_create_device_mask(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l,
+                            const uint32_t* mask_bits, int32_t target_waves, rpca_ctx** out) {
+  if (!mask_bits || target_waves < 0 || target_waves > (1 << 20)) return RPCA_EINVAL;
+  return rpca::create_ctx(m, n, k, lam_s, lam_l, nullptr, target_waves, out, mask_bits);
 }
 
 

@@ -762,6 +762,99 @@ hipError_t right_product(const rpca::CtxView& cv, const Workspace& w, const floa
   return hipSuccess;
 }
 
+// Growth column on the device (rank growth, Sec. 4.1).  part[b * k + j] = block b's
+// share of U^T y (U: m x k FP32 row-major, y: m FP64), rows in a grid-stride order.
+__global__ __launch_bounds__(THREADS) void k_uty(const float* __restrict__ U, const double* __restrict__ y,
+                                                 int64_t m, int k, double* __restrict__ part) {
+  __shared__ double red[WAVES][32];
+  double acc[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * THREADS) {
+    const double yi = y[i];
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if (j < k) acc[j] += (double)U[i * k + j] * yi;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    double v = acc[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[w][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double t = 0.0;
+    for (int ww = 0; ww < WAVES; ++ww) t += red[ww][threadIdx.x];
+    part[(int64_t)blockIdx.x * k + threadIdx.x] = t;
+  }
+}
+
+// back = T_U (T_U^T Uty) (k values): one thread; T_U is k x r row-major
+__global__ void k_growth_back(const double* __restrict__ Uty, const double* __restrict__ TU, int k, int r,
+                              double* __restrict__ back) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double coef[32];
+  for (int q = 0; q < r; ++q) {
+    double c = 0.0;
+    for (int j = 0; j < k; ++j) c += TU[j * r + q] * Uty[j];
+    coef[q] = c;
+  }
+  for (int j = 0; j < k; ++j) {
+    double b = 0.0;
+    for (int q = 0; q < r; ++q) b += TU[j * r + q] * coef[q];
+    back[j] = b;
+  }
+}
+
+// y_i -= U_i . back (back null: y unchanged); part[b] = block b's share of ||y||^2
+__global__ __launch_bounds__(THREADS) void k_growth_project(const float* __restrict__ U,
+                                                            const double* __restrict__ back, int64_t m, int k,
+                                                            double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double red[WAVES];
+  double nn = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x; i < m; i += (int64_t)gridDim.x * THREADS) {
+    double v = y[i];
+    if (back) {
+      double sacc = 0.0;
+      for (int j = 0; j < k; ++j) sacc += (double)U[i * k + j] * back[j];
+      v -= sacc;
+      y[i] = v;
+    }
+    nn += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < WAVES; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// From ||P_U^perp y_raw||^2 (nn) with D v = y_raw / lam_L: sigma, t = lam_L (sigma - 1)_+,
+// u_col = sqrt(t) y / ||y||, v_col = -sqrt(t) v; res = {sigma, t}
+__global__ __launch_bounds__(THREADS) void k_growth_cols(const double* __restrict__ y, const double* __restrict__ v,
+                                                         const double* __restrict__ nn, int64_t m, int64_t n,
+                                                         double lam_l, float* __restrict__ u_col,
+                                                         float* __restrict__ v_col, double* __restrict__ res) {
+  const double norm = sqrt(*nn);
+  const double sigma = norm / lam_l;
+  const double t = sigma > 1.0 ? lam_l * (sigma - 1.0) : 0.0;
+  const double st = sqrt(t);
+  const double su = norm > 0.0 ? st / norm : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * THREADS;
+  for (int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x; i < m; i += stride)
+    u_col[i] = norm > 0.0 ? (float)(su * y[i]) : 0.f;  // y is not read without a Ritz vector
+  for (int64_t j = (int64_t)blockIdx.x * THREADS + threadIdx.x; j < n; j += stride) v_col[j] = (float)(-st * v[j]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    res[0] = sigma;
+    res[1] = t;
+  }
+}
+
 // Wf (n x 16 FP32) = columns [col0, col0 + bw) of the FP64 block W (ld ldw), zero beyond
 __global__ void k_pack_w16(const double* W, int ldw, int col0, int bw, int64_t n, float* Wf) {
   const int64_t idx = (int64_t)blockIdx.x * THREADS + threadIdx.x;
@@ -1501,56 +1594,54 @@ int growth_direction_impl(rpca_ctx* c, const float* X, const float* U, const flo
   if (cert_out) *cert_out = cert;
   Workspace ws;
   if ((rc = get_workspace(c, &ws, s))) return rc;
-  double sigma = 0.0;
-  std::vector<double> u((size_t)m, 0.0);
   // every early return below first waits for the copies that use this frame's
-  // host vectors (ex.v, y, Uh, uc, vc)
+  // host vectors (ex.v, the transform)
   auto fail = [&]() {
     (void)hipStreamSynchronize(s);
     return RPCA_EHIP;
   };
+  const unsigned gblocks = (unsigned)std::min<int64_t>(256, (m + THREADS - 1) / THREADS);
+  const unsigned cblocks = (unsigned)std::min<int64_t>(1024, (std::max(m, n) + THREADS - 1) / THREADS);
+  double* res = ws.scal + 20;  // {sigma, t}
+  double* nnd = ws.scal + 22;  // ||P_U^perp y||^2
+  const double* vdev = ws.Wd;
   if (!ex.v.empty()) {
-    // y = D v = G v / lam_L (one left product, b = 1)
-    if (hipMemcpyAsync(ws.Wd, ex.v.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess) return fail();
-    if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, 1, ws.Yd, 1, 1, s) != hipSuccess) return fail();
-    std::vector<double> y((size_t)m);
-    std::vector<float> Uh((size_t)m * k);
-    if (hipMemcpyAsync(y.data(), ws.Yd, (size_t)m * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(Uh.data(), U, (size_t)m * k * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail();
-    for (auto& x : y) x /= lam_l;
-    // P_U^perp y = y - U1 (U1^T y), U1 = U T_U (m x r)
+    // y = G v (one left product, b = 1; D v = y / lam_L), then P_U^perp y with
+    // U1 = U T_U and its norm, all on the device
+    double* pin = ws.pin;  // the transform, then v (n doubles; capacity PIN_SMALL + 64 n)
     const int r = ex.r;
+    memcpy(pin + PIN_SMALL, ex.v.data(), (size_t)n * 8);
+    if (hipMemcpyAsync(ws.Wd, pin + PIN_SMALL, (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail();
+    if (left_product(cv, ws, X, SRC_RESID, U, V, ws.Wd, 1, ws.Yd, 1, 1, s) != hipSuccess) return fail();
+    const double* back = nullptr;
     if (r) {
-      std::vector<double> Uty((size_t)k, 0.0), coef((size_t)r, 0.0), back((size_t)k, 0.0);
-      for (int64_t i = 0; i < m; ++i)
-        for (int j = 0; j < k; ++j) Uty[(size_t)j] += (double)Uh[(size_t)i * k + j] * y[(size_t)i];
-      for (int q = 0; q < r; ++q)
-        for (int j = 0; j < k; ++j) coef[(size_t)q] += ex.TU[(size_t)j * r + q] * Uty[(size_t)j];
-      for (int j = 0; j < k; ++j)
-        for (int q = 0; q < r; ++q) back[(size_t)j] += ex.TU[(size_t)j * r + q] * coef[(size_t)q];
-      for (int64_t i = 0; i < m; ++i) {
-        double sacc = 0.0;
-        for (int j = 0; j < k; ++j) sacc += (double)Uh[(size_t)i * k + j] * back[(size_t)j];
-        y[(size_t)i] -= sacc;
-      }
+      memcpy(pin, ex.TU.data(), (size_t)k * r * 8);
+      double* TUd = ws.T;             // k x r
+      double* Uty = ws.T + 64 * 32;   // k
+      double* backd = Uty + 32;       // k
+      if (hipMemcpyAsync(TUd, pin, (size_t)k * r * 8, hipMemcpyHostToDevice, s) != hipSuccess) return fail();
+      hipLaunchKernelGGL(k_uty, dim3(gblocks), dim3(THREADS), 0, s, U, (const double*)ws.Yd, m, k, ws.gram);
+      hipLaunchKernelGGL(k_gram_sum, dim3(k), dim3(THREADS), 0, s, (const double*)ws.gram, (int)gblocks, k, Uty);
+      hipLaunchKernelGGL(k_growth_back, dim3(1), dim3(64), 0, s, (const double*)Uty, (const double*)TUd, k, r,
+                         backd);
+      if (hipGetLastError() != hipSuccess) return fail();
+      back = backd;
     }
-    double nn = 0.0;
-    for (double x : y) nn += x * x;
-    sigma = sqrt(nn);
-    if (sigma > 0)
-      for (int64_t i = 0; i < m; ++i) u[(size_t)i] = y[(size_t)i] / sigma;
+    hipLaunchKernelGGL(k_growth_project, dim3(gblocks), dim3(THREADS), 0, s, U, back, m, k, ws.Yd, ws.gram);
+    hipLaunchKernelGGL(k_gram_sum, dim3(1), dim3(THREADS), 0, s, (const double*)ws.gram, (int)gblocks, 1, nnd);
+    if (hipGetLastError() != hipSuccess) return fail();
+  } else {
+    // no Ritz vector (nothing to grow): zero columns
+    if (hipMemsetAsync(nnd, 0, 8, s) != hipSuccess || hipMemsetAsync(ws.Wd, 0, (size_t)n * 8, s) != hipSuccess)
+      return fail();
   }
-  const double t = sigma > 1.0 ? lam_l * (sigma - 1.0) : 0.0;
-  const double st = sqrt(t);
-  std::vector<float> uc((size_t)m), vc((size_t)n);
-  for (int64_t i = 0; i < m; ++i) uc[(size_t)i] = (float)(st * u[(size_t)i]);
-  for (int64_t j = 0; j < n; ++j) vc[(size_t)j] = ex.v.empty() ? 0.f : (float)(-st * ex.v[(size_t)j]);
-  if (hipMemcpyAsync(u_col, uc.data(), (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(v_col, vc.data(), (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)  // the host sources die with this frame
+  hipLaunchKernelGGL(k_growth_cols, dim3(cblocks), dim3(THREADS), 0, s, (const double*)ws.Yd, vdev,
+                     (const double*)nnd, m, n, lam_l, u_col, v_col, res);
+  if (hipGetLastError() != hipSuccess) return fail();
+  if (hipMemcpyAsync(ws.pin, res, 2 * 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
     return fail();
+  const double sigma = ws.pin[0], t = ws.pin[1];
   *sigma_out = sigma;
   *t_out = t;
   return RPCA_OK;

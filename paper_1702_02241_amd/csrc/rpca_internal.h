@@ -186,7 +186,7 @@ int sweep_blocks_for(int64_t m, int64_t n, int k, int* row_groups, int* strips_p
                      int* nchunks, int target_waves = 0);
 // rpca_create with the sweep's wave target given (0: the tuning table's).
 int create_ctx(int64_t m, int64_t n, int32_t k, double lam_s, double lam_l, const uint8_t* mask,
-               int target_waves, rpca_ctx** out);
+               int target_waves, rpca_ctx** out, const uint32_t* mask_bits_dev = nullptr);
 hipError_t launch_objgrad(const SweepArgs& sa, const FinishArgs& fa, bool trial, bool bf16,
                           hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs& sa, bool trial, bool bf16, hipStream_t stream);

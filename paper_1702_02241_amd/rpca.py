@@ -119,6 +119,7 @@ def lib():
             "rpca_default_opts": (None, [ctypes.POINTER(rpca_opts)]),
             "rpca_create": (I32, [I64, I64, I32, D, D, P, ctypes.POINTER(P)]),
             "rpca_create_waves": (I32, [I64, I64, I32, D, D, P, I32, ctypes.POINTER(P)]),
+            "rpca_create_device_mask": (I32, [I64, I64, I32, D, D, P, I32, ctypes.POINTER(P)]),
             "rpca_objgrad": (I32, [P, P, P, P, P, P, P, P]),
             "rpca_set_elastic": (I32, [P, D]),
             "rpca_sweep_layout": (I32, [P, ctypes.POINTER(I32 * 4)]),
@@ -179,6 +180,14 @@ def default_opts():
     o = rpca_opts()
     lib().rpca_default_opts(ctypes.byref(o))
     return o
+
+
+def rpca_create_device_mask(m, n, k, lam_s, lam_l, mask_bits_ptr, waves=0):
+    """mask_bits_ptr: device address of the packed bitmask (column-major words of 32
+    rows).  Returns (status, ctx)."""
+    ctx = ctypes.c_void_p()
+    rc = lib().rpca_create_device_mask(m, n, k, lam_s, lam_l, mask_bits_ptr, int(waves), ctypes.byref(ctx))
+    return rc, ctx
 
 
 def rpca_create(m, n, k, lam_s, lam_l, mask=None, waves=None):

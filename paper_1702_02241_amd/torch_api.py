@@ -27,8 +27,13 @@ def to_device_factor(A, device="cuda"):
 class Context:
     """Owns an rpca_ctx for one problem shape."""
 
-    def __init__(self, m, n, k, lam_s, lam_l, mask=None, waves=None, mu=0.0):
-        rc, self.ctx = R.rpca_create(m, n, k, lam_s, lam_l, mask, waves)
+    def __init__(self, m, n, k, lam_s, lam_l, mask=None, waves=None, mu=0.0, mask_bits=None):
+        """mask: host array (m x n, nonzero = observed); or mask_bits: a device tensor
+        holding the packed bitmask (int32/uint32 words, column-major, 32 rows a word)."""
+        if mask_bits is not None:
+            rc, self.ctx = R.rpca_create_device_mask(m, n, k, lam_s, lam_l, mask_bits.data_ptr(), waves or 0)
+        else:
+            rc, self.ctx = R.rpca_create(m, n, k, lam_s, lam_l, mask, waves)
         if rc != R.RPCA_OK:
             raise RuntimeError(f"rpca_create failed: {R.rpca_status_string(rc)}")
         self.m, self.n, self.k = m, n, k

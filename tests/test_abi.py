@@ -204,3 +204,10 @@ def test_objgrad_noalloc_rejects_bad_arguments_and_oversize_before_hip():
 
 def test_set_graphs_rejects_null_context():
     assert R.lib().rpca_set_graphs(None, 1) == R.RPCA_EINVAL
+
+
+def test_create_device_mask_rejects_null_mask():
+    rc, _ = R.rpca_create_device_mask(64, 32, 4, 0.1, 1.0, None, 0)
+    assert rc == R.RPCA_EINVAL
+    rc, _ = R.rpca_create_device_mask(64, 32, 4, 0.1, 1.0, 16, -1)
+    assert rc == R.RPCA_EINVAL
