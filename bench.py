@@ -214,8 +214,11 @@ def run_fw(args):
     launches, ms = fw.profile_read(reset=True)
     fw.profile(False)
     blk = 8
+    # the "right" class is the power step: for n <= 256 the fused G^T (G X_b) pass (one read
+    # of G, the 16-column block and the per-workgroup sums), else the G^T Y product
     names = ["update", "left", "right", "bilinear"]
-    alg = [16 * m * n, 4 * m * n + 4 * blk * m, 4 * m * n + 4 * blk * m, 4 * m * n + 4 * m]
+    alg = [16 * m * n, 4 * m * n + 4 * blk * m, 4 * m * n + (64 * n if n <= 256 else 4 * blk * m),
+           4 * m * n + 4 * m]
     per = {nm: dict(launches=int(launches[i]) // max(args.steps, 1), ms=round(ms[i] / max(args.steps, 1), 3),
                     us_per_launch=round(1000 * ms[i] / max(launches[i], 1), 2)) for i, nm in enumerate(names)}
     dom = max(range(4), key=lambda i: ms[i])
@@ -223,7 +226,8 @@ def run_fw(args):
     achieved = alg[dom] / (k_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel=f"k_fw_{names[dom]}", kernel_ms=round(k_ms, 5), launches=int(launches[dom]),
+                    kernel=("k_gram_apply (fused G^T G X_b)" if names[dom] == "right" and n <= 256
+                            else f"k_fw_{names[dom]}"), kernel_ms=round(k_ms, 5), launches=int(launches[dom]),
                     alg_bytes_per_launch=alg[dom])
     cpu = None
     if not args.no_cpu:
@@ -260,9 +264,6 @@ def run_fw(args):
         "power_steps_per_iter": round(last.power_iters / max(last.iters, 1), 2),
         "kernel_ms_per_step": per,
         "roofline": roofline,
-        "mfma": mfma,
-        "roofline_bf16": roofline_bf16,
-        "other_precision": comparison,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

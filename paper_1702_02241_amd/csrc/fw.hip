@@ -27,6 +27,7 @@
 
 #include "rpca.h"
 #include "rpca_fw.h"
+#include "rpca_internal.h"
 #include "smalllinalg.h"
 
 namespace {
@@ -387,6 +388,12 @@ struct rpca_fw {
   double* zpin = nullptr;       // pinned staging: Z (n x BLK doubles) in, block and v out
   float* xpin = nullptr;        // n x BLK floats
   float* vpin = nullptr;        // n floats
+  // fused G^T G Xb in one pass over G (n <= 256): the block as FP32 n x 16, the
+  // per-workgroup sums and their FP64 segment sums
+  float* Wf = nullptr;
+  float* gpart = nullptr;
+  double* glvl = nullptr;
+  int rg_ga = 0;
   std::vector<double> Xh;       // host copy of the block (FP64)
   int64_t rb_upd = 0, nchunks_left = 0, rc_right = 0, rc_bil = 0;
   bool x_valid = false;
@@ -450,7 +457,7 @@ void fw_free(rpca_fw* h) {
   fw_collect(h);
   for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
   for (void* p : {(void*)h->mask, (void*)h->G, (void*)h->ypart, (void*)h->Y, (void*)h->y, (void*)h->Xb, (void*)h->v,
-                  (void*)h->part, (void*)h->Z, (void*)h->res})
+                  (void*)h->part, (void*)h->Z, (void*)h->res, (void*)h->Wf, (void*)h->gpart, (void*)h->glvl})
     if (p) (void)hipFree(p);
   // a failed free must not stay pending: the caller's next error check would see it
   for (void* p : {(void*)h->res_host, (void*)h->zpin, (void*)h->xpin, (void*)h->vpin})
@@ -528,7 +535,31 @@ void orth_block(std::vector<double>& Xh, int64_t n, int b, uint64_t salt) {
 int upload_block(rpca_fw* h, hipStream_t s) {
   for (size_t e = 0; e < h->Xh.size(); ++e) h->xpin[e] = (float)h->Xh[e];
   FWCHK(hipMemcpyAsync(h->Xb, h->xpin, h->Xh.size() * 4, hipMemcpyHostToDevice, s));
+  if (h->gpart) {  // the same block padded to 16 columns for the fused pass
+    float* w16 = h->xpin + h->Xh.size();
+    for (int64_t j = 0; j < h->n; ++j)
+      for (int c = 0; c < 16; ++c) w16[(size_t)j * 16 + c] = c < BLK ? h->xpin[(size_t)j * BLK + c] : 0.f;
+    FWCHK(hipMemcpyAsync(h->Wf, w16, (size_t)h->n * 16 * 4, hipMemcpyHostToDevice, s));
+  }
   return RPCA_OK;
+}
+
+// Y = G Xb (left product and its chunk sum)
+hipError_t fw_left(rpca_fw* h, hipStream_t s) {
+  const int64_t m = h->m, n = h->n;
+  const int64_t lblocks = h->rb_upd * h->nchunks_left;
+  hipError_t e = fw_timed(h, RPCA_FW_K_LEFT, s, [&] {
+    if (h->vec == 4)
+      hipLaunchKernelGGL(k_fw_left<4>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+    else
+      hipLaunchKernelGGL(k_fw_left<1>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
+                         (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fw_left_finish, dim3((unsigned)((m * BLK + TH - 1) / TH)), dim3(TH), 0, s,
+                     (const float*)h->ypart, h->nchunks_left, m * BLK, h->Y);
+  return hipGetLastError();
 }
 
 // Linear minimisation: top singular triplet of G by block power iteration with
@@ -542,28 +573,34 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
   const int64_t rblocks = h->rc_right * ncb;
   std::vector<double> Zh((size_t)n * BLK), H((size_t)b * b), th(b), W((size_t)b * b), ZW((size_t)n * BLK);
   for (int p = 0;; ++p) {
-    FWCHK(fw_timed(h, RPCA_FW_K_LEFT, s, [&] {
-      if (h->vec == 4)
-        hipLaunchKernelGGL(k_fw_left<4>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
-                           (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
-      else
-        hipLaunchKernelGGL(k_fw_left<1>, dim3((unsigned)lblocks), dim3(TH), 0, s, (const float*)h->G,
-                           (const float*)h->Xb, m, n, h->rb_upd, h->ypart);
-    }));
-    hipLaunchKernelGGL(k_fw_left_finish, dim3((unsigned)((m * BLK + TH - 1) / TH)), dim3(TH), 0, s,
-                       (const float*)h->ypart, h->nchunks_left, m * BLK, h->Y);
-    FWCHK(hipGetLastError());
-    FWCHK(fw_timed(h, RPCA_FW_K_RIGHT, s, [&] {
-      if (h->vec == 4)
-        hipLaunchKernelGGL(k_fw_right<4>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
-                           (const float*)h->Y, m, n, ncb, h->part);
-      else
-        hipLaunchKernelGGL(k_fw_right<1>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
-                           (const float*)h->Y, m, n, ncb, h->part);
-    }));
-    hipLaunchKernelGGL(k_fw_right_finish, dim3((unsigned)((n * BLK + TH - 1) / TH)), dim3(TH), 0, s,
-                       (const double*)h->part, h->rc_right, n * BLK, h->Z);
-    FWCHK(hipGetLastError());
+    if (h->gpart) {
+      // Z = G^T G Xb in one pass over G (Y is formed once, at the end)
+      rpca::GramApplyArgs ga;
+      memset(&ga, 0, sizeof(ga));
+      ga.X = h->G;
+      ga.m = m;
+      ga.n = n;
+      ga.W = h->Wf;
+      ga.part = h->gpart;
+      ga.row_groups = h->rg_ga;
+      ga.xvec = h->vec == 4 ? 1 : 0;
+      hipError_t ge = hipSuccess;
+      FWCHK(fw_timed(h, RPCA_FW_K_RIGHT, s, [&] { ge = rpca::launch_gram_apply(ga, false, h->glvl, h->Z, BLK, 0, b, 1.0, s); }));
+      FWCHK(ge);
+    } else {
+      FWCHK(fw_left(h, s));
+      FWCHK(fw_timed(h, RPCA_FW_K_RIGHT, s, [&] {
+        if (h->vec == 4)
+          hipLaunchKernelGGL(k_fw_right<4>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                             (const float*)h->Y, m, n, ncb, h->part);
+        else
+          hipLaunchKernelGGL(k_fw_right<1>, dim3((unsigned)rblocks), dim3(TH), 0, s, (const float*)h->G,
+                             (const float*)h->Y, m, n, ncb, h->part);
+      }));
+      hipLaunchKernelGGL(k_fw_right_finish, dim3((unsigned)((n * BLK + TH - 1) / TH)), dim3(TH), 0, s,
+                         (const double*)h->part, h->rc_right, n * BLK, h->Z);
+      FWCHK(hipGetLastError());
+    }
     FWCHK(hipMemcpyAsync(h->zpin, h->Z, Zh.size() * 8, hipMemcpyDeviceToHost, s));
     FWCHK(hipStreamSynchronize(s));
     memcpy(Zh.data(), h->zpin, Zh.size() * 8);
@@ -602,6 +639,7 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
       Coef cw;
       for (int a = 0; a < BLK; ++a) cw.w[a] = a < b ? (float)W[(size_t)a * b] : 0.f;
       FWCHK(hipMemcpyAsync(h->v, h->vpin, (size_t)n * 4, hipMemcpyHostToDevice, s));
+      if (h->gpart) FWCHK(fw_left(h, s));  // Y = G Xb for this step's block
       hipLaunchKernelGGL(k_fw_combine, dim3((unsigned)((m + TH - 1) / TH)), dim3(TH), 0, s, (const float*)h->Y, cw, m,
                          h->y);
       FWCHK(hipGetLastError());
@@ -689,10 +727,22 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_s, double lam_l, const uint8
        hipMalloc(&h->part, (size_t)parts * 8) == hipSuccess && hipMalloc(&h->Z, (size_t)(n * BLK) * 8) == hipSuccess &&
        hipMalloc(&h->res, 16 * 8) == hipSuccess && hipHostMalloc(&h->res_host, 16 * 8, hipHostMallocDefault) == hipSuccess &&
        hipHostMalloc(&h->zpin, (size_t)(n * BLK) * 8, hipHostMallocDefault) == hipSuccess &&
-       hipHostMalloc(&h->xpin, (size_t)(n * BLK) * 4, hipHostMallocDefault) == hipSuccess &&
+       hipHostMalloc(&h->xpin, (size_t)(n * (BLK + 16)) * 4, hipHostMallocDefault) == hipSuccess &&
        hipHostMalloc(&h->vpin, (size_t)n * 4, hipHostMallocDefault) == hipSuccess;
   if (ok && (hipMemset(h->y, 0, (size_t)m * 4) != hipSuccess || hipMemset(h->v, 0, (size_t)n * 4) != hipSuccess))
     ok = false;
+  if (ok && rpca::gram_apply_fits(n, 0)) {
+    // the fused power step: one workgroup per compute unit, two strips a wave at least
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    h->rg_ga = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((m + 15) / 16) / 8));
+    const int segs = rpca::gram_apply_segments(h->rg_ga);
+    ok = hipMalloc(&h->Wf, (size_t)n * 16 * 4) == hipSuccess &&
+         hipMalloc(&h->gpart, (size_t)h->rg_ga * n * 16 * 4) == hipSuccess &&
+         hipMalloc(&h->glvl, (size_t)segs * n * 16 * 8) == hipSuccess;
+  }
   if (ok && mask) {
     h->mw = (int)((m + 31) / 32);
     std::vector<uint32_t> bits((size_t)h->mw * (size_t)n, 0u);
