@@ -327,7 +327,8 @@ enum rpca_kernel_class {
   RPCA_K_TRIAL = 4,       /* the same sweep at line-search trial points */
   RPCA_K_LEFT = 5,        /* thin product Op W of the certificate, the rSVD and the proximal baseline */
   RPCA_K_RIGHT = 6,       /* thin product Op^T Y (the same users) */
-  RPCA_K_GRAM = 7,        /* fused thin product Op^T (Op W) in one pass (certificate power steps) */
+  RPCA_K_GRAM = 7,        /* fused thin product Op^T (Op W) in one pass, per-workgroup sums (certificate
+                             and rSVD power steps; the FP64 sum over workgroups is not counted) */
   RPCA_K_NCLASS = 8
 };
 

@@ -73,7 +73,9 @@ void rpca_fw_destroy(rpca_fw* fw);
 enum rpca_fw_kernel {
   RPCA_FW_K_UPDATE = 0,    /* L <- a L + b y v^T and G: reads L, X; writes L, G */
   RPCA_FW_K_LEFT = 1,      /* partial Y = G Xb over column chunks: reads G */
-  RPCA_FW_K_RIGHT = 2,     /* partial Z = G^T Y over row chunks: reads G and Y */
+  RPCA_FW_K_RIGHT = 2,     /* the power step: for n <= 256 the per-workgroup sums of
+                              G^T (G Xb) in one pass over G (reads G), else the
+                              partial Z = G^T Y over row chunks (reads G and Y) */
   RPCA_FW_K_BILINEAR = 3   /* u^T P_Omega(L) v: reads L */
 };
 typedef struct rpca_fw_profile {

@@ -648,10 +648,9 @@ struct Workspace {
   double* pin;
   int rg_left, spw_left, rg_right, spw_right, nch_right, gram_blocks;
   // fused Op^T Op W pass (n <= 256, k <= 16): W in FP32 (n x 16), per-workgroup
-  // sums, FP64 segment sums
+  // sums
   float* Wf;
   float* gpart;
-  double* glvl;
   int rg_ga;
 };
 constexpr size_t PIN_SMALL = 4096;
@@ -887,10 +886,10 @@ hipError_t gram_product(const rpca::CtxView& cv, const Workspace& w, const float
   a.xvec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0 && cv.m % 4 == 0) ? 1 : 0;
   void* tok = nullptr;
   if (cv.ctx && rpca::prof_begin(cv.ctx, s, &tok) != hipSuccess) return hipErrorUnknown;
-  const hipError_t e = rpca::launch_gram_apply(a, src == SRC_RESID, w.glvl, Z, ldz, col0, b, 1.0, s);
+  hipError_t e = rpca::launch_gram_apply_pass(a, src == SRC_RESID, s);
   if (e != hipSuccess) return e;
   if (tok && rpca::prof_end(cv.ctx, RPCA_K_GRAM, s, tok) != hipSuccess) return hipErrorUnknown;
-  return hipSuccess;
+  return rpca::launch_gram_apply_sum(a, Z, ldz, col0, b, 1.0, s);
 }
 
 // Sum of the per-block Gram partials, one workgroup per entry e: out[e] = sum over
@@ -1129,7 +1128,6 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   const bool ga = rpca::gram_apply_fits(n, (int)k);
   const size_t sz_Wf = ga ? align_up(n * 16) * 4 : 0;
   const size_t sz_gpart = ga ? align_up((int64_t)w->rg_ga * n * 16) * 4 : 0;
-  const size_t sz_glvl = ga ? align_up((int64_t)rpca::gram_apply_segments(w->rg_ga) * n * 16) * 8 : 0;
   size_t off = 0;
   const size_t sz_W = align_up(n * LMAX) * 8, sz_Y = align_up(m * LMAX) * 8;
   const size_t sz_part = align_up((int64_t)w->rg_right * n * BP) * 8;
@@ -1137,7 +1135,7 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   const size_t sz_T = 64 * 64 * 8;
   const size_t sz_gU = align_up(m * k) * 4, sz_gV = align_up(n * k) * 4;
   const size_t total =
-      sz_W * 2 + sz_Y * 2 + sz_part + sz_gram + sz_T + sz_gU * 2 + sz_gV * 2 + 256 + sz_Wf + sz_gpart + sz_glvl;
+      sz_W * 2 + sz_Y * 2 + sz_part + sz_gram + sz_T + sz_gU * 2 + sz_gV * 2 + 256 + sz_Wf + sz_gpart;
   int fresh = 0;
   char* base = (char*)rpca::ctx_workspace(c, total, &fresh);
   if (!base) return RPCA_ENOMEM;
@@ -1158,7 +1156,6 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   w->gV = (float*)take(sz_gV);
   w->zV = (float*)take(sz_gV);
   w->scal = (double*)take(256);
-  w->glvl = ga ? (double*)take(sz_glvl) : nullptr;
   w->Wf = ga ? (float*)take(sz_Wf) : nullptr;
   w->gpart = ga ? (float*)take(sz_gpart) : nullptr;
   w->pin = (double*)rpca::ctx_pinned(c, (PIN_SMALL + (size_t)n * 64) * sizeof(double));

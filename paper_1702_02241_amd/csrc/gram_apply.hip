@@ -33,8 +33,9 @@ constexpr int GA_NG = GA_TMAX / GA_PF;
 
 template <bool RESID, bool MASKED>
 __global__ __launch_bounds__(NT, 1) void k_gram_apply(rpca::GramApplyArgs a) {
+  if (a.skip && *a.skip != 0.0) return;
   extern __shared__ float lds[];
-  constexpr int TMAX = GA_TMAX, PF = GA_PF, NG = GA_NG, NBUF = 2, D = NBUF - 1;
+  constexpr int TMAX = GA_TMAX, PF = GA_PF, NG = GA_NG, NBUF = 4, D = NBUF - 1;  // three groups in flight
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = lane & 15, g = lane >> 4;
@@ -274,45 +275,43 @@ __global__ __launch_bounds__(NT, 1) void k_gram_apply(rpca::GramApplyArgs a) {
   }
 }
 
-// level2[seg][o] = sum of part[r][o] over the workgroup rows r of segment seg (in order)
-__global__ __launch_bounds__(256) void k_ga_reduce1(const float* part, int64_t outs, int rows, int rows_per_seg,
-                                                    double* level2) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= outs) return;
-  const int r0 = blockIdx.y * rows_per_seg;
-  const int r1 = r0 + rows_per_seg < rows ? r0 + rows_per_seg : rows;
+// Z[j * ldz + col0 + p] = scale * (sum over workgroups r of part[r][j * 16 + p]), p < b.
+// One pass: a block takes GR_OUT consecutive outputs; its GR_SL row slices sum
+// workgroups sl, sl + GR_SL, ... in FP64 (all loads of a slice in flight at
+// once), then one thread per output adds the slices in slice order.  The order
+// depends only on the number of workgroups.
+constexpr int GR_OUT = 16, GR_SL = 16, GR_INF = 16;
+__global__ __launch_bounds__(256) void k_ga_reduce(const float* __restrict__ part, int64_t n, int rows, int b,
+                                                   double scale, double* __restrict__ Z, int ldz, int col0,
+                                                   const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
+  __shared__ double sh[GR_SL][GR_OUT + 1];
+  const int oo = threadIdx.x & (GR_OUT - 1), sl = threadIdx.x / GR_OUT;
+  const int64_t outs = n * b;
+  const int64_t o = (int64_t)blockIdx.x * GR_OUT + oo;
+  const int64_t oc = o < outs ? o : outs - 1;
+  const int64_t j = oc / b;
+  const int64_t src = j * 16 + (oc - j * b);
+  const int64_t stride = n * 16;
   double s = 0.0;
-  int r = r0;
-  for (; r + 7 < r1; r += 8) {  // eight loads in flight, summed in row order
-    float x[8];
+  for (int r0 = sl; r0 < rows; r0 += GR_SL * GR_INF) {
+    float x[GR_INF];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = part[(int64_t)(r + e) * outs + o];
+    for (int e = 0; e < GR_INF; ++e) {  // clamped rows: every load issued before the first use
+      const int r = r0 + e * GR_SL;
+      x[e] = part[(int64_t)(r < rows ? r : rows - 1) * stride + src];
+    }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) s += (double)x[e];
+    for (int e = 0; e < GR_INF; ++e) s += r0 + e * GR_SL < rows ? (double)x[e] : 0.0;
   }
-  for (; r < r1; ++r) s += (double)part[(int64_t)r * outs + o];
-  level2[(int64_t)blockIdx.y * outs + o] = s;
-}
-
-// Z[j * ldz + col0 + p] = scale * (sum over segments of level2[.][j * 16 + p]), p < b
-__global__ __launch_bounds__(256) void k_ga_reduce2(const double* level2, int64_t n, int segs, int b, double scale,
-                                                    double* Z, int ldz, int col0) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (o >= n * b) return;
-  const int64_t j = o / b;
-  const int p = (int)(o - j * b);
-  const int64_t src = j * 16 + p;
-  double s = 0.0;
-  int q = 0;
-  for (; q + 7 < segs; q += 8) {
-    double x[8];
+  sh[sl][oo] = s;
+  __syncthreads();
+  if (sl == 0 && o < outs) {
+    double t = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = level2[(int64_t)(q + e) * n * 16 + src];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s += x[e];
+    for (int q = 0; q < GR_SL; ++q) t += sh[q][oo];
+    Z[j * ldz + col0 + (o - j * b)] = scale * t;
   }
-  for (; q < segs; ++q) s += level2[(int64_t)q * n * 16 + src];
-  Z[j * ldz + col0 + p] = scale * s;
 }
 
 }  // namespace
@@ -328,11 +327,8 @@ size_t gram_apply_lds_bytes(int64_t n) {
 
 bool gram_apply_fits(int64_t n, int k) { return n >= 1 && n <= 16 * GA_TMAX && k >= 0 && k <= 16; }
 
-int gram_apply_segments(int row_groups) { return (row_groups + 15) / 16; }
-
-hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* level2, double* Z, int ldz, int col0,
-                             int b, double scale, hipStream_t s) {
-  if (!gram_apply_fits(a.n, resid ? a.k : 0) || b < 1 || b > 16 || a.row_groups < 1) return hipErrorInvalidValue;
+hipError_t launch_gram_apply_pass(const GramApplyArgs& a, bool resid, hipStream_t s) {
+  if (!gram_apply_fits(a.n, resid ? a.k : 0) || a.row_groups < 1) return hipErrorInvalidValue;
   const size_t lb = gram_apply_lds_bytes(a.n);
   const dim3 grid((unsigned)a.row_groups);
   if (resid) {
@@ -342,18 +338,24 @@ hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* level2,
     if (a.mask) hipLaunchKernelGGL((k_gram_apply<false, true>), grid, dim3(NT), lb, s, a);
     else hipLaunchKernelGGL((k_gram_apply<false, false>), grid, dim3(NT), lb, s, a);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t outs = a.n * 16;
-  const int segs = gram_apply_segments(a.row_groups);
-  const int rps = (a.row_groups + segs - 1) / segs;
-  hipLaunchKernelGGL(k_ga_reduce1, dim3((unsigned)((outs + 255) / 256), (unsigned)segs), dim3(256), 0, s,
-                     (const float*)a.part, outs, a.row_groups, rps, level2);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ga_reduce2, dim3((unsigned)((a.n * b + 255) / 256)), dim3(256), 0, s, (const double*)level2,
-                     a.n, segs, b, scale, Z, ldz, col0);
   return hipGetLastError();
+}
+
+hipError_t launch_gram_apply_sum(const GramApplyArgs& a, double* Z, int ldz, int col0, int b, double scale,
+                                 hipStream_t s) {
+  if (a.n < 1 || b < 1 || b > 16 || a.row_groups < 1) return hipErrorInvalidValue;
+  const int64_t outs = a.n * b;
+  hipLaunchKernelGGL(k_ga_reduce, dim3((unsigned)((outs + GR_OUT - 1) / GR_OUT)), dim3(GR_OUT * GR_SL), 0, s,
+                     (const float*)a.part, a.n, a.row_groups, b, scale, Z, ldz, col0, a.skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* Z, int ldz, int col0, int b, double scale,
+                             hipStream_t s) {
+  if (b < 1 || b > 16) return hipErrorInvalidValue;
+  const hipError_t e = launch_gram_apply_pass(a, resid, s);
+  if (e != hipSuccess) return e;
+  return launch_gram_apply_sum(a, Z, ldz, col0, b, scale, s);
 }
 
 }  // namespace rpca

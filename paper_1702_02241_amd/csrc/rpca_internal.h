@@ -310,12 +310,17 @@ struct GramApplyArgs {
   float* part;            // [row_groups][n * 16] per-workgroup sums
   int32_t row_groups;     // workgroups (grid)
   int32_t xvec;           // 1: X is 16-byte aligned and m % 4 == 0
+  const double* skip;     // null, or a device flag: when nonzero the pass and its sum do nothing
 };
 bool gram_apply_fits(int64_t n, int k);
 size_t gram_apply_lds_bytes(int64_t n);
-int gram_apply_segments(int row_groups);
-// Z[j * ldz + col0 + p] = scale * (Op^T Op W)[j][p] for p < b (FP64 output; level2:
-// gram_apply_segments(row_groups) * n * 16 doubles of scratch).
-hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* level2, double* Z, int ldz, int col0,
-                             int b, double scale, hipStream_t s);
+// The pass: per-workgroup FP32 sums into a.part.
+hipError_t launch_gram_apply_pass(const GramApplyArgs& a, bool resid, hipStream_t s);
+// The sum over workgroups (FP64, fixed order):
+// Z[j * ldz + col0 + p] = scale * (Op^T Op W)[j][p] for p < b.
+hipError_t launch_gram_apply_sum(const GramApplyArgs& a, double* Z, int ldz, int col0, int b, double scale,
+                                 hipStream_t s);
+// Both.
+hipError_t launch_gram_apply(const GramApplyArgs& a, bool resid, double* Z, int ldz, int col0, int b, double scale,
+                             hipStream_t s);
 }  // namespace rpca

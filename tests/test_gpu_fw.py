@@ -2,8 +2,9 @@
 oracle.frank_wolfe.
 
 * one iteration from an oracle iterate (L_k, t_k), on shapes that take the
-  vector and scalar layouts, ragged row blocks and column chunks, with and
-  without a mask: L_{k+1}, t_{k+1} and the next iterate's F, gap and sigma;
+  vector and scalar layouts, ragged row blocks and column chunks, the fused
+  G^T G pass (n <= 256) and the separate products (n > 256), with and without
+  a mask: L_{k+1}, t_{k+1} and the next iterate's F, gap and sigma;
 * the start evaluated alone (max_iter = 0): F, gap, sigma, L untouched;
 * a 300-iteration solve from zero: the objective never increases across calls,
   the gap bounds F - F* (FISTA-SVT), and F tracks the oracle's trajectory;
@@ -51,7 +52,7 @@ def _oracle_iterates(p, k):
 
 
 @pytest.mark.parametrize("m,n,masked", [(300, 120, False), (301, 77, True), (2084, 150, False),
-                                        (2084, 150, True)])
+                                        (2084, 150, True), (520, 300, False), (523, 301, True)])
 def test_one_iteration_matches_oracle(m, n, masked):
     p = _problem(m, n, masked, 80 + m + n)
     dev = device()
