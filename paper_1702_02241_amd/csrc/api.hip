@@ -460,6 +460,8 @@ CtxView ctx_view(rpca_ctx* c) {
   return v;
 }
 
+bool prof_enabled(const rpca_ctx* c) { return c && c->prof_on; }
+
 hipError_t prof_begin(rpca_ctx* c, hipStream_t s, void** token) {
   *token = nullptr;
   if (!c->prof_on) return hipSuccess;

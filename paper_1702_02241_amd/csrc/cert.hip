@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "rpca_internal.h"
+#include "ritz_kernel.h"
 #include "smalllinalg.h"
 
 namespace {
@@ -652,6 +653,18 @@ struct Workspace {
   float* Wf;
   float* gpart;
   int rg_ga;
+  // the power iteration's steps on the device (with the fused pass): two n x BLK
+  // FP64 blocks, a second FP32 block (n x 16), the projected product (n x BLK),
+  // V_1 and B_n (n x RMAX), V_1^T B_n, the top Ritz vector (n), and 64 doubles of
+  // results and state
+  double* pxd[2];
+  float* Wf2;
+  double* pzf;
+  double* pv1;
+  double* pbn;
+  double* pvb;
+  double* pvtop;
+  double* pres;
 };
 constexpr size_t PIN_SMALL = 4096;
 
@@ -866,7 +879,8 @@ __global__ void k_pack_w16(const double* W, int ldw, int col0, int bw, int64_t n
 // Z (n x b, ld ldz, FP64) = Op^T Op W for the FP32 block W in w.Wf (n x 16), one
 // fused pass over X (the workspace has it when n <= 256 and k <= 16).
 hipError_t gram_product(const rpca::CtxView& cv, const Workspace& w, const float* X, int src, const float* U,
-                        const float* V, double* Z, int ldz, int b, hipStream_t s, int col0 = 0) {
+                        const float* V, double* Z, int ldz, int b, hipStream_t s, int col0 = 0,
+                        const float* Wsrc = nullptr, const double* skip = nullptr) {
   if (!w.gpart || src == SRC_PROX) return hipErrorInvalidValue;
   rpca::GramApplyArgs a;
   memset(&a, 0, sizeof(a));
@@ -880,8 +894,9 @@ hipError_t gram_product(const rpca::CtxView& cv, const Workspace& w, const float
   a.kappa = (float)cv.kappa;
   a.U = U;
   a.V = V;
-  a.W = w.Wf;
+  a.W = Wsrc ? Wsrc : w.Wf;
   a.part = w.gpart;
+  a.skip = skip;
   a.row_groups = w.rg_ga;
   a.xvec = ((reinterpret_cast<uintptr_t>(X) & 15) == 0 && cv.m % 4 == 0) ? 1 : 0;
   void* tok = nullptr;
@@ -1158,6 +1173,9 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   const bool ga = rpca::gram_apply_fits(n, (int)k);
   const size_t sz_Wf = ga ? align_up(n * 16) * 4 : 0;
   const size_t sz_gpart = ga ? align_up((int64_t)w->rg_ga * n * 16) * 4 : 0;
+  constexpr int BL = rpca_ritz::BLK, RM = rpca_ritz::RMAX;
+  const size_t sz_pblk = ga ? align_up(n * BL) * 8 : 0, sz_prk = ga ? align_up(n * RM) * 8 : 0;
+  const size_t sz_pdev = ga ? sz_pblk * 3 + sz_Wf + sz_prk * 2 + align_up(RM * RM) * 8 + align_up(n) * 8 + 64 * 8 : 0;
   size_t off = 0;
   const size_t sz_W = align_up(n * LMAX) * 8, sz_Y = align_up(m * LMAX) * 8;
   const size_t sz_part = align_up((int64_t)w->rg_right * n * BP) * 8;
@@ -1165,7 +1183,7 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   const size_t sz_T = 64 * 64 * 8;
   const size_t sz_gU = align_up(m * k) * 4, sz_gV = align_up(n * k) * 4;
   const size_t total =
-      sz_W * 2 + sz_Y * 2 + sz_part + sz_gram + sz_T + sz_gU * 2 + sz_gV * 2 + 256 + sz_Wf + sz_gpart;
+      sz_W * 2 + sz_Y * 2 + sz_part + sz_gram + sz_T + sz_gU * 2 + sz_gV * 2 + 256 + sz_Wf + sz_gpart + sz_pdev;
   int fresh = 0;
   char* base = (char*)rpca::ctx_workspace(c, total, &fresh);
   if (!base) return RPCA_ENOMEM;
@@ -1188,6 +1206,15 @@ int get_workspace(rpca_ctx* c, Workspace* w, hipStream_t s) {
   w->scal = (double*)take(256);
   w->Wf = ga ? (float*)take(sz_Wf) : nullptr;
   w->gpart = ga ? (float*)take(sz_gpart) : nullptr;
+  w->pxd[0] = ga ? (double*)take(sz_pblk) : nullptr;
+  w->pxd[1] = ga ? (double*)take(sz_pblk) : nullptr;
+  w->pzf = ga ? (double*)take(sz_pblk) : nullptr;
+  w->Wf2 = ga ? (float*)take(sz_Wf) : nullptr;
+  w->pv1 = ga ? (double*)take(sz_prk) : nullptr;
+  w->pbn = ga ? (double*)take(sz_prk) : nullptr;
+  w->pvb = ga ? (double*)take(align_up(RM * RM) * 8) : nullptr;
+  w->pvtop = ga ? (double*)take(align_up(n) * 8) : nullptr;
+  w->pres = ga ? (double*)take(64 * 8) : nullptr;
   w->pin = (double*)rpca::ctx_pinned(c, (PIN_SMALL + (size_t)n * 64) * sizeof(double));
   if (!w->pin) return RPCA_ENOMEM;
   if (fresh) {  // zero factors used for phi(0)
@@ -1442,6 +1469,105 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   for (int64_t i = 0; i < n * b; ++i) Xb[i] = normal_deviate(0xC0FFEEull, (uint64_t)i);
   int it_total = 0;
   const int max_it = 300;
+  // The steps on the device (fused pass, a block of at most BLK columns): per step
+  // the pass G^T G X, then k_block_ritz (the projection, Rayleigh-Ritz, the stop
+  // test above, the next block, X w_0); the host reads 9 doubles per step.  Unless
+  // kernel timing is on, the next step is queued before the host reads this one's
+  // stop flag, its kernels doing nothing once the flag is set.  Fills ritz, the
+  // next block Xbh and the top Ritz vector.
+  constexpr int BL = rpca_ritz::BLK;
+  const size_t o_blk = 32, o_w16 = o_blk + (size_t)n * BL, o_v1 = o_w16 + (size_t)n * 8,
+               o_bn = o_v1 + (size_t)n * r, o_vb = o_bn + (size_t)n * r, o_end = o_vb + (size_t)r * r;
+  const bool dev_ok = ws.pres != nullptr && r <= rpca_ritz::RMAX && o_end <= PIN_SMALL + (size_t)n * 64;
+  auto power_dev = [&](std::vector<double>& Xbh, int bb, int* steps) -> int {
+    struct Events {
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } ev;
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming) != hipSuccess) return RPCA_EHIP;
+    // pinned layout (doubles): [0, 32) two result slots, then the block (n x BL),
+    // its FP32 copy (n x 16 floats), V_1 and B_n (n x r), V_1^T B_n (r x r)
+    double* blk = pin + o_blk;
+    float* w16 = reinterpret_cast<float*>(pin + o_w16);
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < BL; ++c) blk[(size_t)i * BL + c] = c < bb ? Xbh[(size_t)i * bb + c] : 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < 16; ++c) w16[(size_t)i * 16 + c] = c < bb ? (float)Xbh[(size_t)i * bb + c] : 0.f;
+    if (hipMemcpyAsync(ws.pxd[0], blk, (size_t)n * BL * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ws.Wf, w16, (size_t)n * 16 * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return RPCA_EHIP;
+    if (r) {
+      memcpy(pin + o_v1, V1.data(), (size_t)n * r * 8);
+      memcpy(pin + o_bn, Bn.data(), (size_t)n * r * 8);
+      rpca::la::matmul_tn(V1.data(), Bn.data(), pin + o_vb, (int)n, r, r);
+      if (hipMemcpyAsync(ws.pv1, pin + o_v1, (size_t)n * r * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(ws.pbn, pin + o_bn, (size_t)n * r * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(ws.pvb, pin + o_vb, (size_t)r * r * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return RPCA_EHIP;
+    }
+    const bool ahead = !rpca::prof_enabled(cv.ctx);
+    auto enqueue = [&](int p) -> int {
+      const int cur = p & 1;
+      const double* skip = (ahead && p > 0) ? ws.pres : nullptr;
+      if (gram_product(cv, ws, X, SRC_RESID, U, V, ws.Zd, BL, bb, s, 0, cur ? ws.Wf2 : ws.Wf, skip) != hipSuccess)
+        return RPCA_EHIP;
+      rpca_ritz::RitzArgs ra;
+      memset(&ra, 0, sizeof(ra));
+      ra.X = ws.pxd[cur];
+      ra.Z = ws.Zd;
+      ra.n = n;
+      ra.b = bb;
+      ra.salt = 0xC0FFEEull + 977ull * (uint64_t)(p + 1);
+      ra.Xn = ws.pxd[cur ^ 1];
+      ra.Wfn = cur ? ws.Wf : ws.Wf2;
+      ra.res = ws.pres;
+      ra.skip = skip;
+      ra.last = p + 1 >= max_it ? 1 : 0;
+      ra.Zf = ws.pzf;
+      ra.V1 = ws.pv1;
+      ra.Bn = ws.pbn;
+      ra.VB = ws.pvb;
+      ra.r = r;
+      ra.inv_lam2 = 1.0 / (lam_l * lam_l);
+      ra.it = p;
+      ra.conv_rel = 1e-6;
+      ra.state = ws.pres + 32;
+      ra.vtop = ws.pvtop;
+      hipLaunchKernelGGL(rpca_ritz::k_block_ritz<rpca_ritz::RITZ_CERT>, dim3(1), dim3(rpca_ritz::RT), 0, s, ra);
+      if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+      if (hipMemcpyAsync(pin + 16 * (p & 1), ws.pres, 9 * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipEventRecord(ev.e[p & 1], s) != hipSuccess)
+        return RPCA_EHIP;
+      return RPCA_OK;
+    };
+    int rc2 = enqueue(0);
+    if (rc2) return rc2;
+    int p = 0;
+    for (;; ++p) {
+      if (ahead && p + 1 < max_it && (rc2 = enqueue(p + 1))) return rc2;
+      if (hipEventSynchronize(ev.e[p & 1]) != hipSuccess) return RPCA_EHIP;
+      if (pin[16 * (p & 1)] != 0.0 || p + 1 >= max_it) break;
+      if (!ahead && (rc2 = enqueue(p + 1))) return rc2;
+    }
+    *steps = p + 1;
+    const double* slot = pin + 16 * (p & 1);
+    for (int q = 0; q < bb; ++q) ritz[q] = slot[1 + q];
+    // the next block (a larger block starts from it) and the top Ritz vector
+    if (hipMemcpyAsync(blk, ws.pxd[(p & 1) ^ 1], (size_t)n * BL * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RPCA_EHIP;
+    double* vt = pin + o_w16;  // n doubles fit in the n x 16 floats
+    if (extra && hipMemcpyAsync(vt, ws.pvtop, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RPCA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < bb; ++c) Xbh[(size_t)i * bb + c] = blk[(size_t)i * BL + c];
+    if (extra) extra->v.assign(vt, vt + n);
+    return RPCA_OK;
+  };
   for (;;) {
     proj_v(Xb, b);
     orth_host(Xb, b);
@@ -1452,7 +1578,13 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
     // to about 1e-7 relative, so their convergence test is 1e-6 instead of 1e-8
     const bool fused = ws.gpart != nullptr && b <= 16;
     const double conv_rel = fused ? 1e-6 : 1e-8;
-    for (int it = 0; it < max_it; ++it) {
+    if (fused && b <= BL && dev_ok) {
+      int steps = 0;
+      const int prc = power_dev(Xb, b, &steps);
+      if (prc) return prc;
+      it_total += steps;
+    }
+    for (int it = 0; it < max_it && !(fused && b <= BL && dev_ok); ++it) {
       ++it_total;
       if (fused) {
         // G^T G X in one pass over X: X as FP32 n x 16 (columns past b zero)

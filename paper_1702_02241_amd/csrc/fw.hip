@@ -30,6 +30,7 @@
 #include "rpca.h"
 #include "rpca_fw.h"
 #include "rpca_internal.h"
+#include "ritz_kernel.h"
 
 namespace {
 
@@ -353,503 +354,8 @@ __global__ __launch_bounds__(FIN_TH) void k_fw_bilinear_finish(const double* __r
   block_sums<2, FIN_TH>(s, res + 2);
 }
 
-// Deterministic start entries of the power-iteration block (SplitMix64 hash of
-// the index, centred; Steele, Lea & Flood 2014).
-__host__ __device__ inline double start_entry(uint64_t j) {
-  uint64_t z = j + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
-}
-
-// ---- the power step's dense b x b work, on the device (one workgroup) ----
-//
-// After Z = G^T G X for the orthonormal block X (n x BLK, first b columns):
-//   Rayleigh-Ritz: H = X^T Z, its eigenpairs (theta_p, w_p) by cyclic Jacobi
-//     (parallel order: four disjoint rotations per round, one element of H and
-//     of the eigenvector matrix per lane of one wave), sorted descending;
-//   stop test: || Z w_0 - theta_0 X w_0 || <= ptol theta_0 (or the last step, or
-//     theta_0 = 0); v = X w_0 and the coefficients w_0 (y = G v = (G X) w_0);
-//   next block: orth(Z W) by Cholesky QR, the Gram of Z W taken as
-//     W^T (Z^T Z) W.  One pass when Gershgorin puts the column-scaled Gram in
-//     [0.5, 1.5] (Cholesky QR's loss of orthogonality grows with the square of
-//     that condition number, so it stays at rounding level; near convergence
-//     the columns of Z W are nearly orthogonal), else a second pass on the
-//     result.  A Cholesky pivot that keeps less than 1e-12 of its diagonal
-//     sends the block through modified Gram-Schmidt instead (twice per column,
-//     a vanishing column replaced by hashed entries once, then zero).
-// Rotating the block by W keeps the next H nearly diagonal, so its Jacobi
-// settles in a sweep.  Every sum has a fixed order.
-constexpr int RT = 256;  // threads of k_fw_ritz
-
-__device__ __forceinline__ double block_sum1(double v, double* red) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < RT / 64; ++i) t += red[i];
-  __syncthreads();
-  return t;
-}
-
-// Row j of a row-major n x BLK FP64 matrix (64-byte aligned rows) in four
-// 16-byte loads, all issued before any use.
-__device__ __forceinline__ void load_row(const double* __restrict__ A, int64_t j, double (&x)[BLK]) {
-  const double2* p = reinterpret_cast<const double2*>(A + j * BLK);
-#pragma unroll
-  for (int k = 0; k < BLK / 2; ++k) {
-    const double2 v = p[k];
-    x[2 * k] = v.x;
-    x[2 * k + 1] = v.y;
-  }
-}
-
-// 1 / sqrt(x) for finite x > 0: an FP32 estimate of the scaled mantissa and
-// two Newton steps in FP64.
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  int e;
-  const double m = frexp(x, &e);  // x = m 2^e, m in [0.5, 1)
-  const int e2 = e & ~1;          // even, so that 2^(-e2/2) is exact
-  const double mm = ldexp(m, e - e2);
-  double r = (double)__frsqrt_rn((float)mm);
-  r = r * fma(-0.5 * mm, r * r, 1.5);
-  r = r * fma(-0.5 * mm, r * r, 1.5);
-  return ldexp(r, -(e2 / 2));
-}
-
-__device__ __forceinline__ float wave_sumf(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Jacobi rotation (FP32) that zeroes the off-diagonal of [[app, apq], [apq, aqq]]:
-// c and t (s = t c) with J[p][p] = J[q][q] = c, J[q][p] = -s, J[p][q] = s, from
-// the hardware reciprocal, square-root and reciprocal-square-root estimates.
-// Lanes given the same entries return the same rotation.
-__device__ __forceinline__ void jacobi_ct(float app, float aqq, float apq, float& c, float& t) {
-  c = 1.f;
-  t = 0.f;
-  if (apq == 0.f) return;
-  const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq), at = fabsf(tau);
-  const float tt = at > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(at)
-                              : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.f)));
-  t = tau >= 0.f ? tt : -tt;
-  c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-}
-
-// Sums over the rows j < n, in tiles of RT rows staged in LDS (whole-row
-// loads, every load of a tile in flight at once), each output over two row
-// slices summed in order:
-//   out1[a BLK + c] = sum_j A[j][a] B[j][c]   (a, c < b; A may be null: skipped)
-//   out2[a BLK + c] = sum_j B[j][a] B[j][c]   (a <= c < b, mirrored)
-// Entries past b are zero; columns past b of A and B are loaded but not used.
-__device__ __forceinline__ void row_grams(const double* __restrict__ A, const double* __restrict__ B, int64_t n, int b,
-                          double* out1, double* out2, double* red, double* sA, double* sB,
-                          const double (&a0)[BLK], const double (&b0)[BLK]) {
-  constexpr int NOP = 128, SL = RT / NOP;
-  const int tid = threadIdx.x, o = tid % NOP, sl = tid / NOP;
-  if (tid < BLK * BLK) {
-    if (A) out1[tid] = 0.0;
-    out2[tid] = 0.0;
-  }
-  int a = 0, c = 0;
-  bool live;
-  if (o < BLK * BLK) {
-    a = o >> 3;
-    c = o & 7;
-    live = A != nullptr;
-  } else {
-    int r = o - BLK * BLK;  // -> (a, c), a <= c, row by row of the upper triangle
-    live = r < BLK * (BLK + 1) / 2;
-    while (live && r >= BLK - a) {
-      r -= BLK - a;
-      ++a;
-    }
-    c = a + r;
-  }
-  live = live && a < b && c < b;
-  const double* sP = o < BLK * BLK ? sA : sB;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int64_t r0 = 0; r0 < n; r0 += RT) {
-    __syncthreads();  // the previous tile is consumed
-    const int64_t j = r0 + tid;
-    if (j < n) {
-      double xa[BLK], xb[BLK];
-      if (r0 == 0) {  // the caller's registers hold row tid
-#pragma unroll
-        for (int k = 0; k < BLK; ++k) {
-          xa[k] = a0[k];
-          xb[k] = b0[k];
-        }
-      } else {
-        if (A) load_row(A, j, xa);
-        load_row(B, j, xb);
-      }
-#pragma unroll
-      for (int k = 0; k < BLK; ++k) {
-        if (A) sA[tid * BLK + k] = k < b ? xa[k] : 0.0;
-        sB[tid * BLK + k] = k < b ? xb[k] : 0.0;
-      }
-    }
-    __syncthreads();
-    const int rows = (int)(n - r0 < RT ? n - r0 : RT);
-    if (live) {
-      int r = sl;
-      for (; r + 3 * SL < rows; r += 4 * SL) {
-        s0 = fma(sP[r * BLK + a], sB[r * BLK + c], s0);
-        s1 = fma(sP[(r + SL) * BLK + a], sB[(r + SL) * BLK + c], s1);
-        s2 = fma(sP[(r + 2 * SL) * BLK + a], sB[(r + 2 * SL) * BLK + c], s2);
-        s3 = fma(sP[(r + 3 * SL) * BLK + a], sB[(r + 3 * SL) * BLK + c], s3);
-      }
-      for (; r < rows; r += SL) s0 = fma(sP[r * BLK + a], sB[r * BLK + c], s0);
-    }
-  }
-  red[sl * NOP + o] = (s0 + s1) + (s2 + s3);
-  __syncthreads();
-  if (tid < NOP && live) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < SL; ++q) t += red[q * NOP + tid];
-    if (o < BLK * BLK) out1[o] = t;
-    else out2[a * BLK + c] = out2[c * BLK + a] = t;
-  }
-  __syncthreads();
-}
-
-// Partner of index i in round r of the round-robin pairing of eight indices:
-// 7 meets r, the others meet (2r - i) mod 7.
-__device__ __forceinline__ int jac_partner(int i, int r) {
-  if (i == 7) return r;
-  if (i == r) return 7;
-  return (2 * r - i + 14) % 7;
-}
-
-// Upper Cholesky factor R (C = R^T R) of the symmetric b x b matrix C, one wave,
-// lane i BLK + j holding C[i][j] (right-looking: after step q the lanes past q
-// hold the Schur complement).  Returns R[i][j] for this lane (zero below the
-// diagonal and past b) and 1 / R[j][j] in rinv_j; ok (the same on every lane)
-// is false on a pivot that keeps less than 1e-12 of its diagonal (six digits of
-// the column) or is not finite.
-__device__ double chol_wave(double cij, int i, int j, int b, double& rinv_j, bool& ok) {
-  double a = cij, r = 0.0;
-  rinv_j = 0.0;
-  ok = true;
-  for (int q = 0; q < b; ++q) {
-    const double d = __shfl(a, q * BLK + q, 64), cqq = __shfl(cij, q * BLK + q, 64);
-    const double aqj = __shfl(a, q * BLK + j, 64), aqi = __shfl(a, q * BLK + i, 64);
-    if (!(cqq > 0.0) || !(d > 1e-12 * cqq) || !isfinite(d)) {
-      ok = false;
-      return 0.0;
-    }
-    const double inv = rsqrt_f64(d);
-    const double rqj = aqj * inv, rqi = aqi * inv;
-    if (i == q && j >= q && j < b) r = rqj;
-    if (j == q) rinv_j = inv;
-    if (i > q && j > q) a = fma(-rqi, rqj, a);
-  }
-  return r;
-}
-
-// x <- x R^{-1} for one row (forward substitution over the b columns).
-__device__ __forceinline__ void solve_row(double (&x)[BLK], const double* R, const double* rinv, int b) {
-#pragma unroll
-  for (int k = 0; k < BLK; ++k) {
-    if (k < b) {
-      double t = x[k];
-#pragma unroll
-      for (int p = 0; p < k; ++p) t = fma(-x[p], R[p * BLK + k], t);
-      x[k] = t * rinv[k];
-    } else {
-      x[k] = 0.0;
-    }
-  }
-}
-
-__device__ __forceinline__ void store_block_row(int64_t j, const double (&x)[BLK], double* __restrict__ Xn,
-                                                float* __restrict__ Xbn, float* __restrict__ Wfn) {
-  double2* p = reinterpret_cast<double2*>(Xn + j * BLK);
-#pragma unroll
-  for (int k = 0; k < BLK / 2; ++k) p[k] = double2{x[2 * k], x[2 * k + 1]};
-  f4* q = reinterpret_cast<f4*>(Xbn + j * BLK);
-  q[0] = f4{(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
-  q[1] = f4{(float)x[4], (float)x[5], (float)x[6], (float)x[7]};
-  if (Wfn) {
-    f4* w = reinterpret_cast<f4*>(Wfn + j * 16);
-    w[0] = q[0];
-    w[1] = q[1];
-    w[2] = f4{0.f, 0.f, 0.f, 0.f};
-    w[3] = f4{0.f, 0.f, 0.f, 0.f};
-  }
-}
-
-// skip (null or res[0] itself): a step queued ahead of the host's reading of the
-// previous step's stop flag does nothing once that flag is set.
-__global__ __launch_bounds__(RT) void k_fw_ritz(const double* __restrict__ X, const double* __restrict__ Z, int64_t n,
-                                                int b, double ptol, int last, uint64_t salt, double* __restrict__ Xn,
-                                                float* __restrict__ Xbn, float* __restrict__ Wfn, float* __restrict__ v,
-                                                float* __restrict__ cw, double* res, const double* skip) {
-  if (skip && *skip != 0.0) return;  // every thread reads it before thread 0 rewrites res[0]
-  __shared__ double red[RT];
-  __shared__ double sA[RT * BLK], sB[RT * BLK];
-  __shared__ double sH[BLK * BLK], sC0[BLK * BLK], sW[BLK * BLK], sT[BLK * BLK], sR[BLK * BLK], sRi[BLK], sth[BLK];
-  __shared__ int sok, ssingle;
-  const int tid = threadIdx.x;
-
-  // 1. H = X^T Z and Z^T Z (row tid of each kept in registers for step 3)
-  double x0[BLK], z0[BLK];
-  if (tid < n) {
-    load_row(Z, tid, z0);
-    load_row(X, tid, x0);
-  }
-  row_grams(X, Z, n, b, sH, sC0, red, sA, sB, x0, z0);
-
-  // 2. eigenpairs of H (one wave): cyclic Jacobi in FP32 on H scaled into FP32
-  //    range (an approximate eigenbasis W: it only rotates the next block), then
-  //    the top pair in FP64 (Rayleigh quotient, one first-order correction of
-  //    w_0 against the other Ritz vectors, normalisation, Rayleigh quotient)
-  double hsym = 0.0;
-  int hexp = 0;
-  if (tid < 64) {
-    const int i = tid >> 3, j = tid & 7;
-    hsym = (i < b && j < b) ? 0.5 * (sH[i * BLK + j] + sH[j * BLK + i]) : 0.0;
-    double mx = fabs(hsym);
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    hexp = (mx > 0.0 && isfinite(mx)) ? ilogb(mx) : 0;
-    float h = (float)ldexp(hsym, -hexp);
-    float w = i == j ? 1.f : 0.f;
-    // until the off-diagonal norm is below 1e-6 of the norm (about FP32 rounding)
-    for (int sweep = 0; sweep < 16; ++sweep) {
-      const float off = wave_sumf(i != j ? h * h : 0.f), dia = wave_sumf(i == j ? h * h : 0.f);
-      if (!(off > 1e-12f * dia)) break;
-      for (int r = 0; r < BLK - 1; ++r) {
-        // this lane's two rotations (the pairs holding its row and column
-        // indices), every exchange of the round issued at once
-        const int pi = jac_partner(i, r), pj = jac_partner(j, r);
-        const int ip = i < pi ? i : pi, iq = i < pi ? pi : i, jp = j < pj ? j : pj, jq = j < pj ? pj : j;
-        const float aipp = __shfl(h, ip * BLK + ip, 64), aiqq = __shfl(h, iq * BLK + iq, 64);
-        const float aipq = __shfl(h, ip * BLK + iq, 64);
-        const float ajpp = __shfl(h, jp * BLK + jp, 64), ajqq = __shfl(h, jq * BLK + jq, 64);
-        const float ajpq = __shfl(h, jp * BLK + jq, 64);
-        const float h_ipj = __shfl(h, i * BLK + pj, 64), h_pij = __shfl(h, pi * BLK + j, 64);
-        const float h_pipj = __shfl(h, pi * BLK + pj, 64), w_ipj = __shfl(w, i * BLK + pj, 64);
-        float ci, ti, cj, tj;
-        jacobi_ct(aipp, aiqq, aipq, ci, ti);
-        jacobi_ct(ajpp, ajqq, ajpq, cj, tj);
-        const float si = (i == ip ? -ti : ti) * ci, sj = (j == jp ? -tj : tj) * cj;
-        h = ci * (cj * h + sj * h_ipj) + si * (cj * h_pij + sj * h_pipj);
-        w = w * cj + w_ipj * sj;
-      }
-    }
-    sT[tid] = (double)w;
-    if (i == j) sth[i] = ldexp((double)h, hexp);
-  }
-  __syncthreads();
-  if (tid < 64) {
-    const int i = tid >> 3, j = tid & 7;
-    // descending order of the b live eigenvalues (ties by index): rank of index j
-    const double lj = sth[j];
-    int rank = 0;
-#pragma unroll
-    for (int q = 0; q < BLK; ++q) {
-      const double lq = sth[q];
-      rank += (q < b && (lq > lj || (lq == lj && q < j))) ? 1 : 0;
-    }
-    int perm_i = 0;  // index whose rank is i (column i of the sorted W)
-#pragma unroll
-    for (int q = 0; q < BLK; ++q) perm_i = __shfl(rank, q, 64) == i && q < b ? q : perm_i;
-    const int src = __shfl(perm_i, j * BLK, 64);  // index of rank j, from a lane with row j
-    double wij = (i < b && j < b) ? sT[i * BLK + src] : 0.0;  // W[i][j], sorted
-    const double thj = j < b ? sth[src] : 0.0;                // theta_j (FP32 accuracy)
-    // FP64: u = H w_0 (lane (i, .) gets u_i), m_j = w_j^T u, n0 = w_0^T w_0
-    double u = hsym * __shfl(wij, j * BLK, 64);  // H[i][j] w_0[j]
-    u += __shfl_xor(u, 1, 64);
-    u += __shfl_xor(u, 2, 64);
-    u += __shfl_xor(u, 4, 64);
-    double m = wij * u;
-    m += __shfl_xor(m, 8, 64);
-    m += __shfl_xor(m, 16, 64);
-    m += __shfl_xor(m, 32, 64);
-    const double w0i = __shfl(wij, i * BLK, 64);
-    double n0 = (j == 0) ? w0i * w0i : 0.0;
-    n0 = wave_sum(n0);
-    const double th0r = __shfl(m, 0, 64) / n0;  // Rayleigh quotient of w_0
-    // w_0 += sum_j m_j / (theta_0 - theta_j) w_j over the well-separated j
-    const double gap = th0r - thj;
-    double coef = 0.0;
-    if (j >= 1 && j < b && fabs(m) <= 0.1 * fabs(gap) * sqrt(n0)) coef = m / gap;
-    double add = coef * wij;
-    add += __shfl_xor(add, 1, 64);
-    add += __shfl_xor(add, 2, 64);
-    add += __shfl_xor(add, 4, 64);
-    double w0n = i < b ? w0i + add : 0.0;  // lanes of row i: the corrected w_0[i]
-    double nn = (j == 0) ? w0n * w0n : 0.0;
-    nn = wave_sum(nn);
-    w0n = nn > 0.0 ? w0n * rsqrt_f64(nn) : w0i;
-    // theta_0 = w_0^T H w_0 with the corrected, unit w_0
-    double u2 = hsym * __shfl(w0n, j * BLK, 64);
-    u2 += __shfl_xor(u2, 1, 64);
-    u2 += __shfl_xor(u2, 2, 64);
-    u2 += __shfl_xor(u2, 4, 64);
-    double th0 = (j == 0) ? w0n * u2 : 0.0;
-    th0 = wave_sum(th0);
-    if (j == 0) wij = w0n;
-    sW[tid] = wij;
-    if (i == 0) sR[j] = j == 0 ? th0 : thj;  // sorted eigenvalues, staged
-  }
-  __syncthreads();
-  if (tid < 64) {  // sT = (Z^T Z) W
-    const int i = tid >> 3, j = tid & 7;
-    double t = 0.0;
-#pragma unroll
-    for (int l = 0; l < BLK; ++l) t = fma(sC0[i * BLK + l], sW[l * BLK + j], t);
-    sT[tid] = t;
-    if (i == 0) sth[j] = sR[j];
-  }
-  __syncthreads();
-  if (tid < 64) {  // the Gram of Z W: W^T (Z^T Z) W (upper triangle, mirrored)
-    const int i = tid >> 3, j = tid & 7;
-    const int ii = i < j ? i : j, jj = i < j ? j : i;
-    double t = 0.0;
-#pragma unroll
-    for (int k = 0; k < BLK; ++k) t = fma(sW[k * BLK + ii], sT[k * BLK + jj], t);
-    // Gershgorin on the column-scaled Gram: the largest off-diagonal row sum
-    const double tii = __shfl(t, i * BLK + i, 64), tjj = __shfl(t, j * BLK + j, 64);
-    double g = 0.0;
-    if (i != j && i < b && j < b)
-      g = (tii > 0.0 && tjj > 0.0 && isfinite(tii) && isfinite(tjj)) ? fabs(t) * rsqrt_f64(tii) * rsqrt_f64(tjj)
-                                                                      : 2.0;
-    g += __shfl_xor(g, 1, 64);
-    g += __shfl_xor(g, 2, 64);
-    g += __shfl_xor(g, 4, 64);
-    g = fmax(g, __shfl_xor(g, 8, 64));
-    g = fmax(g, __shfl_xor(g, 16, 64));
-    g = fmax(g, __shfl_xor(g, 32, 64));
-    bool ok;
-    double rinv;
-    const double r = chol_wave(t, i, j, b, rinv, ok);
-    sR[tid] = r;
-    if (i == 0) sRi[j] = rinv;
-    if (tid == 0) {
-      sok = ok ? 1 : 0;
-      ssingle = g <= 0.5 ? 1 : 0;
-    }
-  }
-  __syncthreads();
-  const bool ok1 = sok != 0, single = ok1 && ssingle != 0;
-  const double th0 = fmax(sth[0], 0.0);
-
-  // 3. rows: Z W, the residual, v = X w_0; the next block after one
-  //    factorisation (final when single)
-  double rr = 0.0;
-  for (int64_t j = tid; j < n; j += RT) {
-    double zr[BLK], xr[BLK], y[BLK];
-    if (j == tid) {
-#pragma unroll
-      for (int k = 0; k < BLK; ++k) {
-        zr[k] = z0[k];
-        xr[k] = x0[k];
-      }
-    } else {
-      load_row(Z, j, zr);
-      load_row(X, j, xr);
-    }
-    double xw = 0.0;
-#pragma unroll
-    for (int k = 0; k < BLK; ++k) y[k] = 0.0;
-#pragma unroll
-    for (int a = 0; a < BLK; ++a) {
-      if (a < b) {
-        xw = fma(xr[a], sW[a * BLK], xw);
-#pragma unroll
-        for (int k = 0; k < BLK; ++k) y[k] = fma(zr[a], sW[a * BLK + k], y[k]);
-      }
-    }
-    const double e = y[0] - th0 * xw;
-    rr = fma(e, e, rr);
-    v[j] = (float)xw;
-    if (ok1) solve_row(y, sR, sRi, b);
-    if (single) {
-      store_block_row(j, y, Xn, Xbn, Wfn);
-    } else {
-      double2* p = reinterpret_cast<double2*>(Xn + j * BLK);
-#pragma unroll
-      for (int k = 0; k < BLK / 2; ++k) p[k] = double2{y[2 * k], y[2 * k + 1]};
-    }
-  }
-  rr = block_sum1(rr, red);
-  const double resid = th0 > 0.0 ? sqrt(rr) / th0 : 0.0;
-  if (tid == 0) {
-    const bool done = resid <= ptol || last != 0 || th0 == 0.0;
-    res[0] = done ? 1.0 : 0.0;
-    res[1] = th0;
-    res[2] = resid;
-  }
-  if (tid < BLK) cw[tid] = (float)sW[tid * BLK];
-  if (single) return;
-  __syncthreads();  // Xn complete
-
-  // 4. second Cholesky QR pass, or Gram-Schmidt
-  bool ok2 = false;
-  if (ok1) {
-    double y0[BLK];
-    if (tid < n) load_row(Xn, tid, y0);
-    row_grams(nullptr, Xn, n, b, nullptr, sH, red, sA, sB, y0, y0);
-    if (tid < 64) {
-      bool ok;
-      double rinv;
-      const double r = chol_wave(sH[tid], tid >> 3, tid & 7, b, rinv, ok);
-      sR[tid] = r;
-      if (tid < BLK) sRi[tid] = rinv;
-      if (tid == 0) sok = ok ? 1 : 0;
-    }
-    __syncthreads();
-    ok2 = sok != 0;
-  }
-  if (ok2) {
-    for (int64_t j = tid; j < n; j += RT) {
-      double x[BLK];
-      load_row(Xn, j, x);
-      solve_row(x, sR, sRi, b);
-      store_block_row(j, x, Xn, Xbn, Wfn);
-    }
-    return;
-  }
-  // modified Gram-Schmidt on the columns of Xn, twice per column
-  for (int q = 0; q < b; ++q) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      double before = 0.0;
-      for (int64_t j = tid; j < n; j += RT) before = fma(Xn[j * BLK + q], Xn[j * BLK + q], before);
-      before = block_sum1(before, red);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int p = 0; p < q; ++p) {
-          double d = 0.0;
-          for (int64_t j = tid; j < n; j += RT) d = fma(Xn[j * BLK + p], Xn[j * BLK + q], d);
-          d = block_sum1(d, red);
-          for (int64_t j = tid; j < n; j += RT) Xn[j * BLK + q] -= d * Xn[j * BLK + p];
-          __syncthreads();
-        }
-      double nn = 0.0;
-      for (int64_t j = tid; j < n; j += RT) nn = fma(Xn[j * BLK + q], Xn[j * BLK + q], nn);
-      nn = block_sum1(nn, red);
-      if (nn > 1e-20 * before && nn > 0.0) {
-        const double inv = 1.0 / sqrt(nn);
-        for (int64_t j = tid; j < n; j += RT) Xn[j * BLK + q] *= inv;
-        __syncthreads();
-        break;
-      }
-      for (int64_t j = tid; j < n; j += RT)
-        Xn[j * BLK + q] = attempt == 0 ? start_entry(salt + (uint64_t)(j * BLK + q)) : 0.0;
-      __syncthreads();
-    }
-  }
-  for (int64_t j = tid; j < n; j += RT) {
-    double x[BLK];
-    load_row(Xn, j, x);
-    store_block_row(j, x, Xn, Xbn, Wfn);
-  }
-}
+using rpca_ritz::start_entry;
+static_assert(rpca_ritz::BLK == BLK, "one block width");
 
 }  // namespace
 
@@ -1060,7 +566,7 @@ hipError_t fw_left(rpca_fw* h, const float* Xb, hipStream_t s) {
 }
 
 // Linear minimisation: top singular triplet of G by block power iteration with
-// Rayleigh-Ritz, every step on the device (k_fw_ritz); the host reads back the
+// Rayleigh-Ritz, every step on the device (k_block_ritz); the host reads back the
 // stop flag, theta_0 and the residual (24 bytes) per step.  With the fused
 // pass (and kernel timing off) the next step is queued before the host reads
 // the current one's flag, its kernels doing nothing once the flag is set, so
@@ -1108,9 +614,23 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
                          (const double*)h->part, h->rc_right, n * BLK, h->Z);
       FWCHK(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_fw_ritz, dim3(1), dim3(RT), 0, s, (const double*)xd_at(h, cur), (const double*)h->Z, n, b,
-                       ptol, p + 1 == POWER_MAX ? 1 : 0, 0x51ull * (uint64_t)(p + 1), xd_at(h, nxt), xb_at(h, nxt),
-                       wf_at(h, nxt), h->v, h->cw, h->res + 8, skip);
+    rpca_ritz::RitzArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.X = xd_at(h, cur);
+    ra.Z = h->Z;
+    ra.n = n;
+    ra.b = b;
+    ra.salt = 0x51ull * (uint64_t)(p + 1);
+    ra.Xn = xd_at(h, nxt);
+    ra.Xbn = xb_at(h, nxt);
+    ra.Wfn = wf_at(h, nxt);
+    ra.res = h->res + 8;
+    ra.skip = skip;
+    ra.ptol = ptol;
+    ra.last = p + 1 == POWER_MAX ? 1 : 0;
+    ra.v32 = h->v;
+    ra.cw = h->cw;
+    hipLaunchKernelGGL(rpca_ritz::k_block_ritz<rpca_ritz::RITZ_FW>, dim3(1), dim3(rpca_ritz::RT), 0, s, ra);
     FWCHK(hipGetLastError());
     double* slot = h->res_host + 8 + 4 * (p & 1);
     FWCHK(hipMemcpyAsync(slot, h->res + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, s));

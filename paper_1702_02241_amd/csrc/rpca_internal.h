@@ -232,6 +232,7 @@ CtxView ctx_view(rpca_ctx* c);
 // files the pair under class cls.
 hipError_t prof_begin(rpca_ctx* c, hipStream_t s, void** token);
 hipError_t prof_end(rpca_ctx* c, int cls, hipStream_t s, void* token);
+bool prof_enabled(const rpca_ctx* c);  // kernel timing on
 // Optional outputs of the certificate's power iteration: the top Ritz vector v of
 // M^T M (n values, P_V^perp-projected, unit norm) and the k x r map T_U with
 // U1 = U T_U (the left singular vectors of L).
