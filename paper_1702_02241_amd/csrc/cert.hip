@@ -1036,71 +1036,12 @@ int proj_norms_host(const Workspace& ws, int64_t m, int64_t n, int k, int r, dou
   return RPCA_OK;
 }
 
-// T (l x l, row-major) holds a Gram matrix G = Y^T Y; replace it by L^{-T}, the
-// inverse transpose of its Cholesky factor (G = L L^T, columns in order; row c of
-// T is column c of L^{-1}).  A column whose squared norm outside the span of the
-// previous ones is at most 1e-13 of the largest squared column norm is dropped:
-// its row and column of L, and its row of T, are zero.  One workgroup: the
-// factor column by column (left-looking, the rows of a column in parallel), then
-// the columns of L^{-1} one per thread by forward substitution.
-__global__ __launch_bounds__(THREADS) void k_chol_tinv(double* T, int l) {
-  __shared__ double sL[LMAX * LMAX], sX[LMAX * LMAX];
-  __shared__ int keep[LMAX];
-  __shared__ double smaxd;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < l * l; e += THREADS) sL[e] = T[e];
-  __syncthreads();
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < l; ++j) mx = fmax(mx, sL[j * l + j]);
-    smaxd = mx;
-  }
-  __syncthreads();
-  for (int j = 0; j < l; ++j) {
-    if (tid == 0) {
-      double d = sL[j * l + j];
-      for (int t = 0; t < j; ++t) d -= sL[j * l + t] * sL[j * l + t];
-      keep[j] = d > 1e-13 * smaxd ? 1 : 0;
-      sL[j * l + j] = keep[j] ? sqrt(d) : 0.0;
-    }
-    __syncthreads();
-    const double ljj = sL[j * l + j];
-    for (int i = j + 1 + tid; i < l; i += THREADS) {
-      double v = 0.0;
-      if (keep[j]) {
-        v = sL[i * l + j];
-        for (int t = 0; t < j; ++t) v -= sL[i * l + t] * sL[j * l + t];
-        v /= ljj;
-      }
-      sL[i * l + j] = v;
-    }
-    __syncthreads();
-  }
-  if (tid < l) {
-    const int c = tid;
-    double* x = sX + c * LMAX;
-    for (int i = 0; i < l; ++i) x[i] = 0.0;
-    if (keep[c]) {
-      x[c] = 1.0 / sL[c * l + c];
-      for (int i = c + 1; i < l; ++i) {
-        if (!keep[i]) continue;
-        double v = 0.0;
-        for (int t = c; t < i; ++t) v -= sL[i * l + t] * x[t];
-        x[i] = v / sL[i * l + i];
-      }
-    }
-    for (int i = 0; i < l; ++i) T[c * l + i] = x[i];
-  }
-}
-
 // Orthonormalise the columns of an FP64 device matrix (rows x l, ld) in place:
-// Cholesky QR, twice, on the device (no host round trip).  With Y^T Y = L L^T
-// (columns in order), Q = Y L^{-T}; a column whose part outside the span of the
-// previous ones has squared norm at most 1e-13 of the largest squared column
-// norm is dropped (its Q column is zero).
+// Cholesky QR, twice.  With Y^T Y = L L^T (columns in order), Q = Y L^{-T}; a
+// column whose part outside the span of the previous ones has squared norm at
+// most 1e-13 of the largest squared column norm is dropped (its Q column is zero).
 int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows, int l, int ld,
                        hipStream_t s) {
-  if (l < 1 || l > LMAX) return RPCA_EINVAL;
   for (int pass = 0; pass < 2; ++pass) {
     GramArgs ga;
     memset(&ga, 0, sizeof(ga));
@@ -1109,19 +1050,48 @@ int orthonormalize_dev(const Workspace& ws, double* Y, double* tmp, int64_t rows
     ga.mode = 1;
     ga.D = Y;
     ga.ldd = ld;
-    ga.part = ws.gram;
-    const int blocks = ws.gram_blocks;
-    hipLaunchKernelGGL(k_gram, dim3(blocks), dim3(THREADS), 0, s, ga);
-    if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
-    hipLaunchKernelGGL(k_gram_sum, dim3(l * l), dim3(THREADS), 0, s, (const double*)ws.gram, blocks, l * l, ws.T);
-    if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
-    hipLaunchKernelGGL(k_chol_tinv, dim3(1), dim3(THREADS), 0, s, ws.T, l);
-    if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
+    std::vector<double> G;
+    int rc = gram_host(ws, ga, G, s);
+    if (rc) return rc;
+    std::vector<double> Lc((size_t)l * l, 0.0), T((size_t)l * l, 0.0), x(l);
+    std::vector<char> keep(l, 0);
+    double maxd = 0.0;
+    for (int j = 0; j < l; ++j) maxd = std::max(maxd, G[(size_t)j * l + j]);
+    for (int j = 0; j < l; ++j) {
+      double d = G[(size_t)j * l + j];
+      for (int t = 0; t < j; ++t) d -= Lc[(size_t)j * l + t] * Lc[(size_t)j * l + t];
+      if (!(d > 1e-13 * maxd)) continue;  // dependent: column j of L stays zero
+      keep[j] = 1;
+      const double ljj = sqrt(d);
+      Lc[(size_t)j * l + j] = ljj;
+      for (int i = j + 1; i < l; ++i) {
+        double v = G[(size_t)i * l + j];
+        for (int t = 0; t < j; ++t) v -= Lc[(size_t)i * l + t] * Lc[(size_t)j * l + t];
+        Lc[(size_t)i * l + j] = v / ljj;
+      }
+    }
+    // T = L^{-T}: row c of T is column c of L^{-1} (forward substitution over kept rows)
+    for (int c = 0; c < l; ++c) {
+      if (!keep[c]) continue;
+      std::fill(x.begin(), x.end(), 0.0);
+      x[c] = 1.0 / Lc[(size_t)c * l + c];
+      for (int i = c + 1; i < l; ++i) {
+        if (!keep[i]) continue;
+        double v = 0.0;
+        for (int t = c; t < i; ++t) v -= Lc[(size_t)i * l + t] * x[t];
+        x[i] = v / Lc[(size_t)i * l + i];
+      }
+      for (int i = 0; i < l; ++i) T[(size_t)c * l + i] = x[i];
+    }
+    memcpy(ws.pin, T.data(), T.size() * 8);
+    if (hipMemcpyAsync(ws.T, ws.pin, T.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     const int64_t outs = rows * l;
     hipLaunchKernelGGL(k_row_transform, dim3((unsigned)((outs + THREADS - 1) / THREADS)), dim3(THREADS), 0, s,
                        (const double*)Y, ld, l, (const double*)ws.T, l, rows, tmp, (float*)nullptr, ld);
     if (hipGetLastError() != hipSuccess) return RPCA_EHIP;
     if (hipMemcpyAsync(Y, tmp, (size_t)rows * ld * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return RPCA_EHIP;
+    // the pinned source of the T upload is rewritten by the next pass
+    if (hipStreamSynchronize(s) != hipSuccess) return RPCA_EHIP;
   }
   return RPCA_OK;
 }
@@ -1977,7 +1947,7 @@ int prox_step(rpca_ctx* c, ProxState& P, const float* A, const float* B, float* 
     memcpy(pinB, Om.data(), Om.size() * 8);
     if (hipMemcpyAsync(ws.Wd, pinB, Om.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) return RPCA_EHIP;
     if (left_product(cv, ws, P.X, SRC_PROX, A, B, ws.Wd, l, ws.Yd, l, l, s) != hipSuccess) return RPCA_EHIP;
-    if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;
+    if ((rc = orthonormalize_dev(ws, ws.Yd, ws.Y2, m, l, l, s))) return rc;  // (syncs: Om may die)
     for (int q = 0; q < P.power; ++q) {
       if (right_product(cv, ws, P.X, SRC_PROX, A, B, ws.Yd, l, ws.Zd, l, l, s) != hipSuccess) return RPCA_EHIP;
       if ((rc = orthonormalize_dev(ws, ws.Zd, ws.Wd, n, l, l, s))) return rc;
