@@ -1448,7 +1448,8 @@ int certificate_impl(rpca_ctx* c, const float* X, const float* U, const float* V
   constexpr int BL = rpca_ritz::BLK;
   const size_t o_blk = 32, o_w16 = o_blk + (size_t)n * BL, o_v1 = o_w16 + (size_t)n * 8,
                o_bn = o_v1 + (size_t)n * r, o_vb = o_bn + (size_t)n * r, o_end = o_vb + (size_t)r * r;
-  const bool dev_ok = ws.pres != nullptr && r <= rpca_ritz::RMAX && o_end <= PIN_SMALL + (size_t)n * 64;
+  const bool dev_ok = ws.pres != nullptr && r <= rpca_ritz::RMAX && n <= rpca_ritz::RT &&
+                      o_end <= PIN_SMALL + (size_t)n * 64;
   auto power_dev = [&](std::vector<double>& Xbh, int bb, int* steps) -> int {
     struct Events {
       hipEvent_t e[2] = {nullptr, nullptr};

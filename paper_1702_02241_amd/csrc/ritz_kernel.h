@@ -62,7 +62,7 @@ struct RitzArgs {
   int last;           // the last allowed step: stop
   float* v32;         // n: X w_0
   float* cw;          // BLK: w_0
-  // certificate: res = [stop, ritz_0 .. ritz_7] (max(theta, 0), zero past b)
+  // certificate (n <= RT): res = [stop, ritz_0 .. ritz_7] (max(theta, 0), zero past b)
   double* Zf;         // n x BLK: the projected Z (written)
   const double* V1;   // n x r
   const double* Bn;   // n x r
@@ -298,39 +298,55 @@ __device__ __forceinline__ void store_block_row(int64_t j, const double (&x)[BLK
 
 // The certificate's projected product into a.Zf (and row tid of it into z0):
 // Zf = S - B_n C_B - V_1 C_V with S = Z / lam_L^2, C_B = B_n^T X and
-// C_V = V_1^T (S - B_n C_B) = V_1^T S - (V_1^T B_n) C_B.  Two passes over the rows
-// in tiles of PTR rows staged in LDS (coalesced loads, all of a tile in flight):
-// the first sums C_B and V_1^T S (two outputs per thread, rows in order), the
-// second forms the rows of Zf (four entries per thread).
-__device__ __forceinline__ void cert_project(const RitzArgs& a, double* stage, double (&z0)[BLK]) {
+// C_V = V_1^T (S - B_n C_B) = V_1^T S - (V_1^T B_n) C_B.  One row per thread
+// (n <= RT): the thread's rows of Z, B_n and V_1 are loaded at once (with X's,
+// already in x0); C_B and V_1^T S are summed over the rows in tiles of PTR rows
+// staged in LDS from those registers (two outputs per thread, rows in order);
+// then each thread forms its own row of Zf.
+__device__ __forceinline__ void cert_project(const RitzArgs& a, double* stage, const double (&x0)[BLK],
+                                             double (&z0)[BLK]) {
   __shared__ double sCB[RMAX * BLK], sCV[RMAX * BLK];
   const int tid = threadIdx.x, b = a.b, r = a.r, rb = r * b;
   const int64_t n = a.n;
+  const bool own = tid < n;
+  double zr[BLK], bn[RMAX], v1[RMAX];
+#pragma unroll
+  for (int t = 0; t < RMAX; ++t) bn[t] = v1[t] = 0.0;
+  if (own) {
+    load_row(a.Z, tid, zr);
+    if (r > 0) {
+      const double* __restrict__ brow = a.Bn + (int64_t)tid * r;
+      const double* __restrict__ vrow = a.V1 + (int64_t)tid * r;
+#pragma unroll
+      for (int t = 0; t < RMAX; ++t) {  // clamped columns: every load issued before any use
+        const int tc = t < r ? t : r - 1;
+        bn[t] = brow[tc];
+        v1[t] = vrow[tc];
+      }
+    }
+  }
   double* sX = stage;
   double* sZ = sX + PTR * BLK;
   double* sBn = sZ + PTR * BLK;
   double* sV = sBn + PTR * RMAX;
-  auto stage_tile = [&](int64_t r0, int rows, bool with_x) {
-    for (int e = tid; e < rows * BLK; e += RT) {
-      const int64_t j = r0 + e / BLK;
-      const int c = e % BLK;
-      const double zv = a.Z[j * BLK + c];
-      sZ[e] = c < b ? zv : 0.0;
-      if (with_x) {
-        const double xv = a.X[j * BLK + c];
-        sX[e] = c < b ? xv : 0.0;
-      }
-    }
-    for (int e = tid; e < rows * r; e += RT) {
-      sBn[e] = a.Bn[r0 * r + e];
-      sV[e] = a.V1[r0 * r + e];
-    }
-  };
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int64_t r0 = 0; r0 < n; r0 += PTR) {
     __syncthreads();  // the previous tile is consumed
     const int rows = (int)(n - r0 < PTR ? n - r0 : PTR);
-    stage_tile(r0, rows, true);
+    const int q = tid - (int)r0;
+    if (own && q >= 0 && q < rows) {
+#pragma unroll
+      for (int c = 0; c < BLK; ++c) {
+        sX[q * BLK + c] = c < b ? x0[c] : 0.0;
+        sZ[q * BLK + c] = c < b ? zr[c] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < RMAX; ++t)
+        if (t < r) {
+          sBn[q * r + t] = bn[t];
+          sV[q * r + t] = v1[t];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -341,15 +357,22 @@ __device__ __forceinline__ void cert_project(const RitzArgs& a, double* stage, d
         const int t = oo / b, c = oo % b;
         const double* L = isB ? sBn : sV;
         const double* Rt = isB ? sX : sZ;
-        double s0 = acc[h][0], s1 = acc[h][1];
-        int q = 0;
-        for (; q + 1 < rows; q += 2) {
-          s0 = fma(L[q * r + t], Rt[q * BLK + c], s0);
-          s1 = fma(L[(q + 1) * r + t], Rt[(q + 1) * BLK + c], s1);
+        // eight rows a step (all sixteen reads in flight), four partial sums
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int qq = 0;
+        for (; qq + 7 < rows; qq += 8) {
+          double lv[8], rv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            lv[u] = L[(qq + u) * r + t];
+            rv[u] = Rt[(qq + u) * BLK + c];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s4[u & 3] = fma(lv[u], rv[u], s4[u & 3]);
         }
-        if (q < rows) s0 = fma(L[q * r + t], Rt[q * BLK + c], s0);
-        acc[h][0] = s0;
-        acc[h][1] = s1;
+        for (; qq < rows; ++qq) s4[qq & 3] = fma(L[qq * r + t], Rt[qq * BLK + c], s4[qq & 3]);
+        acc[h][0] += s4[0] + s4[1];
+        acc[h][1] += s4[2] + s4[3];
       }
     }
   }
@@ -369,23 +392,31 @@ __device__ __forceinline__ void cert_project(const RitzArgs& a, double* stage, d
   }
   __syncthreads();
   if (tid < rb) sCV[tid] = cv;
-  for (int64_t r0 = 0; r0 < n; r0 += PTR) {
-    __syncthreads();  // C_V written; the previous tile is consumed
-    const int rows = (int)(n - r0 < PTR ? n - r0 : PTR);
-    stage_tile(r0, rows, false);
-    __syncthreads();
-    for (int e = tid; e < rows * BLK; e += RT) {
-      const int q = e / BLK, c = e % BLK;
-      double z = 0.0;
-      if (c < b) {
-        z = sZ[e] * a.inv_lam2;
-        for (int t = 0; t < r; ++t) z = fma(-sBn[q * r + t], sCB[t * b + c], fma(-sV[q * r + t], sCV[t * b + c], z));
+  __syncthreads();
+  if (own) {
+    // column chains side by side: per t, the row's 2b coefficients read together
+#pragma unroll
+    for (int c = 0; c < BLK; ++c) z0[c] = c < b ? zr[c] * a.inv_lam2 : 0.0;
+#pragma unroll
+    for (int t = 0; t < RMAX; ++t) {
+      if (t < r) {
+        double cb[BLK], cvv[BLK];
+#pragma unroll
+        for (int c = 0; c < BLK; ++c) {
+          const int cc = c < b ? c : 0;
+          cb[c] = sCB[t * b + cc];
+          cvv[c] = sCV[t * b + cc];
+        }
+#pragma unroll
+        for (int c = 0; c < BLK; ++c)
+          if (c < b) z0[c] = fma(-bn[t], cb[c], fma(-v1[t], cvv[c], z0[c]));
       }
-      a.Zf[(r0 + q) * BLK + c] = z;
     }
+    double2* p = reinterpret_cast<double2*>(a.Zf + (int64_t)tid * BLK);
+#pragma unroll
+    for (int k = 0; k < BLK / 2; ++k) p[k] = double2{z0[2 * k], z0[2 * k + 1]};
   }
   __syncthreads();  // Zf complete
-  if (tid < n) load_row(a.Zf, tid, z0);
 }
 
 // The certificate's stop test (wave 0, lane i BLK + j; sth holds the Ritz
@@ -440,7 +471,7 @@ __global__ __launch_bounds__(RT) void k_block_ritz(RitzArgs a) {
   const double* Z = a.Z;
   if (tid < n) load_row(X, tid, x0);
   if (MODE == RITZ_CERT) {
-    cert_project(a, stage, z0);
+    cert_project(a, stage, x0, z0);
     Z = a.Zf;
   } else if (tid < n) {
     load_row(Z, tid, z0);
