@@ -644,7 +644,8 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
     FWCHK(hipEventSynchronize(h->flag_ev[p & 1]));
     const double* slot = h->res_host + 8 + 4 * (p & 1);
     ++*steps;
-    if (slot[0] != 0.0) {
+    // the kernel sets the flag at the last allowed step; the host stops there too
+    if (slot[0] != 0.0 || p + 1 >= POWER_MAX) {
       const int cur = cur0 ^ (p & 1);
       // y = G v = (G Xb) w_0 for this step's block
       if (h->gpart) FWCHK(fw_left(h, xb_at(h, cur), s));
