@@ -489,8 +489,9 @@ int fw_update(rpca_fw* h, const float* X, float* L, float a, float b, hipStream_
   }));
   hipLaunchKernelGGL(k_sum_parts<3>, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, blocks, h->res + 4);
   FWCHK(hipGetLastError());
+  // read after the next linear minimisation's first wait (which follows this copy
+  // on the stream), so no synchronisation here
   FWCHK(hipMemcpyAsync(h->res_host + 4, h->res + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  FWCHK(hipStreamSynchronize(s));
   return RPCA_OK;
 }
 
@@ -814,15 +815,18 @@ int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t ma
   rpca_fw_info fin;
   memset(&fin, 0, sizeof(fin));
   for (int it = 0;; ++it) {
+    // the update's sums arrive with the minimisation's first wait (a non-finite G
+    // stops the minimisation at its first step)
+    double sigma = 0.0;
+    if ((rc = fw_lmo(h, ptol, &sigma, &fin.power_iters, s))) return rc;
     const double phi = h->res_host[4], gl = h->res_host[5], l2 = h->res_host[6];
     if (!isfinite(phi) || !isfinite(gl) || !isfinite(l2)) {
+      FWCHK(hipStreamSynchronize(s));
       *t_io = t;
       return RPCA_ENONFINITE;
     }
     const double F = phi + lam_l * t;
     const double B = phi / lam_l + t;
-    double sigma = 0.0;
-    if ((rc = fw_lmo(h, ptol, &sigma, &fin.power_iters, s))) return rc;
     const bool step = sigma > lam_l;
     double gap, eta = 0.0;
     if (step) {

@@ -674,7 +674,7 @@ __global__ __launch_bounds__(RT) void k_block_ritz(RitzArgs a) {
   if (MODE == RITZ_FW) {
     const double resid = th0 > 0.0 ? sqrt(rr) / th0 : 0.0;
     if (tid == 0) {
-      const bool done = resid <= a.ptol || a.last != 0 || th0 == 0.0;
+      const bool done = resid <= a.ptol || a.last != 0 || th0 == 0.0 || !isfinite(th0) || !isfinite(resid);
       res[0] = done ? 1.0 : 0.0;
       res[1] = th0;
       res[2] = resid;
