@@ -86,11 +86,14 @@ __device__ __forceinline__ unsigned obs_bits(const uint32_t* mask, int mw, int64
 // phi(L), <G, L>, sum_Omega L^2.  Block b covers rows (b % rb) * TH * VEC ... of
 // column b / rb.
 template <int VEC, bool MASK>
+// a = st[1], b = st[2] from the step state; nothing once st[3] (done) is set.
 __global__ __launch_bounds__(TH) void k_fw_update(float* __restrict__ L, const float* __restrict__ X,
                                                   const uint32_t* __restrict__ mask, int mw, int64_t m,
-                                                  int64_t rb, float a, float b, const float* __restrict__ y,
-                                                  const float* __restrict__ v, float lam_s,
-                                                  float* __restrict__ G, double* __restrict__ part) {
+                                                  int64_t rb, const double* __restrict__ st,
+                                                  const float* __restrict__ y, const float* __restrict__ v,
+                                                  float lam_s, float* __restrict__ G, double* __restrict__ part) {
+  if (st[3] != 0.0) return;
+  const float a = (float)st[1], b = (float)st[2];
   const int64_t blk = blockIdx.x;
   const int64_t j = blk / rb;
   const int64_t i0 = (blk % rb) * (TH * VEC) + (int64_t)threadIdx.x * VEC;
@@ -298,9 +301,15 @@ __global__ __launch_bounds__(TH) void k_fw_combine(const float* __restrict__ Y, 
 // Bilinear pass over a chunk of rows of column j (observed entries only):
 // part[0] = sum_i A_ij u_i, part[1] = sum_i u_i^2, u_i = ws w_i.
 template <int VEC, bool MASK>
-__global__ __launch_bounds__(TH) void k_fw_bilinear(const float* __restrict__ A, const float* __restrict__ w, float ws,
+// u = w / sigma with sigma = sqrt(theta_0) (res[9]); nothing when sigma <= lam_L
+// (no step: the sums are not used).
+__global__ __launch_bounds__(TH) void k_fw_bilinear(const float* __restrict__ A, const float* __restrict__ w,
+                                                    const double* __restrict__ res, double lam_l,
                                                     const uint32_t* __restrict__ mask, int mw, int64_t m, int64_t rc,
                                                     double* __restrict__ part) {
+  const double sigma = sqrt(fmax(res[9], 0.0));
+  if (!(sigma > lam_l)) return;
+  const float ws = (float)(1.0 / sigma);
   const int64_t blk = blockIdx.x;
   const int64_t j = blk / rc;
   const int64_t base = (blk % rc) * (int64_t)(TH * VEC * COL_ITER);
@@ -354,6 +363,58 @@ __global__ __launch_bounds__(FIN_TH) void k_fw_bilinear_finish(const double* __r
   block_sums<2, FIN_TH>(s, res + 2);
 }
 
+// The step of an iteration from its sums (one thread): res[4..6] = phi(L), <G, L>,
+// sum_Omega L^2 (update pass), res[9] = theta_0 (sigma^2), res[2..3] = the
+// bilinear sums; st = [t, a, b, done, F, gap, sigma, eta, step, nonfinite, t of this
+// iteration, eta of the last applied step, phi].  With V = -B u v^T the gap and the
+// exact line search need only these (Alg. 1); done when gap <= tol F or at the
+// last iteration, else st[0..2] take the next t and the update's a, b.
+__global__ void k_fw_step(const double* __restrict__ res, double* __restrict__ st, double lam_l, double tol,
+                          int last) {
+  if (threadIdx.x != 0) return;
+  const double phi = res[4], gl = res[5], l2 = res[6], t = st[0];
+  st[10] = t;
+  st[12] = phi;
+  if (!isfinite(phi) || !isfinite(gl) || !isfinite(l2)) {
+    st[9] = 1.0;
+    st[3] = 1.0;
+    return;
+  }
+  const double F = phi + lam_l * t, B = phi / lam_l + t;
+  const double sigma = sqrt(fmax(res[9], 0.0));
+  const bool step = sigma > lam_l;
+  double gap, eta = 0.0;
+  if (step) {
+    const double b1 = res[2], b2 = res[3];
+    gap = gl + B * sigma + lam_l * (t - B);
+    const double dd = B * B * b2 + 2.0 * B * b1 + l2;
+    if (dd > 0.0) eta = (B * sigma + gl - lam_l * (B - t)) / dd;
+  } else {
+    gap = gl + lam_l * t;
+    if (l2 > 0.0) eta = (gl + lam_l * t) / l2;
+  }
+  eta = fmin(fmax(eta, 0.0), 1.0);
+  const bool done = gap <= tol * F || last != 0;
+  st[4] = F;
+  st[5] = gap;
+  st[6] = sigma;
+  st[7] = eta;
+  st[8] = step ? 1.0 : 0.0;
+  st[3] = done ? 1.0 : 0.0;
+  if (!done) {
+    st[1] = 1.0 - eta;
+    st[2] = step ? -eta * B / sigma : 0.0;
+    st[0] = (1.0 - eta) * t + eta * (step ? B : 0.0);
+    st[11] = eta;
+  }
+}
+
+// st = [t, a = 1, b = 0, not done, ...]: the first update pass forms G and the sums.
+__global__ void k_fw_state_init(double* __restrict__ st, double t) {
+  const int i = threadIdx.x;
+  if (i < 16) st[i] = i == 0 ? t : (i == 1 ? 1.0 : 0.0);
+}
+
 using rpca_ritz::start_entry;
 static_assert(rpca_ritz::BLK == BLK, "one block width");
 
@@ -379,6 +440,8 @@ struct rpca_fw {
   double* Z = nullptr;          // n x BLK
   double* res = nullptr;        // small device results
   double* res_host = nullptr;   // pinned copy
+  double* st = nullptr;         // 16 doubles: the iteration's step state (k_fw_step)
+  double* st_host = nullptr;    // pinned copy of it
   hipEvent_t flag_ev[2] = {nullptr, nullptr};  // the power steps' stop-flag copies (two slots)
   double* zpin = nullptr;       // pinned staging of the start block (n x BLK doubles)
   float* xpin = nullptr;        // n x (BLK + 16) floats
@@ -453,10 +516,10 @@ void fw_free(rpca_fw* h) {
     if (e) (void)hipEventDestroy(e);
   for (void* p : {(void*)h->mask, (void*)h->G, (void*)h->ypart, (void*)h->Y, (void*)h->y, (void*)h->Xd, (void*)h->Xb,
                   (void*)h->cw, (void*)h->v, (void*)h->part, (void*)h->Z, (void*)h->res, (void*)h->Wf,
-                  (void*)h->gpart})
+                  (void*)h->gpart, (void*)h->st})
     if (p) (void)hipFree(p);
   // a failed free must not stay pending: the caller's next error check would see it
-  for (void* p : {(void*)h->res_host, (void*)h->zpin, (void*)h->xpin})
+  for (void* p : {(void*)h->res_host, (void*)h->zpin, (void*)h->xpin, (void*)h->st_host})
     if (p && hipHostFree(p) != hipSuccess) (void)hipGetLastError();
   delete h;
 }
@@ -466,32 +529,30 @@ void fw_free(rpca_fw* h) {
     if ((expr) != hipSuccess) return RPCA_EHIP; \
   } while (0)
 
-// L <- a L + b y v^T, G and the three sums into res[4..6] (host copy on return).
-int fw_update(rpca_fw* h, const float* X, float* L, float a, float b, hipStream_t s) {
+// L <- a L + b y v^T (a, b from the step state), G and the three sums into
+// res[4..6] (host copy queued).
+int fw_update(rpca_fw* h, const float* X, float* L, hipStream_t s) {
   const int64_t blocks = h->rb_upd * h->n;
   const float ls = (float)h->lam_s;
   FWCHK(fw_timed(h, RPCA_FW_K_UPDATE, s, [&] {
     if (h->vec == 4) {
       if (h->mask)
         hipLaunchKernelGGL((k_fw_update<4, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                           h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+                           h->rb_upd, (const double*)h->st, h->y, h->v, ls, h->G, h->part);
       else
         hipLaunchKernelGGL((k_fw_update<4, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw,
-                           h->m, h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+                           h->m, h->rb_upd, (const double*)h->st, h->y, h->v, ls, h->G, h->part);
     } else {
       if (h->mask)
         hipLaunchKernelGGL((k_fw_update<1, true>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw, h->m,
-                           h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+                           h->rb_upd, (const double*)h->st, h->y, h->v, ls, h->G, h->part);
       else
         hipLaunchKernelGGL((k_fw_update<1, false>), dim3((unsigned)blocks), dim3(TH), 0, s, L, X, h->mask, h->mw,
-                           h->m, h->rb_upd, a, b, h->y, h->v, ls, h->G, h->part);
+                           h->m, h->rb_upd, (const double*)h->st, h->y, h->v, ls, h->G, h->part);
     }
   }));
   hipLaunchKernelGGL(k_sum_parts<3>, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, blocks, h->res + 4);
   FWCHK(hipGetLastError());
-  // read after the next linear minimisation's first wait (which follows this copy
-  // on the stream), so no synchronisation here
-  FWCHK(hipMemcpyAsync(h->res_host + 4, h->res + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   return RPCA_OK;
 }
 
@@ -574,7 +635,9 @@ hipError_t fw_left(rpca_fw* h, const float* Xb, hipStream_t s) {
 // the device does not wait on the host between steps.  On return y = G v
 // (device), v (device, unit), *sigma = ||G v||, and the other block copy holds
 // the rotated, orthonormalised block (the next call's start).
-int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
+constexpr int LMO_STOPPED = 100;  // the solve ended before this minimisation was needed
+
+int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s, const double* stop_when) {
   const int64_t m = h->m, n = h->n;
   const int b = h->b;
   const int64_t ncb = (n + RIGHT_COLS - 1) / RIGHT_COLS;
@@ -643,6 +706,8 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
   for (int p = 0;; ++p) {
     if (ahead && p + 1 < POWER_MAX && (rc = enqueue_step(p + 1))) return rc;
     FWCHK(hipEventSynchronize(h->flag_ev[p & 1]));
+    // the previous iteration's step state (copied ahead of this minimisation) says done
+    if (stop_when && *stop_when != 0.0) return LMO_STOPPED;
     const double* slot = h->res_host + 8 + 4 * (p & 1);
     ++*steps;
     // the kernel sets the flag at the last allowed step; the host stops there too
@@ -661,34 +726,34 @@ int fw_lmo(rpca_fw* h, double ptol, double* sigma, int* steps, hipStream_t s) {
   }
 }
 
-// u^T P_Omega(L) v and sum_Omega u_i^2 v_j^2 with u = y / sigma.
-int fw_bilinear(rpca_fw* h, const float* L, double sigma, double* b1, double* b2, hipStream_t s) {
+// u^T P_Omega(L) v and sum_Omega u_i^2 v_j^2 with u = y / sigma into res[2..3]
+// (sigma from the minimisation on the device; nothing without a step).
+int fw_bilinear(rpca_fw* h, const float* L, hipStream_t s) {
   const int64_t cblocks = h->rc_bil * h->n;
-  const float ws = (float)(1.0 / sigma);
   FWCHK(fw_timed(h, RPCA_FW_K_BILINEAR, s, [&] {
     if (h->vec == 4) {
       if (h->mask)
         hipLaunchKernelGGL((k_fw_bilinear<4, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+                           (const double*)h->res, h->lam_l, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil,
+                           h->part);
       else
         hipLaunchKernelGGL((k_fw_bilinear<4, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+                           (const double*)h->res, h->lam_l, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil,
+                           h->part);
     } else {
       if (h->mask)
         hipLaunchKernelGGL((k_fw_bilinear<1, true>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+                           (const double*)h->res, h->lam_l, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil,
+                           h->part);
       else
         hipLaunchKernelGGL((k_fw_bilinear<1, false>), dim3((unsigned)cblocks), dim3(TH), 0, s, L, (const float*)h->y,
-                           ws, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil, h->part);
+                           (const double*)h->res, h->lam_l, (const uint32_t*)h->mask, h->mw, h->m, h->rc_bil,
+                           h->part);
     }
   }));
   hipLaunchKernelGGL(k_fw_bilinear_finish, dim3(1), dim3(FIN_TH), 0, s, (const double*)h->part, h->rc_bil, h->n,
                      (const float*)h->v, h->res);
   FWCHK(hipGetLastError());
-  FWCHK(hipMemcpyAsync(h->res_host + 2, h->res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  FWCHK(hipStreamSynchronize(s));
-  *b1 = h->res_host[2];
-  *b2 = h->res_host[3];
   return RPCA_OK;
 }
 
@@ -728,6 +793,7 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_s, double lam_l, const uint8
        hipMalloc(&h->v, (size_t)n * 4) == hipSuccess &&
        hipMalloc(&h->part, (size_t)parts * 8) == hipSuccess && hipMalloc(&h->Z, (size_t)(n * BLK) * 8) == hipSuccess &&
        hipMalloc(&h->res, 16 * 8) == hipSuccess && hipHostMalloc(&h->res_host, 16 * 8, hipHostMallocDefault) == hipSuccess &&
+       hipMalloc(&h->st, 16 * 8) == hipSuccess && hipHostMalloc(&h->st_host, 16 * 8, hipHostMallocDefault) == hipSuccess &&
        hipHostMalloc(&h->zpin, (size_t)(n * BLK) * 8, hipHostMallocDefault) == hipSuccess &&
        hipHostMalloc(&h->xpin, (size_t)(n * (BLK + 16)) * 4, hipHostMallocDefault) == hipSuccess;
   if (ok && (hipMemset(h->y, 0, (size_t)m * 4) != hipSuccess || hipMemset(h->v, 0, (size_t)n * 4) != hipSuccess))
@@ -809,50 +875,46 @@ int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t ma
     if ((rc = upload_block(h, s))) return rc;
     h->x_valid = true;
   }
-  // G, phi, <G, L>, sum_Omega L^2 at the start
-  if ((rc = fw_update(h, X, L, 1.f, 0.f, s))) return rc;
+  // G, phi, <G, L>, sum_Omega L^2 at the start (a = 1, b = 0)
   double t = *t_io;
+  hipLaunchKernelGGL(k_fw_state_init, dim3(1), dim3(64), 0, s, h->st, t);
+  FWCHK(hipGetLastError());
+  if ((rc = fw_update(h, X, L, s))) return rc;
   rpca_fw_info fin;
   memset(&fin, 0, sizeof(fin));
+  // Per iteration: the minimisation (the host waits on its steps), the bilinear
+  // pass, the step (k_fw_step: gap, stop test, eta, the update's a and b) and the
+  // update pass (nothing once done), with no other wait: the step state's copy
+  // is read after the next minimisation's first wait, which ends that
+  // minimisation when the state says done.
   for (int it = 0;; ++it) {
-    // the update's sums arrive with the minimisation's first wait (a non-finite G
-    // stops the minimisation at its first step)
     double sigma = 0.0;
-    if ((rc = fw_lmo(h, ptol, &sigma, &fin.power_iters, s))) return rc;
-    const double phi = h->res_host[4], gl = h->res_host[5], l2 = h->res_host[6];
-    if (!isfinite(phi) || !isfinite(gl) || !isfinite(l2)) {
-      FWCHK(hipStreamSynchronize(s));
-      *t_io = t;
-      return RPCA_ENONFINITE;
+    rc = fw_lmo(h, ptol, &sigma, &fin.power_iters, s, it > 0 ? h->st_host + 3 : nullptr);
+    if (rc != RPCA_OK && rc != LMO_STOPPED) return rc;
+    if (it > 0) {
+      const double* st = h->st_host;  // iteration it - 1
+      if (st[9] != 0.0) {
+        FWCHK(hipStreamSynchronize(s));
+        *t_io = st[10];
+        return RPCA_ENONFINITE;
+      }
+      fin.F = st[4];
+      fin.phi = st[12];
+      fin.gap = st[5];
+      fin.sigma = st[6];
+      fin.last_step = st[8] != 0.0;
+      fin.iters = it - 1;
+      fin.eta = st[11];
+      t = st[0];
+      if (st[3] != 0.0) break;
     }
-    const double F = phi + lam_l * t;
-    const double B = phi / lam_l + t;
-    const bool step = sigma > lam_l;
-    double gap, eta = 0.0;
-    if (step) {
-      double b1 = 0.0, b2 = 0.0;
-      if ((rc = fw_bilinear(h, L, sigma, &b1, &b2, s))) return rc;
-      gap = gl + B * sigma + lam_l * (t - B);
-      const double dd = B * B * b2 + 2.0 * B * b1 + l2;
-      if (dd > 0.0) eta = (B * sigma + gl - lam_l * (B - t)) / dd;
-    } else {
-      gap = gl + lam_l * t;
-      if (l2 > 0.0) eta = (gl + lam_l * t) / l2;
-    }
-    eta = fmin(fmax(eta, 0.0), 1.0);
-    fin.F = F;
-    fin.phi = phi;
-    fin.gap = gap;
-    fin.sigma = sigma;
-    fin.last_step = step;
-    fin.iters = it;
-    if (gap <= tol * F || it == max_iter) break;
-    // L <- (1 - eta) L + eta V, V = -B u v^T = -(B / sigma) y v^T
-    const float a = (float)(1.0 - eta);
-    const float bsc = step ? (float)(-eta * B / sigma) : 0.f;
-    if ((rc = fw_update(h, X, L, a, bsc, s))) return rc;
-    t = (1.0 - eta) * t + eta * (step ? B : 0.0);
-    fin.eta = eta;
+    if (rc == LMO_STOPPED) break;
+    if ((rc = fw_bilinear(h, L, s))) return rc;
+    hipLaunchKernelGGL(k_fw_step, dim3(1), dim3(64), 0, s, (const double*)h->res, h->st, lam_l, tol,
+                       it == max_iter ? 1 : 0);
+    FWCHK(hipGetLastError());
+    FWCHK(hipMemcpyAsync(h->st_host, h->st, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if ((rc = fw_update(h, X, L, s))) return rc;  // L <- (1 - eta) L + eta V, V = -B u v^T
   }
   *t_io = t;
   // the warm-start block's upload from the pinned staging may still be in flight
