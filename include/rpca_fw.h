@@ -4,8 +4,9 @@
  * the Huber marginal of rpca.h (the program of Sec. 6.2, equivalent to SPCP).
  * One iteration from (L_k, t_k):
  *   G_k = P_Omega(clip(L_k - X, -lam_S, lam_S)) (the gradient of phi);
- *   (sigma, u, v) = top singular triplet of G_k (power iteration warm-started
- *   from the previous iteration's right vector);
+ *   (sigma, u, v) = top singular triplet of G_k (block power iteration on
+ *   G_k^T G_k with 8 vectors and Rayleigh-Ritz, warm-started from the previous
+ *   iteration's block);
  *   vertex (V, Vt) = (0, 0) if lam_L >= sigma, else (-B_k u v^T, B_k) with the
  *   bound B_k = (phi(L_k) + lam_L t_k) / lam_L (B_0 = phi(0) / lam_L at L = 0);
  *   eta = minimiser over [0, 1] of 1/2 ||G_k + eta P_Omega(V - L_k)||^2 +
@@ -17,6 +18,8 @@
  *
  * Storage: L, G and X are m x n FP32 column-major in HBM (X as in rpca.h); the
  * solver keeps L dense because its rank grows by one per step.  Sums in FP64.
+ * The power steps' Rayleigh-Ritz, the step size and the stop test run on the
+ * device; the host waits only on the power steps' stop flags.
  */
 #ifndef RPCA_FW_H
 #define RPCA_FW_H
@@ -56,9 +59,10 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_S, double lam_L, const uint8
  * the start (all zeros with *t = 0 is the cold start of Alg. 1; any start needs
  * ||L||_* <= *t), out: the last iterate.  t: host, in/out.  max_iter >= 0
  * (0 evaluates the start only), tol >= 0.  power_tol: the power iteration stops
- * when its unit right vector moves by at most this much in one step (at most 100
- * steps per iteration); 0 selects 1e-4.  info: may be NULL.  Blocks until done.
- * The right singular vector is kept as the next call's warm start.  Returns
+ * when the top Ritz pair's relative residual ||G^T G x - theta x|| / theta is at
+ * most this (at most 100 steps per iteration); 0 selects 1e-4.  info: may be
+ * NULL.  Blocks until done.  The power-iteration block is kept as the next
+ * call's warm start.  Returns
  * RPCA_OK / RPCA_ENOTCONV as in info->status, RPCA_EINVAL on bad arguments,
  * RPCA_ENONFINITE, RPCA_EHIP. */
 int rpca_fw_solve(rpca_fw* fw, const float* X, float* L, double* t, int32_t max_iter, double tol,
