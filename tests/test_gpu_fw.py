@@ -26,7 +26,7 @@ from gpu_common import device, f32
 
 pytestmark = pytest.mark.gpu
 
-TIGHT = 3e-6  # power-iteration tolerance for parity (vector change per step)
+TIGHT = 3e-6  # power-iteration tolerance for parity (top Ritz pair's relative residual)
 
 
 def _problem(m, n, masked, seed):
