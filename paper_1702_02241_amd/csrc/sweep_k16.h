@@ -64,8 +64,9 @@ __device__ __forceinline__ void sweep_item_k16(const Args& a, const int rg, cons
   using namespace k16;
   constexpr int PF = TMAX >= 8 ? 4 : 2;
   constexpr int NG = (TMAX + PF - 1) / PF;
-  // FP32: one group in flight ahead of the computed one (fewer registers, three waves
-  // fit per SIMD); BF16: three (its products leave the registers for a deeper ring)
+  // FP32: one group in flight ahead of the computed one (three groups measured slower:
+  // the waves do not wait on these loads); BF16: three (its products leave the
+  // registers for a deeper ring)
   constexpr int NBUF = BF16 ? (NG >= 4 ? 4 : 2) : 2;
   static_assert(NG % NBUF == 0, "group ring must line up with strips");
   constexpr int NS_MAX = 2;  // BF16 split steps for k <= 16
