@@ -64,7 +64,9 @@ int rpca_fw_create(int64_t m, int64_t n, double lam_S, double lam_L, const uint8
  * NULL.  Blocks until done.  The power-iteration block is kept as the next
  * call's warm start.  Returns
  * RPCA_OK / RPCA_ENOTCONV as in info->status, RPCA_EINVAL on bad arguments,
- * RPCA_ENONFINITE, RPCA_EHIP. */
+ * RPCA_ENONFINITE when phi(L) or <G, L> is NaN/Inf (an observed NaN/Inf in X
+ * or L; *t is then the t of that iterate, L holds it, info is not written and
+ * the next call starts the power iteration cold), RPCA_EHIP. */
 int rpca_fw_solve(rpca_fw* fw, const float* X, float* L, double* t, int32_t max_iter, double tol,
                   double power_tol, rpca_fw_info* info, void* stream);
 

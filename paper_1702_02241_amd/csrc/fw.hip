@@ -896,6 +896,8 @@ int rpca_fw_solve(rpca_fw* h, const float* X, float* L, double* t_io, int32_t ma
       if (st[9] != 0.0) {
         FWCHK(hipStreamSynchronize(s));
         *t_io = st[10];
+        // the power block came from a nonfinite G: the next call starts cold
+        h->x_valid = false;
         return RPCA_ENONFINITE;
       }
       fin.F = st[4];

@@ -9,7 +9,9 @@ oracle.frank_wolfe.
 * a 300-iteration solve from zero: the objective never increases across calls,
   the gap bounds F - F* (FISTA-SVT), and F tracks the oracle's trajectory;
 * the zero solution: lam_L above ||grad phi(0)||_2 stops at once with L = 0;
-* the 76,800 x 200 video shape: one iteration from the oracle's third iterate.
+* the 76,800 x 200 video shape: one iteration from the oracle's third iterate;
+* the stop test: a solve stops at the first iterate whose gap passes, unchanged;
+* nonfinite input: RPCA_ENONFINITE, and the handle's next call starts cold.
 """
 import numpy as np
 import pytest
@@ -174,3 +176,65 @@ def test_fewer_columns_than_the_power_block(m, n, masked):
     assert abs(tg - t3) <= 1e-5 * max(t3, 1e-12) + 1e-12
     assert err <= 1e-4
     solver.close()
+
+
+@pytest.mark.parametrize("m,n,masked", [(300, 120, False), (301, 77, True), (520, 300, False)])
+def test_stops_at_the_gap_test_with_that_iterate(m, n, masked):
+    """The stop test on the device (gap <= tol F, Alg. 1): with tol just above the
+    gap ratio of iterate 25, a solve from zero stops at the first iterate j <= 25
+    that passes, returns that iterate unchanged (bitwise the one max_iter = j
+    returns with tol = 0), and iterate j - 1 does not pass.  Fresh handles for
+    each solve, so every one starts from the same power block."""
+    p = _problem(m, n, masked, seed=41 + n)
+    dev = device()
+    Xcm = _to_dev(p.X, dev)
+
+    def run(max_iter, tol):
+        solver = T.FrankWolfe(m, n, p.lam_s, p.lam_l, mask=p.mask)
+        out = solver.solve(Xcm, None, 0.0, max_iter=max_iter, tol=tol)
+        solver.close()
+        return out
+
+    rc, _, _, info = run(25, 0.0)
+    assert rc == R.RPCA_ENOTCONV and info.iters == 25
+    tol = info.gap / info.F * (1 + 1e-9)
+    rc, Lj, tj, infoj = run(1000, tol)
+    j = infoj.iters
+    print(f"[fw stop {m}x{n} mask={masked}] tol {tol:.6e}: stopped at {j}, gap/F {infoj.gap / infoj.F:.6e}")
+    assert rc == R.RPCA_OK and 0 < j <= 25
+    assert infoj.gap <= tol * infoj.F
+    rc0, L0, t0, info0 = run(j, 0.0)
+    assert rc0 == R.RPCA_ENOTCONV and info0.iters == j
+    assert info0.F == infoj.F and info0.gap == infoj.gap and t0 == tj
+    assert torch.equal(L0, Lj)
+    rcp, _, _, infop = run(j - 1, tol)
+    assert rcp == R.RPCA_ENOTCONV and infop.iters == j - 1
+    assert infop.gap > tol * infop.F
+
+
+@pytest.mark.parametrize("where", ["X", "L"])
+def test_nonfinite_input_reports_and_the_next_call_starts_clean(where):
+    """An observed NaN in X (or Inf in the start L) makes phi nonfinite: the solve
+    returns RPCA_ENONFINITE, and a later solve on clean data with the same handle
+    is bitwise that of a fresh handle (the power block is not reused)."""
+    p = _problem(300, 120, False, seed=43)
+    dev = device()
+    Xcm = _to_dev(p.X, dev)
+    Lbad = torch.zeros_like(Xcm)
+    Xbad = Xcm.clone()
+    if where == "X":
+        Xbad[7, 5] = float("nan")
+    else:
+        Lbad[7, 5] = float("inf")
+    solver = T.FrankWolfe(p.m, p.n, p.lam_s, p.lam_l)
+    rc, t, _ = R.rpca_fw_solve(solver.h, Xbad.data_ptr(), Lbad.data_ptr(), 0.0, 10, 0.0, 0.0, T._stream())
+    torch.cuda.synchronize()
+    assert rc == R.RPCA_ENONFINITE
+    rc1, L1, t1, info1 = solver.solve(Xcm, None, 0.0, max_iter=10, tol=0.0)
+    solver.close()
+    fresh = T.FrankWolfe(p.m, p.n, p.lam_s, p.lam_l)
+    rc2, L2, t2, info2 = fresh.solve(Xcm, None, 0.0, max_iter=10, tol=0.0)
+    fresh.close()
+    print(f"[fw nonfinite {where}] then F {info1.F:.9g} vs fresh {info2.F:.9g}")
+    assert rc1 == rc2 == R.RPCA_ENOTCONV and info1.iters == info2.iters == 10
+    assert info1.F == info2.F and t1 == t2 and torch.equal(L1, L2)
