@@ -225,7 +225,9 @@ def run_fw(args):
     k_ms = ms[dom] / max(launches[dom], 1)
     achieved = alg[dom] / (k_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=(measured_traffic(FW_TRAFFIC_FILE, FW_SOURCES) if names[dom] == "right" and n <= 256
+                             else None),
                     kernel=("k_gram_apply (fused G^T G X_b)" if names[dom] == "right" and n <= 256
                             else f"k_fw_{names[dom]}"), kernel_ms=round(k_ms, 5), launches=int(launches[dom]),
                     alg_bytes_per_launch=alg[dom])
@@ -627,29 +629,32 @@ def probe(args):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fp32_video76800x200_hbm_traffic.md")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_1702_02241_amd", "csrc", f) for f in ("sweep_kernel.h", "sweep_k16.h")]
+FW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_apply_fw_video76800x200_hbm_traffic.md")
+FW_SOURCES = [os.path.join(ROOT, "paper_1702_02241_amd", "csrc", "gram_apply.hip")]
 
 
-def sweep_source_hash():
-    """SHA-256 over the sweep's source files, in order."""
+def source_hash(files=None):
+    """SHA-256 over a kernel's source files, in order (default: the sweep's)."""
     import hashlib
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in files or SWEEP_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when the sweep source changed since the counters were taken."""
+def measured_traffic(path=TRAFFIC_FILE, sources=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    when the kernel's source changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
-        src = sweep_source_hash()
+        text = open(path).read()
+        src = source_hash(sources)
     except OSError:
         return None
     vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
+                                                                           "sources_sha256:",
                                                                            "sweep_sources_sha256:")))
-    if vals.get("sweep_sources_sha256", "").strip() != src:
+    if vals.get("sources_sha256", vals.get("sweep_sources_sha256", "")).strip() != src:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
