@@ -63,6 +63,20 @@ def test_masked_objgrad_matches_oracle(m, n, k, p_obs):
     _check(p, U, V, label="masked")
 
 
+@pytest.mark.parametrize("m,n,k,masked", [(1, 1, 1, False), (1, 70, 1, False), (70, 1, 1, False),
+                                            (5, 3, 3, False), (3, 40, 3, False), (1, 70, 1, True),
+                                            (70, 1, 1, True)])
+def test_objgrad_degenerate_shapes(m, n, k, masked):
+    """One row, one column, one entry, k = min(m, n): every strip and column tile is
+    ragged and most lanes of a tile are padding."""
+    if masked:
+        p = synth.partial_rpca(m=m, n=n, r=1, k=k, p_obs=0.5, seed=11 + m + n)
+    else:
+        p = synth.gaussian_rpca(m=m, n=n, r=min(2, k), k=k, seed=7 + m + n)
+    U, V = synth.random_factors(m, n, k, 3 + m, scale=0.5)
+    _check(p, U, V, label="degenerate")
+
+
 def test_objgrad_video_full_size():
     p = synth.video()                 # 76,800 x 200, k = 10
     U, V = synth.random_factors(p.m, p.n, p.k, 31, scale=0.2)
